@@ -1,0 +1,218 @@
+"""ctypes wrapper of the CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this module.  It shares nothing with the GPU library; problems are
+passed as plain dicts (see ``paper_2603_28770_amd.workloads``) and mapped to
+the oracle's own struct here.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzeus_oracle.so")
+
+OBJECTIVES = {"rosenbrock": 0, "rastrigin": 1, "ackley": 2, "styblinski_tang": 3,
+              "goldstein_price": 4, "sphere": 5, "quartic": 6}
+MAXITER, CONVERGED, STOPPED, NONFINITE = 0, 1, 2, 3
+TAG_X0, TAG_V0, TAG_R1, TAG_R2 = 0, 1, 2, 3
+
+
+class _Problem(C.Structure):
+    _fields_ = [("objective", C.c_int32), ("dim", C.c_int32), ("n", C.c_int64),
+                ("lower", C.c_double), ("upper", C.c_double),
+                ("iter_pso", C.c_int32), ("w", C.c_double), ("c1", C.c_double),
+                ("c2", C.c_double), ("v_half", C.c_double),
+                ("iter_bfgs", C.c_int32), ("iter_ls", C.c_int32),
+                ("armijo_c", C.c_double), ("ls_shrink", C.c_double),
+                ("grad_tol", C.c_double), ("seed", C.c_uint64),
+                ("request_id", C.c_uint64)]
+
+
+class _Swarm(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("v", C.c_void_p), ("px", C.c_void_p),
+                ("pf", C.c_void_p), ("gx", C.c_void_p), ("gf", C.c_double),
+                ("gidx", C.c_int64), ("near_ties", C.c_int64)]
+
+
+class _BfgsOut(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("f", C.c_void_p), ("iters", C.c_void_p),
+                ("status", C.c_void_p), ("ls_trials", C.c_void_p),
+                ("ls_fail", C.c_void_p), ("skips", C.c_void_p),
+                ("resets", C.c_void_p), ("min_margin", C.c_void_p),
+                ("tie_iter", C.c_void_p), ("trace", C.c_void_p),
+                ("trace_len", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from oracle import build as _build
+            _build.build()
+        L = C.CDLL(LIB_PATH)
+        L.zo_philox4x64_10.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.zo_uniform.restype = C.c_double
+        L.zo_uniform.argtypes = [C.c_uint64] * 6
+        L.zo_f.restype = C.c_double
+        L.zo_f.argtypes = [C.c_int, C.c_void_p, C.c_int]
+        L.zo_grad.argtypes = [C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p]
+        L.zo_bfgs_update.restype = C.c_int
+        L.zo_bfgs_update.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.zo_line_search.restype = C.c_double
+        L.zo_line_search.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_double, C.c_void_p,
+                                     C.c_double, C.c_void_p, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]
+        L.zo_validate.restype = C.c_int
+        L.zo_validate.argtypes = [C.POINTER(_Problem)]
+        L.zo_pso.restype = C.c_int
+        L.zo_pso.argtypes = [C.POINTER(_Problem), C.POINTER(_Swarm)]
+        L.zo_bfgs.restype = C.c_int
+        L.zo_bfgs.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_int64,
+                              C.POINTER(_BfgsOut), C.c_int]
+        L.zo_best.restype = C.c_int64
+        L.zo_best.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
+        L.zo_max_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def make_problem(p: dict) -> _Problem:
+    """Map a workload dict to the oracle's struct (defaults are the paper's)."""
+    return _Problem(
+        objective=OBJECTIVES[p["objective"]], dim=int(p["dim"]), n=int(p["n"]),
+        lower=float(p["lower"]), upper=float(p["upper"]),
+        iter_pso=int(p.get("iter_pso", 0)), w=float(p.get("w", 0.5)),
+        c1=float(p.get("c1", 1.2)), c2=float(p.get("c2", 1.5)),
+        v_half=float(p.get("v_half", 0.0)), iter_bfgs=int(p.get("iter_bfgs", 100)),
+        iter_ls=int(p.get("iter_ls", 20)), armijo_c=float(p.get("armijo_c", 0.3)),
+        ls_shrink=float(p.get("ls_shrink", 0.5)), grad_tol=float(p.get("grad_tol", 1e-6)),
+        seed=int(p.get("seed", 0)), request_id=int(p.get("request_id", 0)))
+
+
+def philox(ctr, key):
+    c = (C.c_uint64 * 4)(*[int(v) for v in ctr])
+    k = (C.c_uint64 * 2)(*[int(v) for v in key])
+    o = (C.c_uint64 * 4)()
+    lib().zo_philox4x64_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def uniform(seed, request_id, i, t, tag, j):
+    return lib().zo_uniform(seed, request_id, i, t, tag, j)
+
+
+def f(objective, x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().zo_f(OBJECTIVES[objective], _ptr(x), x.size)
+
+
+def grad(objective, x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    g = np.empty_like(x)
+    fv = C.c_double()
+    lib().zo_grad(OBJECTIVES[objective], _ptr(x), x.size, C.byref(fv), _ptr(g))
+    return fv.value, g
+
+
+def bfgs_update(H, s, y):
+    H = np.array(H, dtype=np.float64, order="C", copy=True)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    applied = lib().zo_bfgs_update(_ptr(H), _ptr(s), _ptr(y), s.size)
+    return H, bool(applied)
+
+
+def line_search(problem, x, f0, p, ddir):
+    pb = make_problem(problem)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    xt = np.empty_like(x)
+    tr, acc = C.c_int32(), C.c_int32()
+    a = lib().zo_line_search(C.byref(pb), _ptr(x), float(f0), _ptr(p), float(ddir), _ptr(xt),
+                             C.byref(tr), C.byref(acc))
+    return a, tr.value, bool(acc.value)
+
+
+def validate(problem) -> bool:
+    try:
+        pb = make_problem(problem)
+    except (KeyError, ValueError, OverflowError, TypeError):
+        return False
+    return lib().zo_validate(C.byref(pb)) == 0
+
+
+def pso(problem):
+    pb = make_problem(problem)
+    n, d = pb.n, pb.dim
+    out = {k: np.empty((n, d)) for k in ("x", "v", "px")}
+    out["pf"] = np.empty(n)
+    out["gx"] = np.empty(d)
+    sw = _Swarm(x=_ptr(out["x"]), v=_ptr(out["v"]), px=_ptr(out["px"]), pf=_ptr(out["pf"]),
+                gx=_ptr(out["gx"]))
+    rc = lib().zo_pso(C.byref(pb), C.byref(sw))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    out["gf"], out["gidx"], out["near_ties"] = sw.gf, sw.gidx, sw.near_ties
+    return out
+
+
+def bfgs(problem, x0, idx=None, trace_len=0, nthreads=None):
+    pb = make_problem(problem)
+    d = pb.dim
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        m = idx.size
+    else:
+        m = x0.shape[0]
+    o = {"x": np.empty((m, d)), "f": np.empty(m), "iters": np.empty(m, np.int32),
+         "status": np.empty(m, np.int32), "ls_trials": np.empty(m, np.int32),
+         "ls_fail": np.empty(m, np.int32), "skips": np.empty(m, np.int32),
+         "resets": np.empty(m, np.int32), "min_margin": np.empty(m),
+         "tie_iter": np.empty(m, np.int32)}
+    if trace_len > 0:
+        o["trace"] = np.full((m, trace_len, d), np.nan)
+    bo = _BfgsOut(x=_ptr(o["x"]), f=_ptr(o["f"]), iters=_ptr(o["iters"]),
+                  status=_ptr(o["status"]), ls_trials=_ptr(o["ls_trials"]),
+                  ls_fail=_ptr(o["ls_fail"]), skips=_ptr(o["skips"]), resets=_ptr(o["resets"]),
+                  min_margin=_ptr(o["min_margin"]), tie_iter=_ptr(o["tie_iter"]),
+                  trace=_ptr(o.get("trace")), trace_len=int(trace_len))
+    nt = nthreads if nthreads else lib().zo_max_threads()
+    rc = lib().zo_bfgs(C.byref(pb), _ptr(x0), _ptr(idx), m, C.byref(bo), int(nt))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    o["threads"] = nt
+    return o
+
+
+def best(fvals, status):
+    fvals = np.ascontiguousarray(fvals, dtype=np.float64)
+    status = np.ascontiguousarray(status, dtype=np.int32)
+    nc = C.c_int64()
+    b = lib().zo_best(_ptr(fvals), _ptr(status), fvals.size, C.byref(nc))
+    return int(b), int(nc.value)
+
+
+def max_threads():
+    return lib().zo_max_threads()
+
+
+def minimize(problem, idx=None, trace_len=0, nthreads=None):
+    """PSO then BFGS from every start (or the starts listed in idx)."""
+    sw = pso(problem)
+    r = bfgs(problem, sw["x"], idx=idx, trace_len=trace_len, nthreads=nthreads)
+    b, nc = best(r["f"], r["status"])
+    r["best_index"] = b if idx is None or b < 0 else int(np.asarray(idx)[b])
+    r["best_f"] = float(r["f"][b]) if b >= 0 else float("nan")
+    r["n_converged"] = nc
+    r["swarm"] = sw
+    return r
