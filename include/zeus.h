@@ -1,0 +1,195 @@
+/*
+ * zeus.h -- C ABI of libzeus.so: batched multistart minimisation on AMD
+ * Instinct MI355X (gfx950) following "Zeus: An Efficient GPU Optimization
+ * Method Integrating PSO, BFGS, and Automatic Differentiation".
+ *
+ * The problem statement follows the paper's driver (Alg. 7, and Alg. 1 for
+ * the sequential form): minimise f over the box [lower, upper]^dim from N
+ * starts.  A swarm of N particles is initialised uniformly in the box
+ * (Alg. 2 / Alg. 8) and moved by iter_pso synchronous PSO updates (Alg. 3 /
+ * Alg. 9); then one BFGS run starts from every particle's position (Alg. 4 /
+ * Alg. 10) with forward-mode dual-number gradients (Alg. 5) and an Armijo
+ * backtracking line search (Alg. 6); finally the best start is reduced
+ * (Alg. 7).  Each start reports its minimum, argmin, iteration count and
+ * status.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns a zeus_err; no C++ exception crosses this boundary.
+ *    On an error, zeus_last_error() returns a message (thread-local, valid
+ *    until the next call on the same thread) and no output has been written
+ *    (asynchronous calls: nothing has been enqueued).
+ *  - The caller owns every struct and array passed in.  The library copies
+ *    the problem at call time.
+ *  - Results are a pure function of the problem: they do not depend on the
+ *    device's occupancy, on work-queue order or on other calls.
+ *  - A context serialises its own calls; different contexts may be used from
+ *    different threads.
+ */
+#ifndef ZEUS_H
+#define ZEUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ZEUS_ABI_VERSION 1u
+
+typedef enum zeus_err {
+  ZEUS_OK = 0,
+  ZEUS_NOT_READY = 1,
+  ZEUS_EINVAL = -1,       /* invalid argument or problem                     */
+  ZEUS_ENOMEM = -2,       /* device or host allocation failed                 */
+  ZEUS_EHIP = -3,         /* a HIP runtime call failed (message has details)  */
+  ZEUS_EUNSUPPORTED = -4, /* valid problem this build cannot run              */
+  ZEUS_ECANCELLED = -5,
+  ZEUS_ETIMEOUT = -6
+} zeus_err;
+
+/* Objectives.  Rosenbrock, Rastrigin, Ackley and Goldstein-Price are the test
+ * functions of Sec. V-B; Styblinski-Tang is the standard test function
+ * 0.5 * sum (x^4 - 16 x^2 + 5 x); SPHERE (0.5 ||x||^2) and QUARTIC (sum x^4)
+ * are small test objectives with exactly representable line searches. */
+typedef enum zeus_objective {
+  ZEUS_ROSENBROCK = 0,      /* dim >= 2 */
+  ZEUS_RASTRIGIN = 1,
+  ZEUS_ACKLEY = 2,
+  ZEUS_STYBLINSKI_TANG = 3,
+  ZEUS_GOLDSTEIN_PRICE = 4, /* dim == 2 */
+  ZEUS_SPHERE = 5,
+  ZEUS_QUARTIC = 6
+} zeus_objective;
+
+/* ZEUS_FP64: everything in IEEE double.
+ * ZEUS_MIXED: objective and dual numbers in float; inverse Hessian, search
+ *             direction, g'p, the Armijo comparison, s, y and y's in double. */
+typedef enum zeus_precision { ZEUS_FP64 = 0, ZEUS_MIXED = 1 } zeus_precision;
+
+/* Per-start termination status (Alg. 4: status 1 when ||grad|| < Theta,
+ * status 0 when the iteration budget runs out). */
+typedef enum zeus_start_status {
+  ZEUS_ST_MAXITER = 0,
+  ZEUS_ST_CONVERGED = 1,
+  ZEUS_ST_STOPPED = 2,   /* reserved for early stopping at required_converged */
+  ZEUS_ST_NONFINITE = 3  /* f or a gradient component became inf/NaN          */
+} zeus_start_status;
+
+/* The problem, after Alg. 7's argument list
+ * Zeus(f, N, range, iter_bfgs, iter_pso, iter_ls, required_c, Theta, w, c1, c2).
+ * Field meanings and the defaults the paper uses: */
+typedef struct zeus_problem {
+  uint32_t abi_version;  /* must be ZEUS_ABI_VERSION                             */
+  int32_t objective;     /* zeus_objective                                       */
+  int32_t dim;           /* 1 <= dim <= 64 in this build                          */
+  int32_t precision;     /* zeus_precision                                       */
+  int64_t n_starts;      /* N particles == N BFGS starts, >= 1                    */
+  double lower, upper;   /* sampling box, same on every axis (Alg. 2 'range');
+                            the search itself is unconstrained                    */
+  int32_t iter_pso;      /* synchronous PSO updates, >= 0                          */
+  int32_t iter_bfgs;     /* BFGS iteration budget per start, >= 0                  */
+  int32_t iter_ls;       /* Armijo trials per line search, >= 1 (paper: 20)         */
+  int32_t reserved0;     /* must be 0                                              */
+  double w, c1, c2;      /* PSO inertia, cognitive, social (paper: 0.5, 1.2, 1.5)  */
+  double v_half;         /* initial velocity in [-v_half, v_half]; <= 0 selects
+                            upper - lower as in Alg. 2                             */
+  double armijo_c;       /* sufficient-decrease constant in (0,1) (paper: 0.3)      */
+  double ls_shrink;      /* backtracking factor in (0,1) (paper: 0.5)               */
+  double grad_tol;       /* Theta > 0: a start converges when ||grad||_2 < Theta     */
+  int64_t required_converged; /* must be 0 (early stopping not built)              */
+  uint64_t seed;         /* Philox key word 0                                      */
+  uint64_t request_id;   /* Philox key word 1                                      */
+} zeus_problem;
+
+/* Reductions over all starts (Alg. 7's final ParallelReduction and counts). */
+typedef struct zeus_summary {
+  int64_t best_index;     /* start with the lowest finite f (lowest index on
+                             ties); -1 if no f is finite                          */
+  double best_f;
+  int64_t n_converged;    /* starts with status CONVERGED                         */
+  int64_t n_nonfinite;    /* starts with status NONFINITE                         */
+  int64_t total_iters;    /* sum of BFGS iterations over starts                   */
+  int64_t total_ls_trials;/* sum of line-search objective evaluations, counted as
+                             the sequential Alg. 6 would evaluate them            */
+  int64_t pso_best_index; /* particle holding the PSO global best                 */
+  double pso_best_f;
+} zeus_summary;
+
+/* Where results go.  For zeus_minimize every pointer is host memory; for
+ * zeus_minimize_async every pointer is device memory.  Required: f, x,
+ * iters, status, summary.  Optional (NULL to skip): everything else. */
+typedef struct zeus_result {
+  double *f;            /* [N] final objective value per start                 */
+  double *x;            /* [N][dim] final iterate per start (row-major)        */
+  int32_t *iters;       /* [N] BFGS iterations taken                           */
+  int32_t *status;      /* [N] zeus_start_status                               */
+  int32_t *ls_trials;   /* [N] line-search evaluations (sequential count)      */
+  double *seeds;        /* [N][dim] particle positions after PSO = BFGS starts */
+  double *pso_v;        /* [N][dim] velocities after PSO                        */
+  double *pso_px;       /* [N][dim] personal-best positions after PSO           */
+  double *pso_pf;       /* [N] personal-best values after PSO                   */
+  double *pso_best_x;   /* [dim] PSO global-best position                       */
+  double *trace;        /* [N][trace_len][dim] iterates x_0, x_1, ...; entries
+                           after a start's last iterate are NaN                 */
+  int32_t trace_len;    /* 0 disables the trace                                 */
+  int32_t reserved0;
+  zeus_summary *summary;/* one zeus_summary                                     */
+} zeus_result;
+
+typedef struct zeus_context zeus_context;
+
+/* Per-kernel device time accumulated by a context while profiling is on,
+ * measured with HIP events on the stream the kernels run on. */
+typedef struct zeus_profile {
+  double pso_ms;        /* swarm initialisation + updates                        */
+  double bfgs_ms;       /* the BFGS kernel                                        */
+  double reduce_ms;     /* final best-of-N reduction                              */
+  int64_t pso_launches, bfgs_launches, reduce_launches;
+} zeus_profile;
+
+/* Library and ABI version. */
+uint32_t zeus_abi_version(void);
+const char *zeus_version(void);
+
+/* Message for the last error on this thread ("" if none). */
+const char *zeus_last_error(void);
+
+/* Checks a problem against the rules above.  ZEUS_OK, ZEUS_EINVAL (invalid) or
+ * ZEUS_EUNSUPPORTED (valid but outside this build, e.g. dim > 64). */
+zeus_err zeus_validate(const zeus_problem *problem);
+
+/* Device workspace that zeus_minimize_async needs for this problem, in bytes.
+ * Swarm state x, v, px ([N][dim] doubles each) and pf [N], plus reduction
+ * scratch; the inverse Hessians never leave the chip. */
+zeus_err zeus_workspace_bytes(const zeus_problem *problem, size_t *bytes);
+
+/* Creates a context on HIP device `device` with its own stream (default
+ * priority).  *out receives the handle. */
+zeus_err zeus_context_create(int device, zeus_context **out);
+zeus_err zeus_context_destroy(zeus_context *ctx);
+
+/* Turns per-kernel event timing on or off and clears the accumulators. */
+zeus_err zeus_context_set_profiling(zeus_context *ctx, int enabled);
+zeus_err zeus_context_get_profile(zeus_context *ctx, zeus_profile *out);
+
+/* Blocking solve.  Allocates (and caches in the context) device memory,
+ * runs PSO, BFGS and the reduction on the context's stream, copies every
+ * requested output to the host arrays of *out and returns when done. */
+zeus_err zeus_minimize(zeus_context *ctx, const zeus_problem *problem,
+                       const zeus_result *out);
+
+/* Asynchronous solve on `stream` (a hipStream_t; NULL = the context's stream)
+ * with caller-owned device memory: `workspace` of at least
+ * zeus_workspace_bytes() bytes (256-byte aligned) and device result arrays in
+ * *out.  Only enqueues work; the caller synchronises the stream.  The
+ * workspace and outputs must not be used by other work until the stream has
+ * passed this call. */
+zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem,
+                             void *workspace, size_t workspace_bytes,
+                             const zeus_result *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZEUS_H */

@@ -1,0 +1,367 @@
+// zeus_bfgs.hip -- the BFGS phase on gfx950 (Alg. 4 / Alg. 10 with the
+// dual-number gradient of Alg. 5 and the Armijo line search of Alg. 6), plus
+// the final best-of-N reduction (Alg. 7).
+//
+// Mapping (the "more levels of parallelism" the paper leaves for later):
+//  * one group of G lanes (G a power of two >= dim, G <= 64) runs one start;
+//    a 64-lane wavefront holds 64/G groups, a 256-thread block four waves;
+//  * lane j owns coordinate j and row j of the inverse Hessian H, which stays
+//    in registers for the whole run (H never touches HBM);
+//  * gradient: lane j evaluates the objective on dual numbers seeded with the
+//    tangent e_j, so the G lanes compute the dim passes of Alg. 5 at once;
+//  * line search: lane j evaluates trial j (alpha = shrink^j) of the
+//    backtracking sequence; the first trial that satisfies the Armijo
+//    condition is taken, which is exactly the step the sequential loop of
+//    Alg. 6 would return, in one objective evaluation instead of several;
+//  * the small vectors a lane needs in full (x, p, g, s, y, u) are exchanged
+//    through the group's slice of LDS;
+//  * starts are claimed from an agent-scope work counter, so a group that
+//    finishes early takes the next start instead of idling; results do not
+//    depend on which group ran which start.
+// The loop is flattened so that every trip does one gradient evaluation and
+// one line search for every group of a wave, whatever iteration each group's
+// start is in.
+#include "zeus_device.h"
+#include "zeus_internal.h"
+
+namespace zeus {
+namespace {
+
+struct BfgsArgs {
+  int64_t n;
+  int d;
+  int iter_bfgs;
+  int iter_ls;
+  int trace_len;
+  double armijo_c, shrink, tol;
+  const double *x0;   // [n][d] starting points
+  uint64_t *queue;    // next unclaimed start
+  double *out_f;
+  double *out_x;
+  int32_t *out_iters;
+  int32_t *out_status;
+  int32_t *out_ls;    // nullable
+  double *trace;      // nullable, [n][trace_len][d]
+};
+
+template <int G>
+struct GroupShm {
+  double xs[G];  // iterate under evaluation (x, then x + alpha p)
+  double ps[G];  // search direction
+  double gs[G];  // gradient at the current iterate
+  double ys[G];  // y = g_new - g
+  double ss[G];  // s = x_new - x
+  double us[G];  // u = H y
+};
+
+// Orders this wave's LDS traffic: LDS operations of one wave complete in
+// issue order, so only the compiler needs to be kept from moving them.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int OBJ, int G>
+__global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
+  constexpr int S = 64 / G;  // groups per wave
+  __shared__ GroupShm<G> shm[kBfgsBlock / 64][S];
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / G;
+  const int j = lane & (G - 1);
+  GroupShm<G> &sh = shm[threadIdx.x >> 6][grp];
+  const int d = a.d;
+  const bool own = j < d;
+  const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
+
+  double h[G];  // row j of H
+  double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
+  int64_t idx = -1;
+  int k = 0, ls_trials = 0;
+  bool fresh = false;
+
+  for (;;) {
+    // -- claim a start when idle ------------------------------------------
+    if (idx < 0) {
+      unsigned long long got = 0;
+      if (j == 0) got = atomicAdd((unsigned long long *)a.queue, 1ull);
+      got = __shfl(got, grp * G, 64);
+      if (got >= (unsigned long long)a.n) break;
+      idx = (int64_t)got;
+      xj = own ? a.x0[idx * d + j] : 0.0;  // x <- swarm[i]
+      sh.xs[j] = xj;
+#pragma unroll
+      for (int c = 0; c < G; ++c) h[c] = (c == j) ? 1.0 : 0.0;  // H <- I
+      k = 0;
+      ls_trials = 0;
+      fresh = true;
+    }
+    wave_sync();
+
+    // -- gradient at xs: lane j takes the dual pass seeded with e_j ---------
+    const dual<double> r = Obj<OBJ>::template eval<dual<double>>(
+        d, [&](int i) { return dual<double>{sh.xs[i], i == j ? 1.0 : 0.0}; });
+    const double fn = r.v, gn = own ? r.t : 0.0;
+
+    // -- after a step: s, y and the rank-2 inverse-Hessian update -----------
+    if (!fresh) {
+      const double yj = gn - gj;
+      sh.ys[j] = yj;
+      sh.ss[j] = sj;
+      wave_sync();
+      double sy = 0.0;
+      for (int i = 0; i < d; ++i) sy = sy + sh.ys[i] * sh.ss[i];
+      if (sy > 0.0) {  // curvature condition; skip the update otherwise
+        const double rho = 1.0 / sy;
+        double uj = 0.0;
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+          if (c < d) uj = __builtin_fma(h[c], sh.ys[c], uj);
+        sh.us[j] = own ? uj : 0.0;
+        wave_sync();
+        double yu = 0.0;
+        for (int i = 0; i < d; ++i) yu = yu + sh.ys[i] * sh.us[i];
+        const double beta = (rho * rho) * yu + rho;
+        // H+ = H - rho (s u' + u s') + beta s s'   (row j, u = H y)
+        const double au = -rho * sj;
+        const double as = beta * sj - rho * uj;
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+          if (c < d) h[c] = __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], h[c]));
+      }
+      xj = own ? sh.xs[j] : 0.0;  // x <- x_new
+      ++k;
+    }
+    gj = gn;
+    f = fn;
+    fresh = false;
+    sh.gs[j] = gj;
+    wave_sync();
+    if (a.trace && own && k < a.trace_len) a.trace[(idx * a.trace_len + k) * d + j] = xj;
+
+    // -- termination: non-finite, ||g|| < Theta, budget ---------------------
+    const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
+    const bool any_bad = (__ballot(bad) & gmask) != 0ull;
+    double gg = 0.0;
+    for (int i = 0; i < d; ++i) gg = gg + sh.gs[i] * sh.gs[i];
+    int status = -1;
+    if (any_bad)
+      status = ZEUS_ST_NONFINITE;
+    else if (sqrt(gg) < a.tol)
+      status = ZEUS_ST_CONVERGED;
+    else if (k == a.iter_bfgs)
+      status = ZEUS_ST_MAXITER;
+    if (status >= 0) {
+      if (own) a.out_x[idx * d + j] = xj;
+      if (j == 0) {
+        a.out_f[idx] = f;
+        a.out_iters[idx] = k;
+        a.out_status[idx] = status;
+        if (a.out_ls) a.out_ls[idx] = ls_trials;
+      }
+      if (a.trace && own)
+        for (int kk = k + 1; kk < a.trace_len; ++kk)
+          a.trace[(idx * a.trace_len + kk) * d + j] = __builtin_nan("");
+      idx = -1;
+      continue;
+    }
+
+    // -- search direction p = -H g (reset to -g if not a descent direction) -
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+      if (c < d) acc = __builtin_fma(h[c], sh.gs[c], acc);
+    pj = own ? -acc : 0.0;
+    sh.ps[j] = pj;
+    wave_sync();
+    double ddir = 0.0;
+    for (int i = 0; i < d; ++i) ddir = ddir + sh.gs[i] * sh.ps[i];
+    if (!(ddir < 0.0)) {
+#pragma unroll
+      for (int c = 0; c < G; ++c) h[c] = (c == j) ? 1.0 : 0.0;
+      pj = own ? -gj : 0.0;
+      sh.ps[j] = pj;
+      wave_sync();
+      ddir = 0.0;
+      for (int i = 0; i < d; ++i) ddir = ddir + sh.gs[i] * sh.ps[i];
+    }
+
+    // -- Armijo backtracking, G trials per round ----------------------------
+    int taken = -1;
+    for (int base = 0; base < a.iter_ls; base += G) {
+      const int t = base + j;
+      bool ok = false;
+      if (t < a.iter_ls) {
+        double alpha = 1.0;
+        for (int q = 0; q < t; ++q) alpha = alpha * a.shrink;
+        const double ft = Obj<OBJ>::template eval<double>(
+            d, [&](int i) { return sh.xs[i] + alpha * sh.ps[i]; });
+        ok = ft <= f + (a.armijo_c * alpha) * ddir;
+      }
+      const uint64_t m = (__ballot(ok) & gmask) >> (grp * G);
+      if (m != 0ull) {
+        taken = base + (__ffsll((unsigned long long)m) - 1);
+        break;
+      }
+    }
+    const int nshrink = taken >= 0 ? taken : a.iter_ls;
+    ls_trials += taken >= 0 ? taken + 1 : a.iter_ls;
+    double alpha = 1.0;
+    for (int q = 0; q < nshrink; ++q) alpha = alpha * a.shrink;
+
+    // -- step ----------------------------------------------------------------
+    const double xnew = xj + alpha * pj;
+    sj = own ? xnew - xj : 0.0;
+    wave_sync();
+    sh.xs[j] = own ? xnew : 0.0;
+  }
+}
+
+// Best-of-N and counts over all starts (one block; deterministic).
+constexpr int kSumBlock = 1024;
+
+__global__ __launch_bounds__(kSumBlock) void summary_kernel(int64_t n, const double *f,
+                                                            const int32_t *status,
+                                                            const int32_t *iters,
+                                                            const int32_t *ls,
+                                                            const PsoBest *pso,
+                                                            zeus_summary *out) {
+  __shared__ double sk[kSumBlock / 64];
+  __shared__ int64_t si[kSumBlock / 64];
+  __shared__ int64_t sc[4][kSumBlock / 64];
+  double key = __builtin_huge_val();
+  int64_t idx = INT64_MAX;
+  int64_t nconv = 0, nnf = 0, it = 0, lt = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kSumBlock) {
+    const double fi = f[i];
+    if (__builtin_isfinite(fi) && key_less(fi, i, key, idx)) {
+      key = fi;
+      idx = i;
+    }
+    const int32_t st = status[i];
+    nconv += st == ZEUS_ST_CONVERGED;
+    nnf += st == ZEUS_ST_NONFINITE;
+    it += iters[i];
+    if (ls) lt += ls[i];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ok = __shfl_xor(key, off, 64);
+    const int64_t oi = __shfl_xor(idx, off, 64);
+    if (key_less(ok, oi, key, idx)) {
+      key = ok;
+      idx = oi;
+    }
+    nconv += __shfl_xor(nconv, off, 64);
+    nnf += __shfl_xor(nnf, off, 64);
+    it += __shfl_xor(it, off, 64);
+    lt += __shfl_xor(lt, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sk[wave] = key;
+    si[wave] = idx;
+    sc[0][wave] = nconv;
+    sc[1][wave] = nnf;
+    sc[2][wave] = it;
+    sc[3][wave] = lt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int wv = 1; wv < kSumBlock / 64; ++wv) {
+      if (key_less(sk[wv], si[wv], key, idx)) {
+        key = sk[wv];
+        idx = si[wv];
+      }
+      nconv += sc[0][wv];
+      nnf += sc[1][wv];
+      it += sc[2][wv];
+      lt += sc[3][wv];
+    }
+    const bool found = idx != INT64_MAX;
+    out->best_index = found ? idx : -1;
+    out->best_f = found ? f[idx] : __builtin_nan("");
+    out->n_converged = nconv;
+    out->n_nonfinite = nnf;
+    out->total_iters = it;
+    out->total_ls_trials = lt;
+    out->pso_best_index = pso->idx;
+    out->pso_best_f = pso->f;
+  }
+}
+
+template <int OBJ, int G>
+hipError_t launch_g(const BfgsArgs &a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((bfgs_kernel<OBJ, G>), dim3(blocks), dim3(kBfgsBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int OBJ>
+hipError_t launch_obj(const BfgsArgs &a, int G, int blocks, hipStream_t s) {
+  switch (G) {
+    case 8: return launch_g<OBJ, 8>(a, blocks, s);
+    case 16: return launch_g<OBJ, 16>(a, blocks, s);
+    case 32: return launch_g<OBJ, 32>(a, blocks, s);
+    case 64: return launch_g<OBJ, 64>(a, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int group_lanes(int dim) {
+  int g = 8;
+  while (g < dim) g <<= 1;
+  return g;
+}
+
+hipError_t launch_bfgs(const Launch &L) {
+  const zeus_problem &p = *L.pb;
+  BfgsArgs a;
+  a.n = p.n_starts;
+  a.d = p.dim;
+  a.iter_bfgs = p.iter_bfgs;
+  a.iter_ls = p.iter_ls;
+  a.trace_len = L.out->trace ? L.out->trace_len : 0;
+  a.armijo_c = p.armijo_c;
+  a.shrink = p.ls_shrink;
+  a.tol = p.grad_tol;
+  a.x0 = L.ws.x;
+  a.queue = L.ws.queue;
+  a.out_f = L.out->f;
+  a.out_x = L.out->x;
+  a.out_iters = L.out->iters;
+  a.out_status = L.out->status;
+  a.out_ls = L.out->ls_trials;
+  a.trace = a.trace_len > 0 ? L.out->trace : nullptr;
+  const int G = group_lanes(p.dim);
+  if (G > kMaxDim) return hipErrorInvalidValue;
+  const int64_t starts_per_block = (int64_t)(kBfgsBlock / G);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int cus = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (cus <= 0) cus = 256;
+  // enough resident blocks to fill the chip; the work counter balances them
+  const int64_t want = (p.n_starts + starts_per_block - 1) / starts_per_block;
+  const int64_t cap = (int64_t)cus * 8;
+  const int blocks = (int)(want < cap ? want : cap);
+  switch (p.objective) {
+    case kRosenbrock: return launch_obj<kRosenbrock>(a, G, blocks, L.stream);
+    case kRastrigin: return launch_obj<kRastrigin>(a, G, blocks, L.stream);
+    case kAckley: return launch_obj<kAckley>(a, G, blocks, L.stream);
+    case kStyblinskiTang: return launch_obj<kStyblinskiTang>(a, G, blocks, L.stream);
+    case kGoldsteinPrice: return launch_g<kGoldsteinPrice, 8>(a, blocks, L.stream);
+    case kSphere: return launch_obj<kSphere>(a, G, blocks, L.stream);
+    case kQuartic: return launch_obj<kQuartic>(a, G, blocks, L.stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_summary(const Launch &L) {
+  hipLaunchKernelGGL(summary_kernel, dim3(1), dim3(kSumBlock), 0, L.stream, L.pb->n_starts,
+                     L.out->f, L.out->status, L.out->iters, L.out->ls_trials, L.ws.best,
+                     L.out->summary);
+  return hipGetLastError();
+}
+
+}  // namespace zeus

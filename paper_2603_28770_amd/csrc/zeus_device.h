@@ -1,0 +1,301 @@
+// zeus_device.h -- device-side building blocks for gfx950: the counter-based
+// random stream, dual numbers and the objectives (written once, templated on
+// the number type so that the same code gives primal values and, on dual
+// numbers, directional derivatives).
+//
+// All code here is compiled with -ffp-contract=off: every multiply and add
+// rounds separately unless a kernel asks for a fused multiply-add explicitly
+// with __builtin_fma.  The evaluation order of each objective is fixed (left
+// to right sums) so that the swarm phase reproduces a plain sequential
+// evaluation bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zeus {
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Stateless: every draw is
+// a pure function of (counter, key), generated in registers when needed
+// (the on-demand generation of Sec. IV-A, without stored generator states).
+// ---------------------------------------------------------------------------
+struct u64x4 {
+  uint64_t w[4];
+};
+
+__device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                               uint64_t c3, uint64_t k0, uint64_t k1) {
+  constexpr uint64_t kMul0 = 0xD2E7470EE14C6C93ull;
+  constexpr uint64_t kMul1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kWeyl0 = 0x9E3779B97F4A7C15ull;
+  constexpr uint64_t kWeyl1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(kMul0, c0), lo0 = kMul0 * c0;
+    const uint64_t hi1 = __umul64hi(kMul1, c2), lo1 = kMul1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += kWeyl0;
+    k1 += kWeyl1;
+  }
+  return u64x4{{c0, c1, c2, c3}};
+}
+
+// 64 random bits -> double in [0, 1): top 53 bits times 2^-53 (exact).
+__device__ __forceinline__ double u01(uint64_t w) {
+  return static_cast<double>(w >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Stream tags: the fourth counter word.
+enum : uint64_t { kTagX0 = 0, kTagV0 = 1, kTagR1 = 2, kTagR2 = 3 };
+
+// ---------------------------------------------------------------------------
+// Dual numbers a + b eps, eps^2 = 0 (Sec. III-C).  T = double or float.
+// ---------------------------------------------------------------------------
+template <class T>
+struct dual {
+  T v, t;  // value, tangent
+};
+
+template <class T>
+__device__ __forceinline__ dual<T> operator+(dual<T> a, dual<T> b) {
+  return {a.v + b.v, a.t + b.t};
+}
+template <class T>
+__device__ __forceinline__ dual<T> operator-(dual<T> a, dual<T> b) {
+  return {a.v - b.v, a.t - b.t};
+}
+// (a + b eps)(c + e eps) = ac + (ae + bc) eps
+template <class T>
+__device__ __forceinline__ dual<T> operator*(dual<T> a, dual<T> b) {
+  return {a.v * b.v, a.v * b.t + a.t * b.v};
+}
+
+// Mixed constant/number operations, one overload set per number type.
+__device__ __forceinline__ double scale(double k, double a) { return k * a; }
+__device__ __forceinline__ float scale(float k, float a) { return k * a; }
+template <class T>
+__device__ __forceinline__ dual<T> scale(T k, dual<T> a) { return {k * a.v, k * a.t}; }
+
+__device__ __forceinline__ double divk(double a, double k) { return a / k; }
+__device__ __forceinline__ float divk(float a, float k) { return a / k; }
+template <class T>
+__device__ __forceinline__ dual<T> divk(dual<T> a, T k) { return {a.v / k, a.t / k}; }
+
+__device__ __forceinline__ double addk(double k, double a) { return k + a; }
+__device__ __forceinline__ float addk(float k, float a) { return k + a; }
+template <class T>
+__device__ __forceinline__ dual<T> addk(T k, dual<T> a) { return {k + a.v, a.t}; }
+
+__device__ __forceinline__ double ksub(double k, double a) { return k - a; }
+__device__ __forceinline__ float ksub(float k, float a) { return k - a; }
+template <class T>
+__device__ __forceinline__ dual<T> ksub(T k, dual<T> a) { return {k - a.v, -a.t}; }
+
+__device__ __forceinline__ double dcos(double a) { return cos(a); }
+__device__ __forceinline__ float dcos(float a) { return cosf(a); }
+__device__ __forceinline__ double dsin(double a) { return sin(a); }
+__device__ __forceinline__ float dsin(float a) { return sinf(a); }
+__device__ __forceinline__ double dexp(double a) { return exp(a); }
+__device__ __forceinline__ float dexp(float a) { return expf(a); }
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float dsqrt(float a) { return sqrtf(a); }
+
+// cos(a + b eps) = cos a - b sin a eps
+template <class T>
+__device__ __forceinline__ dual<T> dcos(dual<T> a) { return {dcos(a.v), -(a.t * dsin(a.v))}; }
+// exp(a + b eps) = e^a + b e^a eps
+template <class T>
+__device__ __forceinline__ dual<T> dexp(dual<T> a) {
+  const T e = dexp(a.v);
+  return {e, a.t * e};
+}
+// sqrt(a + b eps) = sqrt a + b / (2 sqrt a) eps
+template <class T>
+__device__ __forceinline__ dual<T> dsqrt(dual<T> a) {
+  const T s = dsqrt(a.v);
+  return {s, a.t / (T(2) * s)};
+}
+
+template <class N> struct scalar_of { using type = N; };
+template <class T> struct scalar_of<dual<T>> { using type = T; };
+
+template <class N>
+__device__ __forceinline__ N make_const(typename scalar_of<N>::type c);
+template <>
+__device__ __forceinline__ double make_const<double>(double c) { return c; }
+template <>
+__device__ __forceinline__ float make_const<float>(float c) { return c; }
+template <>
+__device__ __forceinline__ dual<double> make_const<dual<double>>(double c) { return {c, 0.0}; }
+template <>
+__device__ __forceinline__ dual<float> make_const<dual<float>>(float c) { return {c, 0.0f}; }
+
+// ---------------------------------------------------------------------------
+// Objectives (Sec. V-B; Styblinski-Tang; sphere and quartic for tests).
+// eval<N>(d, x) with x(i) returning coordinate i as number type N.
+// ---------------------------------------------------------------------------
+enum Objective : int {
+  kRosenbrock = 0,
+  kRastrigin = 1,
+  kAckley = 2,
+  kStyblinskiTang = 3,
+  kGoldsteinPrice = 4,
+  kSphere = 5,
+  kQuartic = 6
+};
+
+template <int OBJ>
+struct Obj;
+
+// sum_{i<d-1} (1 - x_i)^2 + 100 (x_{i+1} - x_i^2)^2
+template <>
+struct Obj<kRosenbrock> {
+  template <class N, class X>
+  __device__ __forceinline__ static N eval(int d, X x) {
+    using S = typename scalar_of<N>::type;
+    N s = make_const<N>(S(0));
+    N xi = x(0);
+    for (int i = 0; i + 1 < d; ++i) {
+      const N xn = x(i + 1);
+      const N a = ksub(S(1), xi);
+      const N b = xn - xi * xi;
+      const N term = a * a + scale(S(100), b * b);
+      s = s + term;
+      xi = xn;
+    }
+    return s;
+  }
+};
+
+// 10 d + sum (x_i^2 - 10 cos(2 pi x_i))
+template <>
+struct Obj<kRastrigin> {
+  template <class N, class X>
+  __device__ __forceinline__ static N eval(int d, X x) {
+    using S = typename scalar_of<N>::type;
+    N s = make_const<N>(S(0));
+    for (int i = 0; i < d; ++i) {
+      const N xi = x(i);
+      const N c = dcos(scale(S(6.283185307179586), xi));
+      const N term = xi * xi - scale(S(10), c);
+      s = s + term;
+    }
+    return addk(S(10) * S(d), s);
+  }
+};
+
+// -20 exp(-0.2 sqrt(sum x^2 / d)) - exp(sum cos(2 pi x) / d) + 20 + e
+template <>
+struct Obj<kAckley> {
+  template <class N, class X>
+  __device__ __forceinline__ static N eval(int d, X x) {
+    using S = typename scalar_of<N>::type;
+    N s1 = make_const<N>(S(0)), s2 = make_const<N>(S(0));
+    for (int i = 0; i < d; ++i) {
+      const N xi = x(i);
+      s1 = s1 + xi * xi;
+      s2 = s2 + dcos(scale(S(6.283185307179586), xi));
+    }
+    const N a = scale(S(-20), dexp(scale(S(-0.2), dsqrt(divk(s1, S(d))))));
+    const N b = dexp(divk(s2, S(d)));
+    N r = a - b;
+    r = addk(S(20), r);
+    r = addk(S(2.718281828459045), r);
+    return r;
+  }
+};
+
+// 0.5 sum (x^4 - 16 x^2 + 5 x)
+template <>
+struct Obj<kStyblinskiTang> {
+  template <class N, class X>
+  __device__ __forceinline__ static N eval(int d, X x) {
+    using S = typename scalar_of<N>::type;
+    N s = make_const<N>(S(0));
+    for (int i = 0; i < d; ++i) {
+      const N xi = x(i);
+      const N x2 = xi * xi;
+      const N x4 = x2 * x2;
+      const N term = (x4 - scale(S(16), x2)) + scale(S(5), xi);
+      s = s + term;
+    }
+    return scale(S(0.5), s);
+  }
+};
+
+// Goldstein-Price, d = 2
+template <>
+struct Obj<kGoldsteinPrice> {
+  template <class N, class X>
+  __device__ __forceinline__ static N eval(int, X x) {
+    using S = typename scalar_of<N>::type;
+    const N x1 = x(0), x2 = x(1);
+    const N a = addk(S(1), x1 + x2);
+    N pa = ksub(S(19), scale(S(14), x1));
+    pa = pa + scale(S(3), x1 * x1);
+    pa = pa - scale(S(14), x2);
+    pa = pa + scale(S(6), x1 * x2);
+    pa = pa + scale(S(3), x2 * x2);
+    const N A = addk(S(1), (a * a) * pa);
+    const N b = scale(S(2), x1) - scale(S(3), x2);
+    N pb = ksub(S(18), scale(S(32), x1));
+    pb = pb + scale(S(12), x1 * x1);
+    pb = pb + scale(S(48), x2);
+    pb = pb - scale(S(36), x1 * x2);
+    pb = pb + scale(S(27), x2 * x2);
+    const N B = addk(S(30), (b * b) * pb);
+    return A * B;
+  }
+};
+
+// 0.5 sum x^2
+template <>
+struct Obj<kSphere> {
+  template <class N, class X>
+  __device__ __forceinline__ static N eval(int d, X x) {
+    using S = typename scalar_of<N>::type;
+    N s = make_const<N>(S(0));
+    for (int i = 0; i < d; ++i) {
+      const N xi = x(i);
+      s = s + xi * xi;
+    }
+    return scale(S(0.5), s);
+  }
+};
+
+// sum x^4
+template <>
+struct Obj<kQuartic> {
+  template <class N, class X>
+  __device__ __forceinline__ static N eval(int d, X x) {
+    using S = typename scalar_of<N>::type;
+    N s = make_const<N>(S(0));
+    for (int i = 0; i < d; ++i) {
+      const N xi = x(i);
+      const N x2 = xi * xi;
+      s = s + x2 * x2;
+    }
+    return s;
+  }
+};
+
+// NaN ranks as +infinity in every best-of comparison.
+__device__ __forceinline__ double rank_key(double f) {
+  return (f != f) ? __builtin_huge_val() : f;
+}
+
+// (key, index) lexicographic minimum: lowest value, lowest index on ties.
+struct KeyIdx {
+  double key;
+  int64_t idx;
+};
+__device__ __forceinline__ bool key_less(double ka, int64_t ia, double kb, int64_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+}  // namespace zeus

@@ -1,0 +1,250 @@
+"""Thin ctypes binding of libzeus.so (the C ABI in include/zeus.h).
+
+The entry points keep their C names; this module only marshals arguments.
+Every step of the method runs in the HIP kernels of libzeus.so; there is no
+fallback: if the library is missing, importing this module raises.
+
+PyTorch (imported first, so that one HIP runtime serves both) supplies device
+memory and streams for the asynchronous entry point.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzeus.so")
+
+ABI_VERSION = 1
+OK, NOT_READY, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ECANCELLED, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
+OBJECTIVES = {"rosenbrock": 0, "rastrigin": 1, "ackley": 2, "styblinski_tang": 3,
+              "goldstein_price": 4, "sphere": 5, "quartic": 6}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+ST_MAXITER, ST_CONVERGED, ST_STOPPED, ST_NONFINITE = 0, 1, 2, 3
+
+# Symbols declared in include/zeus.h.
+EXPORTS = ("zeus_abi_version", "zeus_version", "zeus_last_error", "zeus_validate",
+           "zeus_workspace_bytes", "zeus_context_create", "zeus_context_destroy",
+           "zeus_context_set_profiling", "zeus_context_get_profile", "zeus_minimize",
+           "zeus_minimize_async")
+
+
+class zeus_problem(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("objective", C.c_int32), ("dim", C.c_int32),
+                ("precision", C.c_int32), ("n_starts", C.c_int64), ("lower", C.c_double),
+                ("upper", C.c_double), ("iter_pso", C.c_int32), ("iter_bfgs", C.c_int32),
+                ("iter_ls", C.c_int32), ("reserved0", C.c_int32), ("w", C.c_double),
+                ("c1", C.c_double), ("c2", C.c_double), ("v_half", C.c_double),
+                ("armijo_c", C.c_double), ("ls_shrink", C.c_double), ("grad_tol", C.c_double),
+                ("required_converged", C.c_int64), ("seed", C.c_uint64),
+                ("request_id", C.c_uint64)]
+
+
+class zeus_summary(C.Structure):
+    _fields_ = [("best_index", C.c_int64), ("best_f", C.c_double), ("n_converged", C.c_int64),
+                ("n_nonfinite", C.c_int64), ("total_iters", C.c_int64),
+                ("total_ls_trials", C.c_int64), ("pso_best_index", C.c_int64),
+                ("pso_best_f", C.c_double)]
+
+
+class zeus_result(C.Structure):
+    _fields_ = [("f", C.c_void_p), ("x", C.c_void_p), ("iters", C.c_void_p),
+                ("status", C.c_void_p), ("ls_trials", C.c_void_p), ("seeds", C.c_void_p),
+                ("pso_v", C.c_void_p), ("pso_px", C.c_void_p), ("pso_pf", C.c_void_p),
+                ("pso_best_x", C.c_void_p), ("trace", C.c_void_p), ("trace_len", C.c_int32),
+                ("reserved0", C.c_int32), ("summary", C.c_void_p)]
+
+
+class zeus_profile(C.Structure):
+    _fields_ = [("pso_ms", C.c_double), ("bfgs_ms", C.c_double), ("reduce_ms", C.c_double),
+                ("pso_launches", C.c_int64), ("bfgs_launches", C.c_int64),
+                ("reduce_launches", C.c_int64)]
+
+
+class ZeusError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"zeus error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2603_28770_amd.build` (no fallback exists)")
+    try:  # share torch's HIP runtime when torch is present
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    L.zeus_abi_version.restype = C.c_uint32
+    L.zeus_version.restype = C.c_char_p
+    L.zeus_last_error.restype = C.c_char_p
+    L.zeus_validate.argtypes = [P(zeus_problem)]
+    L.zeus_workspace_bytes.argtypes = [P(zeus_problem), P(C.c_size_t)]
+    L.zeus_context_create.argtypes = [C.c_int, P(C.c_void_p)]
+    L.zeus_context_destroy.argtypes = [C.c_void_p]
+    L.zeus_context_set_profiling.argtypes = [C.c_void_p, C.c_int]
+    L.zeus_context_get_profile.argtypes = [C.c_void_p, P(zeus_profile)]
+    L.zeus_minimize.argtypes = [C.c_void_p, P(zeus_problem), P(zeus_result)]
+    L.zeus_minimize_async.argtypes = [C.c_void_p, P(zeus_problem), C.c_void_p, C.c_size_t,
+                                      P(zeus_result), C.c_void_p]
+    for name in EXPORTS:
+        if name not in ("zeus_abi_version", "zeus_version", "zeus_last_error"):
+            getattr(L, name).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(code):
+    if code != OK:
+        raise ZeusError(code, lib.zeus_last_error().decode())
+    return code
+
+
+def make_problem(p: dict) -> zeus_problem:
+    """Map a workload dict to zeus_problem (defaults are the paper's)."""
+    return zeus_problem(
+        abi_version=ABI_VERSION, objective=OBJECTIVES[p["objective"]], dim=int(p["dim"]),
+        precision=PRECISIONS[p.get("precision", "fp64")], n_starts=int(p["n"]),
+        lower=float(p["lower"]), upper=float(p["upper"]), iter_pso=int(p.get("iter_pso", 0)),
+        iter_bfgs=int(p.get("iter_bfgs", 100)), iter_ls=int(p.get("iter_ls", 20)), reserved0=0,
+        w=float(p.get("w", 0.5)), c1=float(p.get("c1", 1.2)), c2=float(p.get("c2", 1.5)),
+        v_half=float(p.get("v_half", 0.0)), armijo_c=float(p.get("armijo_c", 0.3)),
+        ls_shrink=float(p.get("ls_shrink", 0.5)), grad_tol=float(p.get("grad_tol", 1e-6)),
+        required_converged=int(p.get("required_converged", 0)), seed=int(p.get("seed", 0)),
+        request_id=int(p.get("request_id", 0)))
+
+
+# ---- C entry points under their own names --------------------------------------
+
+def zeus_abi_version() -> int:
+    return lib.zeus_abi_version()
+
+
+def zeus_version() -> str:
+    return lib.zeus_version().decode()
+
+
+def zeus_last_error() -> str:
+    return lib.zeus_last_error().decode()
+
+
+def zeus_validate(problem: zeus_problem) -> int:
+    return lib.zeus_validate(C.byref(problem))
+
+
+def zeus_workspace_bytes(problem: zeus_problem) -> int:
+    b = C.c_size_t()
+    _check(lib.zeus_workspace_bytes(C.byref(problem), C.byref(b)))
+    return b.value
+
+
+def zeus_context_create(device: int = 0) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib.zeus_context_create(int(device), C.byref(h)))
+    return h
+
+
+def zeus_context_destroy(ctx) -> None:
+    _check(lib.zeus_context_destroy(ctx))
+
+
+def zeus_context_set_profiling(ctx, enabled: bool) -> None:
+    _check(lib.zeus_context_set_profiling(ctx, 1 if enabled else 0))
+
+
+def zeus_context_get_profile(ctx) -> dict:
+    p = zeus_profile()
+    _check(lib.zeus_context_get_profile(ctx, C.byref(p)))
+    return {k: getattr(p, k) for k, _ in zeus_profile._fields_}
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p).value
+
+
+def zeus_minimize(ctx, problem, *, trace_len=0, pso_state=False, ls_trials=True) -> dict:
+    """Blocking solve; returns host numpy arrays."""
+    pb = problem if isinstance(problem, zeus_problem) else make_problem(problem)
+    n, d = pb.n_starts, pb.dim
+    o = {"f": np.empty(n), "x": np.empty((n, d)), "iters": np.empty(n, np.int32),
+         "status": np.empty(n, np.int32)}
+    if ls_trials:
+        o["ls_trials"] = np.empty(n, np.int32)
+    if pso_state:
+        o.update(seeds=np.empty((n, d)), pso_v=np.empty((n, d)), pso_px=np.empty((n, d)),
+                 pso_pf=np.empty(n), pso_best_x=np.empty(d))
+    if trace_len:
+        o["trace"] = np.empty((n, trace_len, d))
+    s = zeus_summary()
+    r = zeus_result(f=_np_ptr(o["f"]), x=_np_ptr(o["x"]), iters=_np_ptr(o["iters"]),
+                    status=_np_ptr(o["status"]), ls_trials=_np_ptr(o.get("ls_trials")),
+                    seeds=_np_ptr(o.get("seeds")), pso_v=_np_ptr(o.get("pso_v")),
+                    pso_px=_np_ptr(o.get("pso_px")), pso_pf=_np_ptr(o.get("pso_pf")),
+                    pso_best_x=_np_ptr(o.get("pso_best_x")), trace=_np_ptr(o.get("trace")),
+                    trace_len=int(trace_len), reserved0=0,
+                    summary=C.cast(C.pointer(s), C.c_void_p).value)
+    _check(lib.zeus_minimize(ctx, C.byref(pb), C.byref(r)))
+    o["summary"] = {k: getattr(s, k) for k, _ in zeus_summary._fields_}
+    return o
+
+
+def zeus_minimize_async(ctx, problem, workspace_ptr: int, workspace_bytes: int,
+                        result: zeus_result, stream_ptr: int = 0) -> None:
+    """Enqueue a solve with caller-owned device memory (e.g. torch tensors)."""
+    pb = problem if isinstance(problem, zeus_problem) else make_problem(problem)
+    _check(lib.zeus_minimize_async(ctx, C.byref(pb), C.c_void_p(workspace_ptr),
+                                   C.c_size_t(workspace_bytes), C.byref(result),
+                                   C.c_void_p(stream_ptr) if stream_ptr else None))
+
+
+class DeviceSolve:
+    """Device-resident buffers (torch tensors) for zeus_minimize_async."""
+
+    def __init__(self, problem: dict, device="cuda:0", trace_len=0, pso_state=False):
+        import torch
+        self.pb = make_problem(problem)
+        n, d = self.pb.n_starts, self.pb.dim
+        dev = torch.device(device)
+        ws = zeus_workspace_bytes(self.pb)
+        self.ws = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.ws_bytes = ws
+        f64, i32 = torch.float64, torch.int32
+        self.t = {"f": torch.empty(n, dtype=f64, device=dev),
+                  "x": torch.empty((n, d), dtype=f64, device=dev),
+                  "iters": torch.empty(n, dtype=i32, device=dev),
+                  "status": torch.empty(n, dtype=i32, device=dev),
+                  "ls_trials": torch.empty(n, dtype=i32, device=dev),
+                  "summary": torch.empty(C.sizeof(zeus_summary), dtype=torch.uint8, device=dev)}
+        if pso_state:
+            self.t.update(seeds=torch.empty((n, d), dtype=f64, device=dev),
+                          pso_v=torch.empty((n, d), dtype=f64, device=dev),
+                          pso_px=torch.empty((n, d), dtype=f64, device=dev),
+                          pso_pf=torch.empty(n, dtype=f64, device=dev),
+                          pso_best_x=torch.empty(d, dtype=f64, device=dev))
+        if trace_len:
+            self.t["trace"] = torch.empty((n, trace_len, d), dtype=f64, device=dev)
+        p = lambda k: self.t[k].data_ptr() if k in self.t else None
+        self.result = zeus_result(f=p("f"), x=p("x"), iters=p("iters"), status=p("status"),
+                                  ls_trials=p("ls_trials"), seeds=p("seeds"), pso_v=p("pso_v"),
+                                  pso_px=p("pso_px"), pso_pf=p("pso_pf"),
+                                  pso_best_x=p("pso_best_x"), trace=p("trace"),
+                                  trace_len=int(trace_len), reserved0=0, summary=p("summary"))
+
+    def enqueue(self, ctx, stream_ptr: int = 0):
+        zeus_minimize_async(ctx, self.pb, self.ws_ptr, self.ws_bytes, self.result, stream_ptr)
+
+    def summary(self) -> dict:
+        raw = bytes(self.t["summary"].cpu().numpy().tobytes())
+        s = zeus_summary.from_buffer_copy(raw)
+        return {k: getattr(s, k) for k, _ in zeus_summary._fields_}
+
+    def host(self) -> dict:
+        out = {k: v.cpu().numpy() for k, v in self.t.items() if k != "summary"}
+        out["summary"] = self.summary()
+        return out

@@ -1,0 +1,115 @@
+"""CPU-only checks of the C ABI library: it loads, exports every entry point
+declared in include/zeus.h, its struct layouts match the header as compiled
+by gcc, and argument validation behaves as documented (no GPU needed)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "zeus.h")
+
+
+@pytest.fixture(scope="module")
+def Z():
+    from paper_2603_28770_amd import zeus
+    return zeus
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(zeus_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(Z):
+    names = _declared()
+    assert len(names) >= 11
+    out = subprocess.run(["nm", "-D", "--defined-only", Z.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (zeus_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert set(Z.EXPORTS) == set(names)
+
+
+def test_struct_layouts_match_header(Z, tmp_path):
+    import ctypes as C
+    prog = tmp_path / "layout.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "zeus.h"\n'
+                    "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\","
+                    "sizeof(zeus_problem), sizeof(zeus_result), sizeof(zeus_summary),"
+                    "sizeof(zeus_profile), offsetof(zeus_problem, seed),"
+                    "offsetof(zeus_result, summary), offsetof(zeus_problem, grad_tol));return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o",
+                    str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals == [C.sizeof(Z.zeus_problem), C.sizeof(Z.zeus_result),
+                    C.sizeof(Z.zeus_summary), C.sizeof(Z.zeus_profile),
+                    Z.zeus_problem.seed.offset, Z.zeus_result.summary.offset,
+                    Z.zeus_problem.grad_tol.offset]
+
+
+def test_version(Z):
+    assert Z.zeus_abi_version() == 1 and "gfx950" in Z.zeus_version()
+
+
+def _p(**kw):
+    from paper_2603_28770_amd import workloads as W
+    p = W.problem(objective="rastrigin", dim=10, n=1000, lower=-5.12, upper=5.12, iter_pso=3)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("bad", [dict(dim=0), dict(n=0), dict(lower=1.0, upper=1.0),
+                                 dict(upper=float("nan")), dict(iter_ls=0),
+                                 dict(iter_bfgs=-1), dict(iter_pso=-1), dict(grad_tol=0.0),
+                                 dict(grad_tol=float("inf")), dict(armijo_c=0.0),
+                                 dict(armijo_c=1.0), dict(ls_shrink=1.0), dict(c1=float("inf")),
+                                 dict(objective="rosenbrock", dim=1),
+                                 dict(objective="goldstein_price", dim=3),
+                                 dict(required_converged=-1)])
+def test_validation_rejects(Z, bad):
+    assert Z.zeus_validate(Z.make_problem(_p())) == Z.OK
+    pb = Z.make_problem(_p(**bad))
+    assert Z.zeus_validate(pb) == Z.EINVAL
+    assert Z.zeus_last_error() != ""
+
+
+def test_validation_abi_and_reserved(Z):
+    pb = Z.make_problem(_p())
+    pb.abi_version = 2
+    assert Z.zeus_validate(pb) == Z.EINVAL
+    pb = Z.make_problem(_p())
+    pb.reserved0 = 1
+    assert Z.zeus_validate(pb) == Z.EINVAL
+    pb = Z.make_problem(_p())
+    pb.objective = 99
+    assert Z.zeus_validate(pb) == Z.EINVAL
+    assert Z.lib.zeus_validate(None) == Z.EINVAL
+
+
+@pytest.mark.parametrize("unsup", [dict(dim=65), dict(required_converged=5)])
+def test_validation_unsupported(Z, unsup):
+    assert Z.zeus_validate(Z.make_problem(_p(**unsup))) == Z.EUNSUPPORTED
+
+
+def test_workspace_bytes(Z):
+    pb = Z.make_problem(_p(n=65536, dim=10))
+    b = Z.zeus_workspace_bytes(pb)
+    n, d = 65536, 10
+    assert 3 * 8 * n * d + 8 * n <= b <= 3 * 8 * n * d + 8 * n + 64 * 1024
+    with pytest.raises(Z.ZeusError):
+        Z.zeus_workspace_bytes(Z.make_problem(_p(dim=0)))
+
+
+def test_context_without_device_is_a_clean_error(Z):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(Z.ZeusError) as e:
+        Z.zeus_context_create(0)
+    assert e.value.code in (Z.EHIP, Z.EINVAL)

@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded problems.
+
+Bars:
+  * swarm phase: bit-exact positions, velocities, personal bests and global
+    best for every objective (both sides evaluate the objective in the same
+    order without fused multiply-adds; transcendental objectives may differ by
+    an ulp in the personal-best values, which is checked to 1e-15 relative);
+  * BFGS iterates: the first 20 iterates agree to 1e-9 relative (infinity
+    norm) up to the first iteration where the oracle took a branch with a
+    relative margin below 1e-9 (a near-tie that rounding may flip);
+  * final results: same status and iteration count and |df| <= 1e-6 max(1,|f|)
+    for starts without a near-tie; success rates (f - f* < 1e-4) within 0.01
+    over all starts.
+"""
+import numpy as np
+import pytest
+
+from paper_2603_28770_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TRAJ_TOL = 1e-9
+F_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def Z():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28770_amd import zeus  # raises if libzeus.so is missing
+    return zeus
+
+
+@pytest.fixture(scope="module")
+def ctx(Z):
+    c = Z.zeus_context_create(0)
+    yield c
+    Z.zeus_context_destroy(c)
+
+
+def _run_both(Z, ctx, O, p, trace_len=20, idx=None):
+    print(f"\n[parity] {p.get('name', p['objective'])} d={p['dim']} n={p['n']}", flush=True)
+    g = Z.zeus_minimize(ctx, p, trace_len=trace_len, pso_state=True)
+    sw = O.pso(p)
+    o = O.bfgs(p, sw["x"], idx=idx, trace_len=trace_len)
+    return g, sw, o
+
+
+def _check_pso(g, sw, transcendental):
+    assert np.array_equal(g["seeds"], sw["x"])
+    assert np.array_equal(g["pso_v"], sw["v"])
+    assert np.array_equal(g["pso_px"], sw["px"])
+    assert np.array_equal(g["pso_best_x"], sw["gx"])
+    assert g["summary"]["pso_best_index"] == sw["gidx"]
+    if transcendental:
+        assert np.allclose(g["pso_pf"], sw["pf"], rtol=1e-15, atol=1e-300)
+    else:
+        assert np.array_equal(g["pso_pf"], sw["pf"])
+
+
+def _check_bfgs(g, o, p, idx=None, max_tie_share=0.35, max_mismatch_share=0.02):
+    sel = np.arange(p["n"]) if idx is None else np.asarray(idx)
+    gf, gx, gi, gs = g["f"][sel], g["x"][sel], g["iters"][sel], g["status"][sel]
+    tie = o["tie_iter"]
+    clean = tie < 0
+    # trajectories: first iterates up to (and including) the near-tie step
+    tr_g, tr_o = g["trace"][sel], o["trace"]
+    L = tr_o.shape[1]
+    worst = 0.0
+    for s in range(sel.size):
+        kmax = min(L, o["iters"][s] + 1)
+        if tie[s] >= 0:
+            kmax = min(kmax, tie[s] + 1)
+        if kmax == 0:
+            continue
+        a, b = tr_g[s, :kmax], tr_o[s, :kmax]
+        scale = np.maximum(1.0, np.max(np.abs(b), axis=1))
+        err = np.max(np.abs(a - b), axis=1) / scale
+        worst = max(worst, float(err.max()))
+    print(f"[parity]   worst trajectory rel err {worst:.3e}; near-tie starts "
+          f"{np.mean(~clean):.3f}", flush=True)
+    assert worst <= TRAJ_TOL
+    # final results for starts without a near-tie
+    fs = np.maximum(1.0, np.abs(o["f"]))
+    df = np.abs(gf - o["f"]) / fs
+    same = (gs == o["status"]) & (gi == o["iters"]) & (df <= F_TOL)
+    bad_clean = np.flatnonzero(clean & ~same)
+    print(f"[parity]   clean starts {clean.sum()}, clean mismatches {bad_clean.size}, "
+          f"all mismatches {np.sum(~same)}", flush=True)
+    assert bad_clean.size == 0, (bad_clean[:10], gs[bad_clean[:10]], o["status"][bad_clean[:10]],
+                                 gi[bad_clean[:10]], o["iters"][bad_clean[:10]])
+    assert np.mean(~clean) <= max_tie_share
+    fval_ok = (df <= F_TOL) | ~np.isfinite(o["f"])
+    assert np.mean(~fval_ok) <= max_mismatch_share
+    fstar = W.f_star(p["objective"], p["dim"])
+    rate_g = np.mean(gf - fstar < 1e-4)
+    rate_o = np.mean(o["f"] - fstar < 1e-4)
+    print(f"[parity]   success gpu {rate_g:.4f} oracle {rate_o:.4f}", flush=True)
+    assert abs(rate_g - rate_o) <= 0.01
+
+
+def _check_summary(g):
+    s = g["summary"]
+    f, st = g["f"], g["status"]
+    fin = np.isfinite(f)
+    if fin.any():
+        b = int(np.flatnonzero(fin & (f == f[fin].min()))[0])
+        assert s["best_index"] == b and s["best_f"] == f[b]
+    else:
+        assert s["best_index"] == -1
+    assert s["n_converged"] == int(np.sum(st == 1))
+    assert s["n_nonfinite"] == int(np.sum(st == 3))
+    assert s["total_iters"] == int(g["iters"].sum())
+    assert s["total_ls_trials"] == int(g["ls_trials"].sum())
+
+
+CASES = [
+    (W.ROSENBROCK_D2, False),
+    (W.problem(name="rastrigin_d10", objective="rastrigin", dim=10, n=2000, lower=-5.12,
+               upper=5.12, iter_pso=20, iter_bfgs=1000, seed=1), True),
+    (W.problem(name="styblinski_d13", objective="styblinski_tang", dim=13, n=1000, lower=-5.0,
+               upper=5.0, iter_pso=7, iter_bfgs=1000, seed=3, request_id=5), False),
+    (W.problem(name="ackley_d7", objective="ackley", dim=7, n=777, lower=-5.0, upper=5.0,
+               iter_pso=5, iter_bfgs=300, seed=2), True),
+    (W.problem(name="goldstein_price", objective="goldstein_price", dim=2, n=1500, lower=-2.0,
+               upper=2.0, iter_pso=4, iter_bfgs=500, seed=6), False),
+    (W.problem(name="rosenbrock_d33", objective="rosenbrock", dim=33, n=300, lower=-5.0,
+               upper=5.0, iter_pso=5, iter_bfgs=400, seed=2), False),
+    (W.problem(name="quartic_d17", objective="quartic", dim=17, n=257, lower=-3.0, upper=3.0,
+               iter_pso=2, iter_bfgs=200, seed=9), False),
+    (W.problem(name="sphere_d64", objective="sphere", dim=64, n=129, lower=-3.0, upper=3.0,
+               iter_pso=3, iter_bfgs=50, seed=4), False),
+]
+
+
+@pytest.mark.parametrize("p,transc", CASES, ids=[c[0]["name"] for c in CASES])
+def test_parity(Z, ctx, oracle_mod, p, transc):
+    g, sw, o = _run_both(Z, ctx, oracle_mod, p)
+    _check_pso(g, sw, transc)
+    _check_bfgs(g, o, p)
+    _check_summary(g)
+
+
+def test_rosenbrock_d64_max_dim(Z, ctx, oracle_mod):
+    p = W.problem(name="rosenbrock_d64", objective="rosenbrock", dim=64, n=70, lower=-2.0,
+                  upper=2.0, iter_pso=2, iter_bfgs=300, seed=12)
+    g, sw, o = _run_both(Z, ctx, oracle_mod, p)
+    _check_pso(g, sw, False)
+    _check_bfgs(g, o, p)
+
+
+def test_single_start_and_dim_one(Z, ctx, oracle_mod):
+    for p in (W.problem(name="one", objective="rastrigin", dim=3, n=1, lower=-2.0, upper=2.0,
+                        iter_pso=3, seed=8),
+              W.problem(name="d1", objective="styblinski_tang", dim=1, n=100, lower=-5.0,
+                        upper=5.0, iter_pso=2, seed=8)):
+        g, sw, o = _run_both(Z, ctx, oracle_mod, p)
+        _check_pso(g, sw, p["objective"] == "rastrigin")
+        _check_bfgs(g, o, p)
+        _check_summary(g)
+
+
+def test_zero_budgets(Z, ctx, oracle_mod):
+    p = W.problem(name="zero", objective="rosenbrock", dim=5, n=300, lower=-2.0, upper=2.0,
+                  iter_pso=0, iter_bfgs=0, seed=3)
+    g, sw, o = _run_both(Z, ctx, oracle_mod, p, trace_len=2)
+    _check_pso(g, sw, False)
+    assert np.array_equal(g["x"], sw["x"]) and np.all(g["iters"] == 0)
+    assert np.all(g["status"] == 0) and np.array_equal(g["f"], o["f"])
+    assert np.all(np.isnan(g["trace"][:, 1]))
+
+
+def test_non_finite_path(Z, ctx):
+    p = W.problem(name="huge", objective="rosenbrock", dim=3, n=64, lower=1e200, upper=2e200,
+                  iter_bfgs=10)
+    g = Z.zeus_minimize(ctx, p)
+    assert np.all(g["status"] == 3) and np.all(g["iters"] == 0)
+    assert g["summary"]["best_index"] == -1 and g["summary"]["n_nonfinite"] == 64
+
+
+def test_ackley_failure_mode(Z, ctx):
+    p = W.problem(name="ackley0", objective="ackley", dim=2, n=64, lower=-0.1, upper=0.1,
+                  iter_bfgs=200, seed=5)
+    g = Z.zeus_minimize(ctx, p)
+    assert np.all(g["status"] == 0) and np.all(g["iters"] == 200) and g["f"].max() < 1e-12
+
+
+def test_sphere_one_exact_step(Z, ctx):
+    p = W.problem(objective="sphere", dim=9, n=500, lower=-3.0, upper=3.0, iter_pso=2, seed=2)
+    g = Z.zeus_minimize(ctx, p)
+    assert np.all(g["status"] == 1) and np.all(g["iters"] == 1) and np.all(g["x"] == 0.0)
+
+
+def test_deterministic_repeat(Z, ctx):
+    p = W.scaled(W.RASTRIGIN_D10, 5000)
+    a = Z.zeus_minimize(ctx, p, pso_state=True)
+    b = Z.zeus_minimize(ctx, p, pso_state=True)
+    for k in ("f", "x", "iters", "status", "ls_trials", "seeds"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_async_matches_blocking(Z, ctx):
+    import torch
+    p = W.scaled(W.RASTRIGIN_D10, 3000)
+    a = Z.zeus_minimize(ctx, p, pso_state=True, trace_len=4)
+    ds = Z.DeviceSolve(p, trace_len=4, pso_state=True)
+    s = torch.cuda.Stream()
+    ds.enqueue(ctx, s.cuda_stream)
+    s.synchronize()
+    b = ds.host()
+    for k in ("f", "x", "iters", "status", "ls_trials", "seeds", "pso_v", "pso_px", "pso_pf",
+              "pso_best_x", "trace"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    assert a["summary"] == b["summary"]
+
+
+def test_errors_through_the_abi(Z, ctx):
+    bad = Z.make_problem(W.problem(objective="rastrigin", dim=65, n=10, lower=-1.0, upper=1.0))
+    with pytest.raises(Z.ZeusError) as e:
+        Z.zeus_minimize(ctx, bad)
+    assert e.value.code == Z.EUNSUPPORTED
+    with pytest.raises(Z.ZeusError) as e:
+        Z.zeus_minimize(ctx, W.problem(objective="rastrigin", dim=0, n=10, lower=-1.0, upper=1.0))
+    assert e.value.code == Z.EINVAL
+
+
+def test_full_size_rastrigin_sampled(Z, ctx, oracle_mod):
+    """The benchmark's workload at full size (N = 65,536, d = 10): the whole
+    swarm bit for bit and a strided sample of 512 starts against the oracle."""
+    p = W.RASTRIGIN_D10
+    idx = W.strided_subset(p["n"], 512)
+    g, sw, o = _run_both(Z, ctx, oracle_mod, p, idx=idx)
+    _check_pso(g, sw, True)
+    _check_bfgs(g, o, p, idx=idx)
+    _check_summary(g)
