@@ -121,7 +121,7 @@ def main():
     p = WORKLOADS[args.workload]
     ctx = Z.zeus_context_create(0)
     ds = Z.DeviceSolve(p)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()   # the library's kernels and torch's events share it
     sptr = stream.cuda_stream
 
     for _ in range(args.warmup):

@@ -71,6 +71,102 @@ double zo_uniform(uint64_t seed, uint64_t request_id, uint64_t i, uint64_t t,
 }
 
 /* ======================================================================== */
+/* sin, cos and exp in double precision, by Cody-Waite argument reduction    */
+/* (Cody and Waite, "Software Manual for the Elementary Functions", 1980)    */
+/* followed by the Taylor series of the reduced argument, evaluated by       */
+/* Horner's rule with fused multiply-adds.  Accurate to about one ulp.  The  */
+/* objectives use these instead of the C library so that their rounding is   */
+/* specified here, operation by operation.                                  */
+/* ======================================================================== */
+
+/* pi/2 as an unevaluated sum of three doubles, and 2/pi rounded. */
+static const double ZM_PIO2_1 = 0x1.921fb54442d18p+0;
+static const double ZM_PIO2_2 = 0x1.1a62633145c07p-54;
+static const double ZM_PIO2_3 = -0x1.f1976b7ed8fbcp-110;
+static const double ZM_2_OVER_PI = 0x1.45f306dc9c883p-1;
+/* ln 2 as a sum of two doubles, and log2(e) rounded. */
+static const double ZM_LN2_1 = 0x1.62e42fefa39efp-1;
+static const double ZM_LN2_2 = 0x1.abc9e3b39803fp-56;
+static const double ZM_LOG2E = 0x1.71547652b82fep+0;
+/* beyond this |x| the three-term reduction loses accuracy: use libm */
+static const double ZM_TRIG_MAX = 0x1p28;
+
+/* sin r and cos r for |r| <= pi/4 (Taylor series to r^17 and r^16). */
+static double sin_taylor(double r) {
+  double z = r * r;
+  double p = 1.0 / 355687428096000.0;     /*  1/17! */
+  p = fma(p, z, -1.0 / 1307674368000.0);  /* -1/15! */
+  p = fma(p, z, 1.0 / 6227020800.0);      /*  1/13! */
+  p = fma(p, z, -1.0 / 39916800.0);       /* -1/11! */
+  p = fma(p, z, 1.0 / 362880.0);          /*  1/9!  */
+  p = fma(p, z, -1.0 / 5040.0);           /* -1/7!  */
+  p = fma(p, z, 1.0 / 120.0);             /*  1/5!  */
+  p = fma(p, z, -1.0 / 6.0);              /* -1/3!  */
+  return fma(r * z, p, r);
+}
+
+static double cos_taylor(double r) {
+  double z = r * r;
+  double q = 1.0 / 20922789888000.0;      /*  1/16! */
+  q = fma(q, z, -1.0 / 87178291200.0);    /* -1/14! */
+  q = fma(q, z, 1.0 / 479001600.0);       /*  1/12! */
+  q = fma(q, z, -1.0 / 3628800.0);        /* -1/10! */
+  q = fma(q, z, 1.0 / 40320.0);           /*  1/8!  */
+  q = fma(q, z, -1.0 / 720.0);            /* -1/6!  */
+  q = fma(q, z, 1.0 / 24.0);              /*  1/4!  */
+  q = fma(q, z, -1.0 / 2.0);              /* -1/2!  */
+  return fma(z, q, 1.0);
+}
+
+static void zo_sincos(double x, double *s, double *c) {
+  if (!(fabs(x) <= ZM_TRIG_MAX)) { /* huge, inf or NaN */
+    *s = sin(x);
+    *c = cos(x);
+    return;
+  }
+  /* x = k pi/2 + r, |r| <= pi/4 (about) */
+  double k = rint(x * ZM_2_OVER_PI);
+  double r = fma(-k, ZM_PIO2_1, x);
+  r = fma(-k, ZM_PIO2_2, r);
+  r = fma(-k, ZM_PIO2_3, r);
+  double sr = sin_taylor(r), cr = cos_taylor(r);
+  switch ((int)((int64_t)k & 3)) {
+    case 0: *s = sr; *c = cr; break;
+    case 1: *s = cr; *c = -sr; break;
+    case 2: *s = -sr; *c = -cr; break;
+    default: *s = -cr; *c = sr; break;
+  }
+}
+
+double zo_sin(double x) { double s, c; zo_sincos(x, &s, &c); return s; }
+double zo_cos(double x) { double s, c; zo_sincos(x, &s, &c); return c; }
+
+double zo_exp(double x) {
+  if (x != x) return x;
+  if (x > 710.0) return INFINITY;
+  if (x < -746.0) return 0.0;
+  /* x = k ln2 + r, |r| <= ln2/2; e^x = 2^k e^r */
+  double k = rint(x * ZM_LOG2E);
+  double r = fma(-k, ZM_LN2_1, x);
+  r = fma(-k, ZM_LN2_2, r);
+  double p = 1.0 / 6227020800.0;          /* 1/13! */
+  p = fma(p, r, 1.0 / 479001600.0);       /* 1/12! */
+  p = fma(p, r, 1.0 / 39916800.0);        /* 1/11! */
+  p = fma(p, r, 1.0 / 3628800.0);         /* 1/10! */
+  p = fma(p, r, 1.0 / 362880.0);          /* 1/9!  */
+  p = fma(p, r, 1.0 / 40320.0);           /* 1/8!  */
+  p = fma(p, r, 1.0 / 5040.0);            /* 1/7!  */
+  p = fma(p, r, 1.0 / 720.0);             /* 1/6!  */
+  p = fma(p, r, 1.0 / 120.0);             /* 1/5!  */
+  p = fma(p, r, 1.0 / 24.0);              /* 1/4!  */
+  p = fma(p, r, 1.0 / 6.0);               /* 1/3!  */
+  p = fma(p, r, 0.5);                     /* 1/2!  */
+  p = fma(p, r, 1.0);                     /* 1/1!  */
+  p = fma(p, r, 1.0);                     /* 1/0!  */
+  return ldexp(p, (int)k);
+}
+
+/* ======================================================================== */
 /* Dual numbers a + b*eps with eps^2 = 0 (Sec. III-C).  v = value, t = tangent.*/
 /* ======================================================================== */
 
@@ -89,9 +185,13 @@ static dual d_divk(dual a, double k) { return dd(a.v / k, a.t / k); }
 static dual d_addk(double k, dual a) { return dd(k + a.v, a.t); }
 static dual d_ksub(double k, dual a) { return dd(k - a.v, -a.t); }
 /* cos(a + b eps) = cos a - b sin a eps */
-static dual d_cos(dual a) { return dd(cos(a.v), -(a.t * sin(a.v))); }
+static dual d_cos(dual a) {
+  double sv, cv;
+  zo_sincos(a.v, &sv, &cv);
+  return dd(cv, -(a.t * sv));
+}
 /* exp(a + b eps) = e^a + b e^a eps */
-static dual d_exp(dual a) { double e = exp(a.v); return dd(e, a.t * e); }
+static dual d_exp(dual a) { double e = zo_exp(a.v); return dd(e, a.t * e); }
 /* sqrt(a + b eps) = sqrt a + b / (2 sqrt a) eps */
 static dual d_sqrt(dual a) { double s = sqrt(a.v); return dd(s, a.t / (2.0 * s)); }
 
@@ -404,16 +504,19 @@ int zo_bfgs_update(double *H, const double *s, const double *y, int d) {
   double *u = (double *)malloc(sizeof(double) * (size_t)d);
   for (int i = 0; i < d; ++i) {
     double acc = 0.0;
-    for (int j = 0; j < d; ++j) acc = acc + H[i * d + j] * y[j];
+    for (int j = 0; j < d; ++j) acc = fma(H[i * d + j], y[j], acc);
     u[i] = acc;
   }
   double yu = 0.0;
   for (int i = 0; i < d; ++i) yu = yu + y[i] * u[i];
   double beta = (rho * rho) * yu + rho;
-  for (int i = 0; i < d; ++i)
-    for (int j = 0; j < d; ++j)
-      H[i * d + j] = (H[i * d + j] - rho * (s[i] * u[j] + u[i] * s[j])) +
-                     beta * (s[i] * s[j]);
+  /* row i: H_ij + a_i u_j + e_i s_j with a_i = -rho s_i and
+   * e_i = beta s_i - rho u_i, each element by two fused multiply-adds */
+  for (int i = 0; i < d; ++i) {
+    double a = -rho * s[i];
+    double e = beta * s[i] - rho * u[i];
+    for (int j = 0; j < d; ++j) H[i * d + j] = fma(e, s[j], fma(a, u[j], H[i * d + j]));
+  }
   free(u);
   return 1;
 }
@@ -462,10 +565,10 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
     if (gnorm < pb->grad_tol) { status = ZO_CONVERGED; break; }
     if (k == pb->iter_bfgs) { status = ZO_MAXITER; break; }
 
-    /* search direction p = -H g */
+    /* search direction p = -H g (products accumulated by fused multiply-add) */
     for (int i = 0; i < d; ++i) {
       double acc = 0.0;
-      for (int j = 0; j < d; ++j) acc = acc + H[i * d + j] * g[j];
+      for (int j = 0; j < d; ++j) acc = fma(H[i * d + j], g[j], acc);
       p[i] = -acc;
     }
     double ddir = 0.0;

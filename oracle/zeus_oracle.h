@@ -9,8 +9,9 @@
  * no code, header, constant table or helper with the GPU library: everything
  * here (Philox, dual numbers, objectives, PSO, BFGS) is written separately.
  *
- * Everything is IEEE double, built with -O2 -ffp-contract=off (no fused
- * multiply-add anywhere, no -ffast-math), summations strictly left to right.
+ * Everything is IEEE double, built with -O2 -ffp-contract=off and without
+ * -ffast-math: a multiply-add is fused only where the code calls fma(), and
+ * summations run strictly left to right.
  *
  * Readings of the paper that this oracle fixes (the paper is silent or
  * ambiguous there) are listed next to the code that applies them.
@@ -106,6 +107,12 @@ void zo_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2],
  * (w >> 11) * 2^-53. */
 double zo_uniform(uint64_t seed, uint64_t request_id, uint64_t i, uint64_t t,
                   uint64_t tag, uint64_t j);
+
+/* sin, cos, exp used by the objectives: Cody-Waite reduction and Taylor
+ * series with fused multiply-adds (about one ulp); libm beyond |x| = 2^28. */
+double zo_sin(double x);
+double zo_cos(double x);
+double zo_exp(double x);
 
 /* Objective value (primal evaluation). */
 double zo_f(int objective, const double *x, int dim);

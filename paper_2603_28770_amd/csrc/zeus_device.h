@@ -96,18 +96,111 @@ __device__ __forceinline__ float ksub(float k, float a) { return k - a; }
 template <class T>
 __device__ __forceinline__ dual<T> ksub(T k, dual<T> a) { return {k - a.v, -a.t}; }
 
-__device__ __forceinline__ double dcos(double a) { return cos(a); }
+// ---------------------------------------------------------------------------
+// sin, cos, exp in double: Cody-Waite argument reduction (Cody and Waite,
+// "Software Manual for the Elementary Functions", 1980) and the Taylor series
+// of the reduced argument by Horner's rule with fused multiply-adds (about
+// one ulp).  Every rounding step is explicit, so the value does not depend on
+// the device math library; beyond |x| = 2^28 the library takes over.
+// ---------------------------------------------------------------------------
+namespace zm {
+constexpr double kPio2A = 0x1.921fb54442d18p+0;   // pi/2 = A + B + C
+constexpr double kPio2B = 0x1.1a62633145c07p-54;
+constexpr double kPio2C = -0x1.f1976b7ed8fbcp-110;
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+constexpr double kLn2A = 0x1.62e42fefa39efp-1;    // ln 2 = A + B
+constexpr double kLn2B = 0x1.abc9e3b39803fp-56;
+constexpr double kLog2e = 0x1.71547652b82fep+0;
+constexpr double kTrigMax = 0x1p28;
+
+__device__ __forceinline__ double sin_taylor(double r) {  // |r| <= pi/4, to r^17
+  const double z = r * r;
+  double p = 1.0 / 355687428096000.0;
+  p = __builtin_fma(p, z, -1.0 / 1307674368000.0);
+  p = __builtin_fma(p, z, 1.0 / 6227020800.0);
+  p = __builtin_fma(p, z, -1.0 / 39916800.0);
+  p = __builtin_fma(p, z, 1.0 / 362880.0);
+  p = __builtin_fma(p, z, -1.0 / 5040.0);
+  p = __builtin_fma(p, z, 1.0 / 120.0);
+  p = __builtin_fma(p, z, -1.0 / 6.0);
+  return __builtin_fma(r * z, p, r);
+}
+
+__device__ __forceinline__ double cos_taylor(double r) {  // |r| <= pi/4, to r^16
+  const double z = r * r;
+  double q = 1.0 / 20922789888000.0;
+  q = __builtin_fma(q, z, -1.0 / 87178291200.0);
+  q = __builtin_fma(q, z, 1.0 / 479001600.0);
+  q = __builtin_fma(q, z, -1.0 / 3628800.0);
+  q = __builtin_fma(q, z, 1.0 / 40320.0);
+  q = __builtin_fma(q, z, -1.0 / 720.0);
+  q = __builtin_fma(q, z, 1.0 / 24.0);
+  q = __builtin_fma(q, z, -1.0 / 2.0);
+  return __builtin_fma(z, q, 1.0);
+}
+
+__device__ __forceinline__ void sincos(double x, double &s, double &c) {
+  if (!(__builtin_fabs(x) <= kTrigMax)) {
+    s = ::sin(x);
+    c = ::cos(x);
+    return;
+  }
+  const double k = __builtin_rint(x * kTwoOverPi);  // x = k pi/2 + r
+  double r = __builtin_fma(-k, kPio2A, x);
+  r = __builtin_fma(-k, kPio2B, r);
+  r = __builtin_fma(-k, kPio2C, r);
+  const double sr = sin_taylor(r), cr = cos_taylor(r);
+  const int q = (int)((long long)k & 3);
+  s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
+  c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
+}
+
+__device__ __forceinline__ double exp(double x) {
+  if (x != x) return x;
+  if (x > 710.0) return __builtin_huge_val();
+  if (x < -746.0) return 0.0;
+  const double k = __builtin_rint(x * kLog2e);  // x = k ln2 + r
+  double r = __builtin_fma(-k, kLn2A, x);
+  r = __builtin_fma(-k, kLn2B, r);
+  double p = 1.0 / 6227020800.0;
+  p = __builtin_fma(p, r, 1.0 / 479001600.0);
+  p = __builtin_fma(p, r, 1.0 / 39916800.0);
+  p = __builtin_fma(p, r, 1.0 / 3628800.0);
+  p = __builtin_fma(p, r, 1.0 / 362880.0);
+  p = __builtin_fma(p, r, 1.0 / 40320.0);
+  p = __builtin_fma(p, r, 1.0 / 5040.0);
+  p = __builtin_fma(p, r, 1.0 / 720.0);
+  p = __builtin_fma(p, r, 1.0 / 120.0);
+  p = __builtin_fma(p, r, 1.0 / 24.0);
+  p = __builtin_fma(p, r, 1.0 / 6.0);
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)k);
+}
+}  // namespace zm
+
+__device__ __forceinline__ double dcos(double a) {
+  double s, c;
+  zm::sincos(a, s, c);
+  return c;
+}
 __device__ __forceinline__ float dcos(float a) { return cosf(a); }
-__device__ __forceinline__ double dsin(double a) { return sin(a); }
 __device__ __forceinline__ float dsin(float a) { return sinf(a); }
-__device__ __forceinline__ double dexp(double a) { return exp(a); }
+__device__ __forceinline__ double dexp(double a) { return zm::exp(a); }
 __device__ __forceinline__ float dexp(float a) { return expf(a); }
 __device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ float dsqrt(float a) { return sqrtf(a); }
 
 // cos(a + b eps) = cos a - b sin a eps
-template <class T>
-__device__ __forceinline__ dual<T> dcos(dual<T> a) { return {dcos(a.v), -(a.t * dsin(a.v))}; }
+__device__ __forceinline__ dual<double> dcos(dual<double> a) {
+  double s, c;
+  zm::sincos(a.v, s, c);
+  return {c, -(a.t * s)};
+}
+__device__ __forceinline__ dual<float> dcos(dual<float> a) {
+  return {cosf(a.v), -(a.t * sinf(a.v))};
+}
 // exp(a + b eps) = e^a + b e^a eps
 template <class T>
 __device__ __forceinline__ dual<T> dexp(dual<T> a) {
