@@ -93,40 +93,58 @@ struct DeviceGuard {
 
 namespace zeus {
 
-size_t workspace_bytes(int64_t n, int dim) {
-  const int64_t blocks = (n + kPsoBlock - 1) / kPsoBlock;
-  size_t b = 0;
-  b += align_up(sizeof(uint32_t));                 // pso counter
-  b += align_up(sizeof(uint64_t));                 // work queue
-  b += align_up(sizeof(PsoBest));                  // global best
-  b += align_up(sizeof(double) * blocks);          // partial keys
-  b += align_up(sizeof(int64_t) * blocks);         // partial indices
-  b += align_up(sizeof(double) * dim);             // gx
-  b += 3 * align_up(sizeof(double) * (size_t)n * dim);  // x, v, px
-  b += align_up(sizeof(double) * (size_t)n);       // pf
-  return b;
+namespace {
+struct Layout {
+  size_t queue, best, gx, best_store, gx_store, part_key, part_f, part_idx, part_x, x, v, px,
+      pf, total;
+};
+Layout layout(int64_t n, int dim) {
+  const size_t P = (size_t)pso_blocks(n, dim), N = (size_t)n, D = (size_t)dim;
+  Layout l;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  l.queue = take(sizeof(uint64_t));
+  l.best = take(sizeof(PsoBest));
+  l.gx = take(sizeof(double) * D);
+  l.best_store = take(2 * sizeof(PsoBest));
+  l.gx_store = take(2 * sizeof(double) * D);
+  l.part_key = take(2 * sizeof(double) * P);
+  l.part_f = take(2 * sizeof(double) * P);
+  l.part_idx = take(2 * sizeof(int64_t) * P);
+  l.part_x = take(2 * sizeof(double) * P * D);
+  l.x = take(sizeof(double) * N * D);
+  l.v = take(sizeof(double) * N * D);
+  l.px = take(sizeof(double) * N * D);
+  l.pf = take(sizeof(double) * N);
+  l.total = o;
+  return l;
 }
+}  // namespace
+
+size_t workspace_bytes(int64_t n, int dim) { return layout(n, dim).total; }
 
 Workspace carve_workspace(void *base, int64_t n, int dim) {
-  const int64_t blocks = (n + kPsoBlock - 1) / kPsoBlock;
+  const Layout l = layout(n, dim);
   char *p = static_cast<char *>(base);
-  auto take = [&](size_t bytes) {
-    char *q = p;
-    p += align_up(bytes);
-    return q;
-  };
   Workspace w;
-  w.pso_counter = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t)));
-  w.queue = reinterpret_cast<uint64_t *>(take(sizeof(uint64_t)));
-  w.best = reinterpret_cast<PsoBest *>(take(sizeof(PsoBest)));
-  w.partial_key = reinterpret_cast<double *>(take(sizeof(double) * blocks));
-  w.partial_idx = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * blocks));
-  w.gx = reinterpret_cast<double *>(take(sizeof(double) * dim));
-  w.x = reinterpret_cast<double *>(take(sizeof(double) * (size_t)n * dim));
-  w.v = reinterpret_cast<double *>(take(sizeof(double) * (size_t)n * dim));
-  w.px = reinterpret_cast<double *>(take(sizeof(double) * (size_t)n * dim));
-  w.pf = reinterpret_cast<double *>(take(sizeof(double) * (size_t)n));
-  w.pso_blocks = (int)blocks;
+  w.queue = reinterpret_cast<uint64_t *>(p + l.queue);
+  w.best = reinterpret_cast<PsoBest *>(p + l.best);
+  w.gx = reinterpret_cast<double *>(p + l.gx);
+  w.best_store = reinterpret_cast<PsoBest *>(p + l.best_store);
+  w.gx_store = reinterpret_cast<double *>(p + l.gx_store);
+  w.part_key = reinterpret_cast<double *>(p + l.part_key);
+  w.part_f = reinterpret_cast<double *>(p + l.part_f);
+  w.part_idx = reinterpret_cast<int64_t *>(p + l.part_idx);
+  w.part_x = reinterpret_cast<double *>(p + l.part_x);
+  w.x = reinterpret_cast<double *>(p + l.x);
+  w.v = reinterpret_cast<double *>(p + l.v);
+  w.px = reinterpret_cast<double *>(p + l.px);
+  w.pf = reinterpret_cast<double *>(p + l.pf);
+  w.pso_blocks = pso_blocks(n, dim);
   return w;
 }
 
@@ -204,6 +222,7 @@ zeus_err enqueue_solve(zeus_context *ctx, const zeus_problem *pb, void *ws_base,
   if ((e = zeus::launch_pso_init(L)) != hipSuccess) return hip_fail(e, "swarm init launch");
   for (int t = 1; t <= pb->iter_pso; ++t)
     if ((e = zeus::launch_pso_step(L, t)) != hipSuccess) return hip_fail(e, "swarm update launch");
+  if ((e = zeus::launch_pso_finish(L)) != hipSuccess) return hip_fail(e, "swarm best launch");
   if (prof) (void)hipEventRecord(pend.ev[1], stream);
   if ((e = zeus::launch_bfgs(L)) != hipSuccess) return hip_fail(e, "BFGS launch");
   if (prof) (void)hipEventRecord(pend.ev[2], stream);
@@ -222,7 +241,7 @@ zeus_err enqueue_solve(zeus_context *ctx, const zeus_problem *pb, void *ws_base,
       return hip_fail(e, "hipMemcpyAsync");
   if (prof) {
     ctx->pending.push_back(pend);
-    ctx->prof.pso_launches += 2 + pb->iter_pso;
+    ctx->prof.pso_launches += 3 + pb->iter_pso;
     ctx->prof.bfgs_launches += 1;
     ctx->prof.reduce_launches += 1;
   }

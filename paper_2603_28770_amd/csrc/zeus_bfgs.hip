@@ -21,7 +21,10 @@
 // The loop is flattened so that every trip does one gradient evaluation and
 // one line search for every group of a wave, whatever iteration each group's
 // start is in.
+#include <cstdlib>
+
 #include "zeus_device.h"
+#include "zeus_group.h"
 #include "zeus_internal.h"
 
 namespace zeus {
@@ -42,38 +45,73 @@ struct BfgsArgs {
   int32_t *out_status;
   int32_t *out_ls;    // nullable
   double *trace;      // nullable, [n][trace_len][d]
+  int trials_per_round;  // R, a power of two <= G
 };
 
-template <int G>
+// Per-group LDS slice.  Every vector is zero beyond the dimension, so the
+// loops below run over whole chunks without per-element tests.
 struct GroupShm {
-  double xs[G];  // iterate under evaluation (x, then x + alpha p)
-  double ps[G];  // search direction
-  double gs[G];  // gradient at the current iterate
-  double ys[G];  // y = g_new - g
-  double ss[G];  // s = x_new - x
-  double us[G];  // u = H y
+  double *xs;  // [G] iterate under evaluation (x, then x_new)
+  double *ps;  // [G] search direction
+  double *gs;  // [G] gradient at the current iterate
+  double *ys;  // [G] y = g_new - g
+  double *ss;  // [G] s = x_new - x
+  double *us;  // [G] u = H y
+  double *tg;  // [K][G] term values of a gradient evaluation
+  double *tt;  // [K][R][mp] term values of the trials of a line-search round
 };
 
-// Orders this wave's LDS traffic: LDS operations of one wave complete in
-// issue order, so only the compiler needs to be kept from moving them.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+// Doubles per group slice (mp = m rounded up to the chunk size).
+__device__ __host__ __forceinline__ int group_stride(int G, int K, int R, int mp) {
+  return 6 * G + K * G + K * R * mp;
 }
+
+// Step lengths alpha_t = shrink^t of the first kTabTrials trials, each the
+// product of the previous one and shrink, as Alg. 6 forms them.
+constexpr int kTabTrials = 64;
 
 template <int OBJ, int G>
 __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
+  using E = Elem<OBJ>;
   constexpr int S = 64 / G;  // groups per wave
-  __shared__ GroupShm<G> shm[kBfgsBlock / 64][S];
-  const int lane = threadIdx.x & 63;
-  const int grp = lane / G;
-  const int j = lane & (G - 1);
-  GroupShm<G> &sh = shm[threadIdx.x >> 6][grp];
+  extern __shared__ double smem[];
+  const GroupLanes<G> L;
+  const int j = L.j;
   const int d = a.d;
   const bool own = j < d;
-  const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
+  const int m = E::terms(d);
+  const int dp = Chunk<G>::padded(d), mp = Chunk<G>::padded(m);
+  const int R = a.trials_per_round;      // line-search trials per round
+  const int tp = G / R;                  // lanes per trial
+  const int trial_slot = j / tp, term_slot = j % tp;
+  uint64_t leaders = 0;                  // bit r*tp of every trial r of a round
+  for (int r = 0; r < R; ++r) leaders |= 1ull << (r * tp);
 
-  double h[G];  // row j of H
+  __shared__ double alpha_tab[kTabTrials];
+  const int stride = group_stride(G, E::K, R, mp);
+  for (int i = threadIdx.x; i < stride * (kBfgsBlock / G); i += kBfgsBlock) smem[i] = 0.0;
+  if (threadIdx.x == 0) {
+    double al = 1.0;
+    for (int t = 0; t < kTabTrials; ++t) {
+      alpha_tab[t] = al;
+      al = al * a.shrink;
+    }
+  }
+  __syncthreads();
+  GroupShm sh;
+  {
+    double *base = smem + (size_t)((threadIdx.x >> 6) * S + L.grp) * stride;
+    sh.xs = base;
+    sh.ps = base + G;
+    sh.gs = base + 2 * G;
+    sh.ys = base + 3 * G;
+    sh.ss = base + 4 * G;
+    sh.us = base + 5 * G;
+    sh.tg = base + 6 * G;
+    sh.tt = base + 6 * G + E::K * G;
+  }
+
+  double h[G];  // row j of H; h[c] = 0 for c >= d except h[j] = 1 when j >= d
   double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
   int64_t idx = -1;
   int k = 0, ls_trials = 0;
@@ -84,7 +122,7 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     if (idx < 0) {
       unsigned long long got = 0;
       if (j == 0) got = atomicAdd((unsigned long long *)a.queue, 1ull);
-      got = __shfl(got, grp * G, 64);
+      got = __shfl(got, L.grp * G, 64);
       if (got >= (unsigned long long)a.n) break;
       idx = (int64_t)got;
       xj = own ? a.x0[idx * d + j] : 0.0;  // x <- swarm[i]
@@ -97,10 +135,9 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     }
     wave_sync();
 
-    // -- gradient at xs: lane j takes the dual pass seeded with e_j ---------
-    const dual<double> r = Obj<OBJ>::template eval<dual<double>>(
-        d, [&](int i) { return dual<double>{sh.xs[i], i == j ? 1.0 : 0.0}; });
-    const double fn = r.v, gn = own ? r.t : 0.0;
+    // -- value and gradient at xs (dual numbers, one direction per lane) ----
+    double gn;
+    const double fn = group_value_grad<OBJ, G>(L, d, sh.xs, sh.tg, &gn);
 
     // -- after a step: s, y and the rank-2 inverse-Hessian update -----------
     if (!fresh) {
@@ -108,25 +145,27 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
       sh.ys[j] = yj;
       sh.ss[j] = sj;
       wave_sync();
-      double sy = 0.0;
-      for (int i = 0; i < d; ++i) sy = sy + sh.ys[i] * sh.ss[i];
+      const double sy = dot_ordered<G>(sh.ys, sh.ss, dp);
       if (sy > 0.0) {  // curvature condition; skip the update otherwise
         const double rho = 1.0 / sy;
         double uj = 0.0;
 #pragma unroll
-        for (int c = 0; c < G; ++c)
-          if (c < d) uj = __builtin_fma(h[c], sh.ys[c], uj);
+        for (int c = 0; c < G; ++c) uj = __builtin_fma(h[c], sh.ys[c], uj);
         sh.us[j] = own ? uj : 0.0;
         wave_sync();
-        double yu = 0.0;
-        for (int i = 0; i < d; ++i) yu = yu + sh.ys[i] * sh.us[i];
+        const double yu = dot_ordered<G>(sh.ys, sh.us, dp);
         const double beta = (rho * rho) * yu + rho;
         // H+ = H - rho (s u' + u s') + beta s s'   (row j, u = H y)
         const double au = -rho * sj;
         const double as = beta * sj - rho * uj;
 #pragma unroll
-        for (int c = 0; c < G; ++c)
-          if (c < d) h[c] = __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], h[c]));
+        for (int c = 0; c < G; ++c) h[c] = __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], h[c]));
+        if (!__builtin_isfinite(au) || !__builtin_isfinite(as)) {
+          // inf * 0 would have reached the padding: restore it
+#pragma unroll
+          for (int c = 0; c < G; ++c)
+            if (c >= d) h[c] = (c == j) ? 1.0 : 0.0;
+        }
       }
       xj = own ? sh.xs[j] : 0.0;  // x <- x_new
       ++k;
@@ -140,9 +179,8 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
 
     // -- termination: non-finite, ||g|| < Theta, budget ---------------------
     const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
-    const bool any_bad = (__ballot(bad) & gmask) != 0ull;
-    double gg = 0.0;
-    for (int i = 0; i < d; ++i) gg = gg + sh.gs[i] * sh.gs[i];
+    const bool any_bad = L.ballot(bad) != 0ull;
+    const double gg = dot_ordered<G>(sh.gs, sh.gs, dp);
     int status = -1;
     if (any_bad)
       status = ZEUS_ST_NONFINITE;
@@ -168,50 +206,69 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     // -- search direction p = -H g (reset to -g if not a descent direction) -
     double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < G; ++c)
-      if (c < d) acc = __builtin_fma(h[c], sh.gs[c], acc);
+    for (int c = 0; c < G; ++c) acc = __builtin_fma(h[c], sh.gs[c], acc);
     pj = own ? -acc : 0.0;
     sh.ps[j] = pj;
     wave_sync();
-    double ddir = 0.0;
-    for (int i = 0; i < d; ++i) ddir = ddir + sh.gs[i] * sh.ps[i];
+    double ddir = dot_ordered<G>(sh.gs, sh.ps, dp);
     if (!(ddir < 0.0)) {
 #pragma unroll
       for (int c = 0; c < G; ++c) h[c] = (c == j) ? 1.0 : 0.0;
       pj = own ? -gj : 0.0;
       sh.ps[j] = pj;
       wave_sync();
-      ddir = 0.0;
-      for (int i = 0; i < d; ++i) ddir = ddir + sh.gs[i] * sh.ps[i];
+      ddir = dot_ordered<G>(sh.gs, sh.ps, dp);
     }
 
-    // -- Armijo backtracking, G trials per round ----------------------------
+    // -- Armijo backtracking (Alg. 6) ---------------------------------------
+    // A round evaluates R consecutive trials of the sequence at once, each
+    // spread over tp = G / R lanes (lane c of a trial takes terms c, c + tp,
+    // ...); the first trial that passes is the step Alg. 6 returns.
     int taken = -1;
-    for (int base = 0; base < a.iter_ls; base += G) {
-      const int t = base + j;
-      bool ok = false;
-      if (t < a.iter_ls) {
-        double alpha = 1.0;
-        for (int q = 0; q < t; ++q) alpha = alpha * a.shrink;
-        const double ft = Obj<OBJ>::template eval<double>(
-            d, [&](int i) { return sh.xs[i] + alpha * sh.ps[i]; });
-        ok = ft <= f + (a.armijo_c * alpha) * ddir;
+    for (int base = 0; base < a.iter_ls; base += R) {
+      const int t = base + trial_slot;
+      double alpha;
+      if (t < kTabTrials) {
+        alpha = alpha_tab[t];
+      } else {
+        alpha = alpha_tab[kTabTrials - 1];
+        for (int q = kTabTrials - 1; q < t; ++q) alpha = alpha * a.shrink;
       }
-      const uint64_t m = (__ballot(ok) & gmask) >> (grp * G);
-      if (m != 0ull) {
-        taken = base + (__ffsll((unsigned long long)m) - 1);
+      double *tvr = sh.tt + trial_slot * mp;
+      for (int i = term_slot; i < m; i += tp) {
+        double w[E::W], out[E::K];
+#pragma unroll
+        for (int q = 0; q < E::W; ++q) w[q] = sh.xs[i + q] + alpha * sh.ps[i + q];
+        E::template term<double>(w, out);
+#pragma unroll
+        for (int kk = 0; kk < E::K; ++kk) tvr[kk * R * mp + i] = out[kk];
+      }
+      wave_sync();
+      double sums[E::K];
+#pragma unroll
+      for (int kk = 0; kk < E::K; ++kk) sums[kk] = sum_ordered<G>(tvr + kk * R * mp, mp);
+      const double ft = E::template outer<double>(d, sums);
+      const bool ok = t < a.iter_ls && ft <= f + (a.armijo_c * alpha) * ddir;
+      const uint64_t hit = L.ballot(ok) & leaders;
+      wave_sync();  // every lane has read tv before it is written again
+      if (hit != 0ull) {
+        taken = base + (__ffsll((unsigned long long)hit) - 1) / tp;
         break;
       }
     }
     const int nshrink = taken >= 0 ? taken : a.iter_ls;
     ls_trials += taken >= 0 ? taken + 1 : a.iter_ls;
-    double alpha = 1.0;
-    for (int q = 0; q < nshrink; ++q) alpha = alpha * a.shrink;
+    double alpha;
+    if (nshrink < kTabTrials) {
+      alpha = alpha_tab[nshrink];
+    } else {
+      alpha = alpha_tab[kTabTrials - 1];
+      for (int q = kTabTrials - 1; q < nshrink; ++q) alpha = alpha * a.shrink;
+    }
 
     // -- step ----------------------------------------------------------------
     const double xnew = xj + alpha * pj;
     sj = own ? xnew - xj : 0.0;
-    wave_sync();
     sh.xs[j] = own ? xnew : 0.0;
   }
 }
@@ -291,13 +348,22 @@ __global__ __launch_bounds__(kSumBlock) void summary_kernel(int64_t n, const dou
 
 template <int OBJ, int G>
 hipError_t launch_g(const BfgsArgs &a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((bfgs_kernel<OBJ, G>), dim3(blocks), dim3(kBfgsBlock), 0, s, a);
+  using E = Elem<OBJ>;
+  const int m = E::terms(a.d);
+  const int R = a.trials_per_round;
+  constexpr int CH = G < 8 ? G : 8;
+  const int stride = group_stride(G, E::K, R, (m + CH - 1) / CH * CH);
+  const size_t lds = sizeof(double) * (size_t)stride * (kBfgsBlock / 64) * (64 / G);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((bfgs_kernel<OBJ, G>), dim3(blocks), dim3(kBfgsBlock), lds, s, a);
   return hipGetLastError();
 }
 
 template <int OBJ>
 hipError_t launch_obj(const BfgsArgs &a, int G, int blocks, hipStream_t s) {
   switch (G) {
+    case 2: return launch_g<OBJ, 2>(a, blocks, s);
+    case 4: return launch_g<OBJ, 4>(a, blocks, s);
     case 8: return launch_g<OBJ, 8>(a, blocks, s);
     case 16: return launch_g<OBJ, 16>(a, blocks, s);
     case 32: return launch_g<OBJ, 32>(a, blocks, s);
@@ -308,10 +374,33 @@ hipError_t launch_obj(const BfgsArgs &a, int G, int blocks, hipStream_t s) {
 
 }  // namespace
 
+// Lanes per start: the smallest power of two >= dim, at least kMinLanes
+// (more lanes per start than coordinates buy more line-search trials per
+// round; ZEUS_MIN_LANES overrides the floor for experiments).
 int group_lanes(int dim) {
-  int g = 8;
+  static int floor_lanes = [] {
+    const char *e = getenv("ZEUS_MIN_LANES");
+    int v = e ? atoi(e) : 4;
+    int g = 2;
+    while (g < v && g < 64) g <<= 1;
+    return g;
+  }();
+  int g = floor_lanes;
   while (g < dim) g <<= 1;
   return g;
+}
+
+// Line-search trials evaluated per round (a power of two <= G; default 4,
+// ZEUS_LS_TRIALS overrides it for experiments).
+int trials_per_round(int G) {
+  static int want = [] {
+    const char *e = getenv("ZEUS_LS_TRIALS");
+    int v = e ? atoi(e) : 4;
+    int r = 1;
+    while (r < v && r < 64) r <<= 1;
+    return r;
+  }();
+  return want < G ? want : G;
 }
 
 hipError_t launch_bfgs(const Launch &L) {
@@ -335,6 +424,7 @@ hipError_t launch_bfgs(const Launch &L) {
   a.trace = a.trace_len > 0 ? L.out->trace : nullptr;
   const int G = group_lanes(p.dim);
   if (G > kMaxDim) return hipErrorInvalidValue;
+  a.trials_per_round = trials_per_round(G);
   const int64_t starts_per_block = (int64_t)(kBfgsBlock / G);
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -350,7 +440,7 @@ hipError_t launch_bfgs(const Launch &L) {
     case kRastrigin: return launch_obj<kRastrigin>(a, G, blocks, L.stream);
     case kAckley: return launch_obj<kAckley>(a, G, blocks, L.stream);
     case kStyblinskiTang: return launch_obj<kStyblinskiTang>(a, G, blocks, L.stream);
-    case kGoldsteinPrice: return launch_g<kGoldsteinPrice, 8>(a, blocks, L.stream);
+    case kGoldsteinPrice: return launch_obj<kGoldsteinPrice>(a, G, blocks, L.stream);
     case kSphere: return launch_obj<kSphere>(a, G, blocks, L.stream);
     case kQuartic: return launch_obj<kQuartic>(a, G, blocks, L.stream);
     default: return hipErrorInvalidValue;

@@ -45,6 +45,11 @@ __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   return u64x4{{c0, c1, c2, c3}};
 }
 
+// Word q (0..3) of a block without indexing a register array at run time.
+__device__ __forceinline__ uint64_t word(const u64x4 &b, int q) {
+  return q == 0 ? b.w[0] : q == 1 ? b.w[1] : q == 2 ? b.w[2] : b.w[3];
+}
+
 // 64 random bits -> double in [0, 1): top 53 bits times 2^-53 (exact).
 __device__ __forceinline__ double u01(uint64_t w) {
   return static_cast<double>(w >> 11) * (1.0 / 9007199254740992.0);
@@ -229,8 +234,20 @@ template <>
 __device__ __forceinline__ dual<float> make_const<dual<float>>(float c) { return {c, 0.0f}; }
 
 // ---------------------------------------------------------------------------
-// Objectives (Sec. V-B; Styblinski-Tang; sphere and quartic for tests).
-// eval<N>(d, x) with x(i) returning coordinate i as number type N.
+// Objectives (Sec. V-B; Styblinski-Tang; sphere and quartic for tests), in
+// element form: every objective here is partially separable,
+//     f(x) = outer(S_0, ..., S_{K-1}),   S_k = sum_{i<m} phi_k(x_i, .., x_{i+W-1}),
+// with m terms of window W.  A term is written once over a number type N
+// (double, float or their dual numbers), so the same code gives values and,
+// seeded with a unit tangent, directional derivatives (Sec. III-C).
+//
+// The kernels evaluate the terms in parallel (one lane per term) and then add
+// the term values up in index order, so a value is the same sum, operation for
+// operation, as a left-to-right evaluation of the whole function.  For the
+// gradient, lane j evaluates on dual numbers seeded with e_j only the (at most
+// W) terms whose window contains x_j: every other term of Alg. 5's pass j has a
+// zero tangent, and adding exact zeros changes no nonzero sum, so lane j gets
+// the same tangent as the full pass j.
 // ---------------------------------------------------------------------------
 enum Objective : int {
   kRosenbrock = 0,
@@ -243,59 +260,58 @@ enum Objective : int {
 };
 
 template <int OBJ>
-struct Obj;
+struct Elem;
 
 // sum_{i<d-1} (1 - x_i)^2 + 100 (x_{i+1} - x_i^2)^2
 template <>
-struct Obj<kRosenbrock> {
-  template <class N, class X>
-  __device__ __forceinline__ static N eval(int d, X x) {
+struct Elem<kRosenbrock> {
+  static constexpr int K = 1, W = 2;
+  __host__ __device__ __forceinline__ static int terms(int d) { return d - 1; }
+  template <class N>
+  __device__ __forceinline__ static void term(const N *w, N *out) {
     using S = typename scalar_of<N>::type;
-    N s = make_const<N>(S(0));
-    N xi = x(0);
-    for (int i = 0; i + 1 < d; ++i) {
-      const N xn = x(i + 1);
-      const N a = ksub(S(1), xi);
-      const N b = xn - xi * xi;
-      const N term = a * a + scale(S(100), b * b);
-      s = s + term;
-      xi = xn;
-    }
-    return s;
+    const N a = ksub(S(1), w[0]);
+    const N b = w[1] - w[0] * w[0];
+    out[0] = a * a + scale(S(100), b * b);
   }
+  template <class N>
+  __device__ __forceinline__ static N outer(int, const N *s) { return s[0]; }
 };
 
 // 10 d + sum (x_i^2 - 10 cos(2 pi x_i))
 template <>
-struct Obj<kRastrigin> {
-  template <class N, class X>
-  __device__ __forceinline__ static N eval(int d, X x) {
+struct Elem<kRastrigin> {
+  static constexpr int K = 1, W = 1;
+  __host__ __device__ __forceinline__ static int terms(int d) { return d; }
+  template <class N>
+  __device__ __forceinline__ static void term(const N *w, N *out) {
     using S = typename scalar_of<N>::type;
-    N s = make_const<N>(S(0));
-    for (int i = 0; i < d; ++i) {
-      const N xi = x(i);
-      const N c = dcos(scale(S(6.283185307179586), xi));
-      const N term = xi * xi - scale(S(10), c);
-      s = s + term;
-    }
-    return addk(S(10) * S(d), s);
+    const N c = dcos(scale(S(6.283185307179586), w[0]));
+    out[0] = w[0] * w[0] - scale(S(10), c);
+  }
+  template <class N>
+  __device__ __forceinline__ static N outer(int d, const N *s) {
+    using S = typename scalar_of<N>::type;
+    return addk(S(10) * S(d), s[0]);
   }
 };
 
 // -20 exp(-0.2 sqrt(sum x^2 / d)) - exp(sum cos(2 pi x) / d) + 20 + e
 template <>
-struct Obj<kAckley> {
-  template <class N, class X>
-  __device__ __forceinline__ static N eval(int d, X x) {
+struct Elem<kAckley> {
+  static constexpr int K = 2, W = 1;
+  __host__ __device__ __forceinline__ static int terms(int d) { return d; }
+  template <class N>
+  __device__ __forceinline__ static void term(const N *w, N *out) {
     using S = typename scalar_of<N>::type;
-    N s1 = make_const<N>(S(0)), s2 = make_const<N>(S(0));
-    for (int i = 0; i < d; ++i) {
-      const N xi = x(i);
-      s1 = s1 + xi * xi;
-      s2 = s2 + dcos(scale(S(6.283185307179586), xi));
-    }
-    const N a = scale(S(-20), dexp(scale(S(-0.2), dsqrt(divk(s1, S(d))))));
-    const N b = dexp(divk(s2, S(d)));
+    out[0] = w[0] * w[0];
+    out[1] = dcos(scale(S(6.283185307179586), w[0]));
+  }
+  template <class N>
+  __device__ __forceinline__ static N outer(int d, const N *s) {
+    using S = typename scalar_of<N>::type;
+    const N a = scale(S(-20), dexp(scale(S(-0.2), dsqrt(divk(s[0], S(d))))));
+    const N b = dexp(divk(s[1], S(d)));
     N r = a - b;
     r = addk(S(20), r);
     r = addk(S(2.718281828459045), r);
@@ -305,29 +321,32 @@ struct Obj<kAckley> {
 
 // 0.5 sum (x^4 - 16 x^2 + 5 x)
 template <>
-struct Obj<kStyblinskiTang> {
-  template <class N, class X>
-  __device__ __forceinline__ static N eval(int d, X x) {
+struct Elem<kStyblinskiTang> {
+  static constexpr int K = 1, W = 1;
+  __host__ __device__ __forceinline__ static int terms(int d) { return d; }
+  template <class N>
+  __device__ __forceinline__ static void term(const N *w, N *out) {
     using S = typename scalar_of<N>::type;
-    N s = make_const<N>(S(0));
-    for (int i = 0; i < d; ++i) {
-      const N xi = x(i);
-      const N x2 = xi * xi;
-      const N x4 = x2 * x2;
-      const N term = (x4 - scale(S(16), x2)) + scale(S(5), xi);
-      s = s + term;
-    }
-    return scale(S(0.5), s);
+    const N x2 = w[0] * w[0];
+    const N x4 = x2 * x2;
+    out[0] = (x4 - scale(S(16), x2)) + scale(S(5), w[0]);
+  }
+  template <class N>
+  __device__ __forceinline__ static N outer(int, const N *s) {
+    using S = typename scalar_of<N>::type;
+    return scale(S(0.5), s[0]);
   }
 };
 
-// Goldstein-Price, d = 2
+// Goldstein-Price, d = 2: one term over the whole window
 template <>
-struct Obj<kGoldsteinPrice> {
-  template <class N, class X>
-  __device__ __forceinline__ static N eval(int, X x) {
+struct Elem<kGoldsteinPrice> {
+  static constexpr int K = 1, W = 2;
+  __host__ __device__ __forceinline__ static int terms(int) { return 1; }
+  template <class N>
+  __device__ __forceinline__ static void term(const N *w, N *out) {
     using S = typename scalar_of<N>::type;
-    const N x1 = x(0), x2 = x(1);
+    const N x1 = w[0], x2 = w[1];
     const N a = addk(S(1), x1 + x2);
     N pa = ksub(S(19), scale(S(14), x1));
     pa = pa + scale(S(3), x1 * x1);
@@ -342,39 +361,38 @@ struct Obj<kGoldsteinPrice> {
     pb = pb - scale(S(36), x1 * x2);
     pb = pb + scale(S(27), x2 * x2);
     const N B = addk(S(30), (b * b) * pb);
-    return A * B;
+    out[0] = A * B;
   }
+  template <class N>
+  __device__ __forceinline__ static N outer(int, const N *s) { return s[0]; }
 };
 
 // 0.5 sum x^2
 template <>
-struct Obj<kSphere> {
-  template <class N, class X>
-  __device__ __forceinline__ static N eval(int d, X x) {
+struct Elem<kSphere> {
+  static constexpr int K = 1, W = 1;
+  __host__ __device__ __forceinline__ static int terms(int d) { return d; }
+  template <class N>
+  __device__ __forceinline__ static void term(const N *w, N *out) { out[0] = w[0] * w[0]; }
+  template <class N>
+  __device__ __forceinline__ static N outer(int, const N *s) {
     using S = typename scalar_of<N>::type;
-    N s = make_const<N>(S(0));
-    for (int i = 0; i < d; ++i) {
-      const N xi = x(i);
-      s = s + xi * xi;
-    }
-    return scale(S(0.5), s);
+    return scale(S(0.5), s[0]);
   }
 };
 
 // sum x^4
 template <>
-struct Obj<kQuartic> {
-  template <class N, class X>
-  __device__ __forceinline__ static N eval(int d, X x) {
-    using S = typename scalar_of<N>::type;
-    N s = make_const<N>(S(0));
-    for (int i = 0; i < d; ++i) {
-      const N xi = x(i);
-      const N x2 = xi * xi;
-      s = s + x2 * x2;
-    }
-    return s;
+struct Elem<kQuartic> {
+  static constexpr int K = 1, W = 1;
+  __host__ __device__ __forceinline__ static int terms(int d) { return d; }
+  template <class N>
+  __device__ __forceinline__ static void term(const N *w, N *out) {
+    const N x2 = w[0] * w[0];
+    out[0] = x2 * x2;
   }
+  template <class N>
+  __device__ __forceinline__ static N outer(int, const N *s) { return s[0]; }
 };
 
 // NaN ranks as +infinity in every best-of comparison.

@@ -16,23 +16,33 @@ constexpr int kMaxDim = 64;
 constexpr int kPsoBlock = 256;
 constexpr int kBfgsBlock = 256;
 
-// Global best of the swarm, kept on the device.
+// Most blocks a swarm launch uses (the grid strides over the particles; every
+// block re-reduces the previous launch's P block results, so P stays small).
+constexpr int kPsoMaxBlocks = 512;
+
+// A swarm best, kept on the device.
 struct PsoBest {
   double f;      // value as computed (may be NaN if every value is NaN)
   int64_t idx;   // particle index
 };
 
 // Device workspace carved out of one allocation (all offsets 256-aligned).
+// The swarm kernels exchange their block results through double-buffered
+// slots: sweep t writes slot t & 1, sweep t+1 reads it after the kernel
+// boundary, so no launch needs a device-wide fence.
 struct Workspace {
-  uint32_t *pso_counter;   // blocks finished in the current PSO launch
   uint64_t *queue;         // next unclaimed BFGS start
-  PsoBest *best;           // swarm global best
-  double *partial_key;     // [pso_blocks] per-block best keys
-  int64_t *partial_idx;    // [pso_blocks]
-  double *gx;              // [dim] global-best position
+  PsoBest *best;           // swarm best after the last sweep
+  double *gx;              // [dim] its position
+  PsoBest *best_store;     // [2] swarm best after sweep t, slot t & 1
+  double *gx_store;        // [2][dim]
+  double *part_key;        // [2][P] each block's best rank key of sweep t
+  double *part_f;          // [2][P] its value
+  int64_t *part_idx;       // [2][P] its particle
+  double *part_x;          // [2][P][dim] its personal-best position
   double *x, *v, *px;      // [n][dim]
   double *pf;              // [n]
-  int pso_blocks;
+  int pso_blocks;          // P
 };
 
 size_t workspace_bytes(int64_t n, int dim);
@@ -49,11 +59,14 @@ struct Launch {
 hipError_t launch_ws_init(const Launch &L);
 hipError_t launch_pso_init(const Launch &L);
 hipError_t launch_pso_step(const Launch &L, int t);
-hipError_t launch_pso_export(const Launch &L);
+hipError_t launch_pso_finish(const Launch &L);
 hipError_t launch_bfgs(const Launch &L);
 hipError_t launch_summary(const Launch &L);
 
-// Lanes per start chosen for a dimension (power of two >= dim, at least 8).
+// Lanes per start of the BFGS kernel for a dimension (power of two >= dim).
 int group_lanes(int dim);
+// Lanes per particle of the swarm kernels, and their grid size.
+int pso_group_lanes(int dim);
+int pso_blocks(int64_t n, int dim);
 
 }  // namespace zeus

@@ -1,16 +1,25 @@
 // zeus_pso.hip -- swarm phase on gfx950: initialisation (Alg. 2 / Alg. 8) and
-// synchronous updates (Alg. 3 / Alg. 9), one thread per particle.
+// synchronous updates (Alg. 3 / Alg. 9).
 //
-// The paper's kernels take the global best with an atomicMin on the value
-// followed by an unsynchronised copy of the position, which lets two winners
-// interleave their copies.  Here every launch ends with a deterministic
-// reduction instead: each block reduces (value, index) pairs to its best, and
-// the last block to finish (an agent-scope counter) reduces the block results
-// in index order and refreshes the global best once, on strict improvement,
-// lowest index on ties.  A NaN value ranks as +infinity.
+// One group of G lanes per particle: lane j draws, updates and stores
+// coordinate j (consecutive lanes touch consecutive addresses), the group
+// evaluates the objective term-parallel and keeps the personal best.
+// Blocks are persistent: a launch runs min(#particle groups, 2048) blocks that
+// stride over the particles.
 //
-// Particle state is struct-of-arrays in HBM, row-major [n][dim] doubles.
+// Global best.  The paper's kernels take it with an atomicMin on the value and
+// an unsynchronised copy of the position, which lets two winners interleave
+// their copies.  Here it is a deterministic reduction in three stages, with no
+// device-wide fence anywhere: (1) each block reduces its particles to one
+// (rank key, index) pair and stores it, with the winner's position, in slot
+// t & 1; (2) every block of the next launch reduces those P block results
+// itself (after the kernel boundary they are visible to all), compares the
+// winner with the previous global best (strict improvement, lowest index on
+// ties, NaN ranking as +infinity) and so starts the sweep with the global best
+// of sweep t; block 0 also records it for later launches; (3) after the last
+// sweep a one-block launch performs stage (2) once more to publish the result.
 #include "zeus_device.h"
+#include "zeus_group.h"
 #include "zeus_internal.h"
 
 namespace zeus {
@@ -19,167 +28,205 @@ namespace {
 struct PsoArgs {
   int64_t n;
   int d;
-  int t;            // PSO iteration (1-based); 0 for the initialisation
-  double lo, hi;    // sampling box
-  double vh;        // velocity half-range
-  double w, c1, c2; // inertia, cognitive, social
-  uint64_t k0, k1;  // Philox key (seed, request id)
+  int t;             // sweep: 0 initialises, t >= 1 is update t
+  double lo, hi;     // sampling box
+  double vh;         // velocity half-range
+  double w, c1, c2;  // inertia, cognitive, social
+  uint64_t k0, k1;   // Philox key (seed, request id)
   Workspace ws;
 };
 
-// Block-wide (key, index) minimum; result valid in thread 0.
-__device__ void block_argmin(double &key, int64_t &idx, double *sk, int64_t *si) {
+// Block-wide minimum of (key, idx) carrying two payloads; the result is left
+// in every thread.
+__device__ void block_argmin(double &key, int64_t &idx, double &val, int64_t &aux) {
+  __shared__ double sk[kPsoBlock / 64], sv[kPsoBlock / 64];
+  __shared__ int64_t si[kPsoBlock / 64], sa[kPsoBlock / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const double ok = __shfl_xor(key, off, 64);
     const int64_t oi = __shfl_xor(idx, off, 64);
+    const double ov = __shfl_xor(val, off, 64);
+    const int64_t oa = __shfl_xor(aux, off, 64);
     if (key_less(ok, oi, key, idx)) {
       key = ok;
       idx = oi;
+      val = ov;
+      aux = oa;
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     sk[wave] = key;
     si[wave] = idx;
+    sv[wave] = val;
+    sa[wave] = aux;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int wv = 1; wv < kPsoBlock / 64; ++wv)
-      if (key_less(sk[wv], si[wv], key, idx)) {
-        key = sk[wv];
-        idx = si[wv];
-      }
-  }
+  key = sk[0];
+  idx = si[0];
+  val = sv[0];
+  aux = sa[0];
+  for (int wv = 1; wv < kPsoBlock / 64; ++wv)
+    if (key_less(sk[wv], si[wv], key, idx)) {
+      key = sk[wv];
+      idx = si[wv];
+      val = sv[wv];
+      aux = sa[wv];
+    }
   __syncthreads();
 }
 
-// Publishes this block's best; the last block of the grid then reduces all
-// block results and updates the global best (always for the initial swarm,
-// on strict improvement afterwards) and copies its position to gx.
-__device__ void finish_global_best(const PsoArgs &a, double key, int64_t idx, bool initial) {
-  __shared__ double sk[kPsoBlock / 64];
-  __shared__ int64_t si[kPsoBlock / 64];
-  __shared__ bool last;
-  __shared__ int64_t winner;
-  block_argmin(key, idx, sk, si);
-  __threadfence();  // make this block's particle writes visible device-wide
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a.ws.partial_key[blockIdx.x] = key;
-    a.ws.partial_idx[blockIdx.x] = idx;
-    __threadfence();
-    const uint32_t done = atomicAdd(a.ws.pso_counter, 1u);
-    last = (done == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();  // acquire the other blocks' results
-  double k = __builtin_huge_val();
-  int64_t i = INT64_MAX;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kPsoBlock) {
-    const double kb = __hip_atomic_load(&a.ws.partial_key[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int64_t ib = __hip_atomic_load(&a.ws.partial_idx[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (key_less(kb, ib, k, i)) {
-      k = kb;
-      i = ib;
+// Stage (2): the global best after sweep `done` (>= 0) from the block results
+// of that sweep and the global best after sweep done-1.  Leaves its position
+// in gx_sh[0..d) for every thread of the block.  When `publish`, the result is
+// also stored for later launches (and in final_best / final_gx if given).
+__device__ void global_best_after(const PsoArgs &a, int done, double *gx_sh, bool publish,
+                                  PsoBest *final_best, double *final_gx) {
+  const int P = a.ws.pso_blocks, d = a.d, slot = done & 1;
+  double key = __builtin_huge_val(), val = __builtin_nan("");
+  int64_t idx = INT64_MAX, blk = 0;
+  for (int b = threadIdx.x; b < P; b += kPsoBlock) {
+    const double kb = a.ws.part_key[slot * P + b];
+    const int64_t ib = a.ws.part_idx[slot * P + b];
+    if (key_less(kb, ib, key, idx)) {
+      key = kb;
+      idx = ib;
+      val = a.ws.part_f[slot * P + b];
+      blk = b;
     }
   }
-  block_argmin(k, i, sk, si);
-  if (threadIdx.x == 0) {
-    const double fm = a.ws.pf[i];
-    bool take = initial || rank_key(fm) < rank_key(a.ws.best->f);
-    if (take) {
-      a.ws.best->f = fm;
-      a.ws.best->idx = i;
-    }
-    winner = take ? i : -1;
-    *a.ws.pso_counter = 0u;  // ready for the next launch
+  block_argmin(key, idx, val, blk);
+  bool take = true;
+  PsoBest prev{0.0, 0};
+  if (done > 0) {
+    prev = a.ws.best_store[(done - 1) & 1];
+    take = rank_key(val) < rank_key(prev.f);  // strict improvement
   }
+  for (int j = threadIdx.x; j < d; j += kPsoBlock)
+    gx_sh[j] = take ? a.ws.part_x[((size_t)slot * P + blk) * d + j]
+                    : a.ws.gx_store[((done - 1) & 1) * d + j];
   __syncthreads();
-  if (winner >= 0)
-    for (int j = threadIdx.x; j < a.d; j += kPsoBlock) a.ws.gx[j] = a.ws.px[winner * a.d + j];
+  if (publish) {
+    const PsoBest nb = take ? PsoBest{val, idx} : prev;
+    if (threadIdx.x == 0) {
+      a.ws.best_store[slot] = nb;
+      if (final_best) *final_best = nb;
+    }
+    for (int j = threadIdx.x; j < d; j += kPsoBlock) {
+      a.ws.gx_store[slot * d + j] = gx_sh[j];
+      if (final_gx) final_gx[j] = gx_sh[j];
+    }
+  }
 }
 
-template <int OBJ>
-__global__ __launch_bounds__(kPsoBlock) void pso_init_kernel(PsoArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kPsoBlock + threadIdx.x;
-  double key = __builtin_huge_val();
-  int64_t idx = INT64_MAX;
-  if (i < a.n) {
-    const int d = a.d;
-    double *xr = a.ws.x + i * d, *vr = a.ws.v + i * d, *pr = a.ws.px + i * d;
-    const double vlo = -a.vh, vhi = a.vh;
-    for (int jb = 0; jb * 4 < d; ++jb) {
-      const u64x4 rx = philox4x64_10((uint64_t)jb, (uint64_t)i, 0, kTagX0, a.k0, a.k1);
-      const u64x4 rv = philox4x64_10((uint64_t)jb, (uint64_t)i, 0, kTagV0, a.k0, a.k1);
+template <int OBJ, int G>
+__global__ __launch_bounds__(kPsoBlock) void pso_kernel(PsoArgs a) {
+  using E = Elem<OBJ>;
+  constexpr int kGroups = kPsoBlock / G;
+  __shared__ double xs_all[kGroups][G];
+  __shared__ double tv_all[kGroups][E::K * G];
+  __shared__ double uw_all[kGroups][2][G + 4];  // the group's uniforms, two streams
+  __shared__ double gx_sh[kMaxDim];
+  const GroupLanes<G> L;
+  const int gib = threadIdx.x / G;  // group in block
+  double *xs = xs_all[gib], *tv = tv_all[gib];
+  const int d = a.d, j = L.j, P = a.ws.pso_blocks;
+  const int nb = (d + 3) >> 2;  // Philox blocks per stream
+  // term buffers: entries past the last term stay zero (see ordered_sums)
+  for (int q = threadIdx.x; q < kGroups * E::K * G; q += kPsoBlock) (&tv_all[0][0])[q] = 0.0;
+  __syncthreads();
+
+  if (a.t > 0) global_best_after(a, a.t - 1, gx_sh, blockIdx.x == 0, nullptr, nullptr);
+  const double gxj = (a.t > 0 && j < d) ? gx_sh[j] : 0.0;
+
+  // this block's best particle of the sweep, tracked by each group's lane 0
+  double key = __builtin_huge_val(), val = __builtin_nan("");
+  int64_t idx = INT64_MAX, unused = 0;
+  const uint64_t tag_a = a.t == 0 ? kTagX0 : kTagR1, tag_b = a.t == 0 ? kTagV0 : kTagR2;
+  const int64_t stride = (int64_t)P * kGroups;
+  for (int64_t i = (int64_t)blockIdx.x * kGroups + gib;; i += stride) {
+    const bool live = i < a.n;
+    if (__ballot(live) == 0ull) break;  // the whole wave is past the end
+    // one Philox block per lane: lane l < 2 nb draws block (l mod nb) of
+    // stream a (l < nb) or b and shares its four words through LDS
+    if (live && j < 2 * nb) {
+      const int sb = j >= nb, jb = sb ? j - nb : j;
+      const u64x4 r = philox4x64_10((uint64_t)jb, (uint64_t)i, (uint64_t)a.t, sb ? tag_b : tag_a,
+                                    a.k0, a.k1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = jb * 4 + q;
-        if (j < d) {
-          // UniformSample(lo, hi) = lo + u (hi - lo)
-          const double xv = a.lo + u01(rx.w[q]) * (a.hi - a.lo);
-          const double vv = vlo + u01(rv.w[q]) * (vhi - vlo);
-          xr[j] = xv;
-          vr[j] = vv;
-          pr[j] = xv;
+      for (int q = 0; q < 4; ++q) uw_all[gib][sb][jb * 4 + q] = u01(r.w[q]);
+    }
+    wave_sync();
+    const bool own = live && j < d;
+    double x = 0.0;
+    if (own) {
+      const int64_t o = i * d + j;
+      const double ua = uw_all[gib][0][j], ub = uw_all[gib][1][j];
+      if (a.t == 0) {
+        const double vlo = -a.vh, vhi = a.vh;
+        // UniformSample(lo, hi) = lo + u (hi - lo)
+        x = a.lo + ua * (a.hi - a.lo);
+        const double v = vlo + ub * (vhi - vlo);
+        a.ws.x[o] = x;
+        a.ws.v[o] = v;
+        a.ws.px[o] = x;
+      } else {
+        const double x0 = a.ws.x[o], v = a.ws.v[o];
+        // v' = w v + c1 r1 (p - x) + c2 r2 (g - x);  x' = x + v'
+        const double inertia = a.w * v;
+        const double cog = (a.c1 * ua) * (a.ws.px[o] - x0);
+        const double soc = (a.c2 * ub) * (gxj - x0);
+        const double vn = (inertia + cog) + soc;
+        x = x0 + vn;
+        a.ws.v[o] = vn;
+        a.ws.x[o] = x;
+      }
+      xs[j] = x;
+    }
+    wave_sync();
+    if (live) {
+      const double f = group_value<OBJ, G>(L, d, xs, tv);
+      bool improved = true;
+      double pf = f;
+      if (a.t > 0) {
+        const double old = a.ws.pf[i];
+        improved = rank_key(f) < rank_key(old);  // personal best, strict
+        pf = improved ? f : old;
+        if (improved && own) a.ws.px[i * d + j] = x;
+      }
+      if (j == 0) {
+        if (improved) a.ws.pf[i] = pf;
+        if (key_less(rank_key(pf), i, key, idx)) {
+          key = rank_key(pf);
+          idx = i;
+          val = pf;
         }
       }
     }
-    const double f = Obj<OBJ>::template eval<double>(d, [=](int j) { return xr[j]; });
-    a.ws.pf[i] = f;
-    key = rank_key(f);
-    idx = i;
+    wave_sync();  // the group's LDS is reused by its next particle
   }
-  finish_global_best(a, key, idx, true);
+  block_argmin(key, idx, val, unused);
+  // stage (1): this block's result and its winner's personal-best position
+  // (written by this block in this launch, so visible after the barrier)
+  const int slot = a.t & 1;
+  if (threadIdx.x == 0) {
+    a.ws.part_key[slot * P + blockIdx.x] = key;
+    a.ws.part_idx[slot * P + blockIdx.x] = idx;
+    a.ws.part_f[slot * P + blockIdx.x] = val;
+  }
+  if (idx != INT64_MAX)
+    for (int jj = threadIdx.x; jj < d; jj += kPsoBlock)
+      a.ws.part_x[((size_t)slot * P + blockIdx.x) * d + jj] = a.ws.px[idx * d + jj];
 }
 
-template <int OBJ>
-__global__ __launch_bounds__(kPsoBlock) void pso_step_kernel(PsoArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kPsoBlock + threadIdx.x;
-  double key = __builtin_huge_val();
-  int64_t idx = INT64_MAX;
-  if (i < a.n) {
-    const int d = a.d;
-    double *xr = a.ws.x + i * d, *vr = a.ws.v + i * d, *pr = a.ws.px + i * d;
-    const double *gx = a.ws.gx;
-    for (int jb = 0; jb * 4 < d; ++jb) {
-      const u64x4 r1w = philox4x64_10((uint64_t)jb, (uint64_t)i, (uint64_t)a.t, kTagR1, a.k0, a.k1);
-      const u64x4 r2w = philox4x64_10((uint64_t)jb, (uint64_t)i, (uint64_t)a.t, kTagR2, a.k0, a.k1);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = jb * 4 + q;
-        if (j < d) {
-          const double r1 = u01(r1w.w[q]), r2 = u01(r2w.w[q]);
-          const double x = xr[j], v = vr[j];
-          // v' = w v + c1 r1 (p - x) + c2 r2 (g - x);  x' = x + v'
-          const double inertia = a.w * v;
-          const double cog = (a.c1 * r1) * (pr[j] - x);
-          const double soc = (a.c2 * r2) * (gx[j] - x);
-          const double vn = (inertia + cog) + soc;
-          vr[j] = vn;
-          xr[j] = x + vn;
-        }
-      }
-    }
-    const double fx = Obj<OBJ>::template eval<double>(d, [=](int j) { return xr[j]; });
-    double pf = a.ws.pf[i];
-    if (rank_key(fx) < rank_key(pf)) {  // personal best, strict
-      pf = fx;
-      a.ws.pf[i] = fx;
-      for (int j = 0; j < d; ++j) pr[j] = xr[j];
-    }
-    key = rank_key(pf);
-    idx = i;
-  }
-  finish_global_best(a, key, idx, false);
+// Stage (3): publish the swarm best after the last sweep.
+__global__ __launch_bounds__(kPsoBlock) void pso_finish_kernel(PsoArgs a) {
+  __shared__ double gx_sh[kMaxDim];
+  global_best_after(a, a.t, gx_sh, true, a.ws.best, a.ws.gx);
 }
 
 __global__ void ws_init_kernel(Workspace ws) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *ws.pso_counter = 0u;
-    *ws.queue = 0ull;
-  }
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ws.queue = 0ull;
 }
 
 PsoArgs make_args(const Launch &L, int t) {
@@ -200,41 +247,68 @@ PsoArgs make_args(const Launch &L, int t) {
   return a;
 }
 
-template <template <int> class K>
-hipError_t launch_obj(int obj, dim3 grid, hipStream_t s, const PsoArgs &a) {
-  switch (obj) {
-    case kRosenbrock: hipLaunchKernelGGL(K<kRosenbrock>::fn, grid, dim3(kPsoBlock), 0, s, a); break;
-    case kRastrigin: hipLaunchKernelGGL(K<kRastrigin>::fn, grid, dim3(kPsoBlock), 0, s, a); break;
-    case kAckley: hipLaunchKernelGGL(K<kAckley>::fn, grid, dim3(kPsoBlock), 0, s, a); break;
-    case kStyblinskiTang: hipLaunchKernelGGL(K<kStyblinskiTang>::fn, grid, dim3(kPsoBlock), 0, s, a); break;
-    case kGoldsteinPrice: hipLaunchKernelGGL(K<kGoldsteinPrice>::fn, grid, dim3(kPsoBlock), 0, s, a); break;
-    case kSphere: hipLaunchKernelGGL(K<kSphere>::fn, grid, dim3(kPsoBlock), 0, s, a); break;
-    case kQuartic: hipLaunchKernelGGL(K<kQuartic>::fn, grid, dim3(kPsoBlock), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
+template <int OBJ, int G>
+hipError_t launch_g(const PsoArgs &a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((pso_kernel<OBJ, G>), dim3(blocks), dim3(kPsoBlock), 0, s, a);
   return hipGetLastError();
 }
 
-template <int OBJ> struct InitK { static constexpr auto fn = pso_init_kernel<OBJ>; };
-template <int OBJ> struct StepK { static constexpr auto fn = pso_step_kernel<OBJ>; };
+template <int OBJ>
+hipError_t launch_obj(const PsoArgs &a, int G, int blocks, hipStream_t s) {
+  switch (G) {
+    case 2: return launch_g<OBJ, 2>(a, blocks, s);
+    case 4: return launch_g<OBJ, 4>(a, blocks, s);
+    case 8: return launch_g<OBJ, 8>(a, blocks, s);
+    case 16: return launch_g<OBJ, 16>(a, blocks, s);
+    case 32: return launch_g<OBJ, 32>(a, blocks, s);
+    case 64: return launch_g<OBJ, 64>(a, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pso(const Launch &L, int t) {
+  const PsoArgs a = make_args(L, t);
+  const int G = pso_group_lanes(L.pb->dim);
+  const int blocks = L.ws.pso_blocks;
+  switch (L.pb->objective) {
+    case kRosenbrock: return launch_obj<kRosenbrock>(a, G, blocks, L.stream);
+    case kRastrigin: return launch_obj<kRastrigin>(a, G, blocks, L.stream);
+    case kAckley: return launch_obj<kAckley>(a, G, blocks, L.stream);
+    case kStyblinskiTang: return launch_obj<kStyblinskiTang>(a, G, blocks, L.stream);
+    case kGoldsteinPrice: return launch_g<kGoldsteinPrice, 2>(a, blocks, L.stream);
+    case kSphere: return launch_obj<kSphere>(a, G, blocks, L.stream);
+    case kQuartic: return launch_obj<kQuartic>(a, G, blocks, L.stream);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 }  // namespace
 
-int pso_blocks(int64_t n) { return (int)((n + kPsoBlock - 1) / kPsoBlock); }
+int pso_group_lanes(int dim) {
+  int g = 2;
+  while (g < dim) g <<= 1;
+  return g;
+}
+
+int pso_blocks(int64_t n, int dim) {
+  const int64_t per_block = kPsoBlock / pso_group_lanes(dim);
+  const int64_t want = (n + per_block - 1) / per_block;
+  return (int)(want < kPsoMaxBlocks ? want : kPsoMaxBlocks);
+}
 
 hipError_t launch_ws_init(const Launch &L) {
   hipLaunchKernelGGL(ws_init_kernel, dim3(1), dim3(64), 0, L.stream, L.ws);
   return hipGetLastError();
 }
 
-hipError_t launch_pso_init(const Launch &L) {
-  const PsoArgs a = make_args(L, 0);
-  return launch_obj<InitK>(L.pb->objective, dim3(L.ws.pso_blocks), L.stream, a);
-}
+hipError_t launch_pso_init(const Launch &L) { return launch_pso(L, 0); }
 
-hipError_t launch_pso_step(const Launch &L, int t) {
-  const PsoArgs a = make_args(L, t);
-  return launch_obj<StepK>(L.pb->objective, dim3(L.ws.pso_blocks), L.stream, a);
+hipError_t launch_pso_step(const Launch &L, int t) { return launch_pso(L, t); }
+
+hipError_t launch_pso_finish(const Launch &L) {
+  const PsoArgs a = make_args(L, L.pb->iter_pso);
+  hipLaunchKernelGGL(pso_finish_kernel, dim3(1), dim3(kPsoBlock), 0, L.stream, a);
+  return hipGetLastError();
 }
 
 }  // namespace zeus
