@@ -109,7 +109,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rastrigin_d10_n65536", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run of the same workload")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 3 times (a plain copy kernel "
+                         "of known size for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 8, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "multi-GPU sharding is a design note, not built", file=sys.stderr)
@@ -120,29 +135,46 @@ def main():
 
     p = WORKLOADS[args.workload]
     ctx = Z.zeus_context_create(0)
-    ds = Z.DeviceSolve(p)
     stream = torch.cuda.Stream()   # the library's kernels and torch's events share it
     sptr = stream.cuda_stream
 
-    for _ in range(args.warmup):
-        ds.enqueue(ctx, sptr)
-    torch.cuda.synchronize()
+    def timed(problem):
+        ds = Z.DeviceSolve(problem)
+        for _ in range(args.warmup):
+            ds.enqueue(ctx, sptr)
+        torch.cuda.synchronize()
+        Z.zeus_context_set_profiling(ctx, True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            ds.enqueue(ctx, sptr)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = Z.zeus_context_get_profile(ctx)
+        Z.zeus_context_set_profiling(ctx, False)
+        lat = np.array([a.elapsed_time(b) for a, b in evs])
+        return wall, prof, lat, ds.host()
 
-    Z.zeus_context_set_profiling(ctx, True)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b in evs:
-        a.record(stream)
-        ds.enqueue(ctx, sptr)
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = Z.zeus_context_get_profile(ctx)
-    lat = np.array([a.elapsed_time(b) for a, b in evs])
-    out = ds.host()
+    wall, prof, lat, out = timed(p)
     s = out["summary"]
+    mixed = None
+    if not args.no_mixed and p.get("precision", "fp64") == "fp64":
+        pm = dict(p, precision="mixed", grad_tol=max(p["grad_tol"], 1e-4))
+        mwall, _, mlat, mout = timed(pm)
+        ms = mout["summary"]
+        mms = mwall * 1e3 / args.steps
+        fstar_m = W.f_star(pm["objective"], pm["dim"])
+        mixed = {"grad_tol": pm["grad_tol"], "ms_per_step": mms,
+                 "start_iters_per_s": ms["total_iters"] / (mms / 1e3),
+                 "converged_starts_per_s": ms["n_converged"] / (mms / 1e3),
+                 "p50_solve_ms": float(np.percentile(mlat, 50)),
+                 "p99_solve_ms": float(np.percentile(mlat, 99)),
+                 "success_rate": float(np.mean(mout["f"] - fstar_m < 1e-4)),
+                 "speedup_vs_fp64": (wall * 1e3 / args.steps) / mms}
     Z.zeus_context_destroy(ctx)
 
     ms_per_step = wall * 1e3 / args.steps
@@ -173,6 +205,8 @@ def main():
                      "traffic": None, "kernel": "bfgs_kernel",
                      "flops_per_launch": flops},
     }
+    if mixed is not None:
+        line["mixed"] = mixed
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)

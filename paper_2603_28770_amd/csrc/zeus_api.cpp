@@ -62,7 +62,6 @@ zeus_err check_problem(const zeus_problem *p) {
   if (p->required_converged != 0)
     return fail(ZEUS_EUNSUPPORTED, "early stopping (required_converged > 0) is not built");
   if (p->dim > zeus::kMaxDim) return fail(ZEUS_EUNSUPPORTED, "dim > 64 is not built");
-  if (p->precision == ZEUS_MIXED) return fail(ZEUS_EUNSUPPORTED, "mixed precision is not built");
   return ZEUS_OK;
 }
 

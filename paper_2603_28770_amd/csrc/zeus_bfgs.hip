@@ -70,9 +70,63 @@ __device__ __host__ __forceinline__ int group_stride(int G, int K, int R, int mp
 // product of the previous one and shrink, as Alg. 6 forms them.
 constexpr int kTabTrials = 64;
 
-template <int OBJ, int G>
+// One Armijo search (Alg. 6) with the objective evaluated in number type U.
+// A round evaluates R consecutive trials of the sequence at once, each spread
+// over tp = G / R lanes (lane c of a trial takes terms c, c + tp, ...); the
+// first trial that passes is the step Alg. 6 returns.  Returns its index, or
+// -1 when none of the iter_ls trials passes.
+template <int OBJ, int G, class U>
+__device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const BfgsArgs &a,
+                                             const double *alpha_tab, const GroupShm &sh, int d,
+                                             int m, int mp, int R, uint64_t leaders, double f,
+                                             double ddir) {
+  using E = Elem<OBJ>;
+  const int tp = G / R, trial_slot = L.j / tp, term_slot = L.j % tp;
+  U *tvr = reinterpret_cast<U *>(sh.tt) + trial_slot * mp;
+  for (int base = 0; base < a.iter_ls; base += R) {
+    const int t = base + trial_slot;
+    double alpha;
+    if (t < kTabTrials) {
+      alpha = alpha_tab[t];
+    } else {
+      alpha = alpha_tab[kTabTrials - 1];
+      for (int q = kTabTrials - 1; q < t; ++q) alpha = alpha * a.shrink;
+    }
+    for (int i = term_slot; i < m; i += tp) {
+      U w[E::W], out[E::K];
+#pragma unroll
+      for (int q = 0; q < E::W; ++q) w[q] = (U)(sh.xs[i + q] + alpha * sh.ps[i + q]);
+      E::template term<U>(w, out);
+#pragma unroll
+      for (int kk = 0; kk < E::K; ++kk) tvr[kk * R * mp + i] = out[kk];
+    }
+    wave_sync();
+    U sums[E::K];
+#pragma unroll
+    for (int kk = 0; kk < E::K; ++kk) sums[kk] = sum_ordered<G, U>(tvr + kk * R * mp, mp);
+    const double ft = (double)E::template outer<U>(d, sums);
+    const bool ok = t < a.iter_ls && ft <= f + (a.armijo_c * alpha) * ddir;
+    const uint64_t hit = L.ballot(ok) & leaders;
+    wave_sync();  // every lane has read the term buffer before it is reused
+    if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1) / tp;
+  }
+  return -1;
+}
+
+// T = double: every step in FP64.
+// T = float (mixed precision): a start evaluates the objective, its dual
+// numbers and the term sums in FP32 at the FP32-rounded point, while x, p, H,
+// Hg, g'p, the Armijo comparison, s, y and y's stay FP64.  Near a minimum FP32
+// can no longer resolve the Armijo decrease nor a gradient below the tolerance,
+// so a start escalates to FP64 evaluation for the rest of its run, re-evaluating
+// its current point, when (a) its FP32 gradient norm falls below 10 Theta,
+// (b) an FP32 value or gradient is not finite, or (c) an FP32 line search finds
+// no step.  Convergence and non-finite outcomes are therefore always decided
+// on FP64 values; the value reported for a start is FP64 at its final x.
+template <int OBJ, int G, class T>
 __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
   using E = Elem<OBJ>;
+  constexpr bool kMixed = sizeof(T) != sizeof(double);
   constexpr int S = 64 / G;  // groups per wave
   extern __shared__ double smem[];
   const GroupLanes<G> L;
@@ -82,10 +136,8 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
   const int m = E::terms(d);
   const int dp = Chunk<G>::padded(d), mp = Chunk<G>::padded(m);
   const int R = a.trials_per_round;      // line-search trials per round
-  const int tp = G / R;                  // lanes per trial
-  const int trial_slot = j / tp, term_slot = j % tp;
-  uint64_t leaders = 0;                  // bit r*tp of every trial r of a round
-  for (int r = 0; r < R; ++r) leaders |= 1ull << (r * tp);
+  uint64_t leaders = 0;                  // bit r*(G/R) of every trial r of a round
+  for (int r = 0; r < R; ++r) leaders |= 1ull << (r * (G / R));
 
   __shared__ double alpha_tab[kTabTrials];
   const int stride = group_stride(G, E::K, R, mp);
@@ -116,6 +168,12 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
   int64_t idx = -1;
   int k = 0, ls_trials = 0;
   bool fresh = false;
+  bool hi = !kMixed;  // evaluating in FP64 (always, unless mixed precision)
+  // term buffers back to zero (their padding), e.g. between FP32 and FP64 use
+  auto zero_terms = [&]() {
+    for (int q = j; q < E::K * G + E::K * R * mp; q += G) sh.tg[q] = 0.0;
+    wave_sync();
+  };
 
   for (;;) {
     // -- claim a start when idle ------------------------------------------
@@ -132,12 +190,17 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
       k = 0;
       ls_trials = 0;
       fresh = true;
+      hi = !kMixed;
+      if (kMixed) zero_terms();
     }
     wave_sync();
 
     // -- value and gradient at xs (dual numbers, one direction per lane) ----
-    double gn;
-    const double fn = group_value_grad<OBJ, G>(L, d, sh.xs, sh.tg, &gn);
+    double gn, fn;
+    if (hi)
+      fn = group_value_grad<OBJ, G, double>(L, d, sh.xs, sh.tg, &gn);
+    else
+      fn = group_value_grad<OBJ, G, T>(L, d, sh.xs, reinterpret_cast<T *>(sh.tg), &gn);
 
     // -- after a step: s, y and the rank-2 inverse-Hessian update -----------
     if (!fresh) {
@@ -181,6 +244,12 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
     const bool any_bad = L.ballot(bad) != 0ull;
     const double gg = dot_ordered<G>(sh.gs, sh.gs, dp);
+    if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * a.tol)) {
+      hi = true;  // escalate: re-evaluate this point in FP64
+      fresh = true;
+      zero_terms();
+      continue;
+    }
     int status = -1;
     if (any_bad)
       status = ZEUS_ST_NONFINITE;
@@ -190,6 +259,13 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
       status = ZEUS_ST_MAXITER;
     if (status >= 0) {
       if (own) a.out_x[idx * d + j] = xj;
+      if (kMixed && !hi) {
+        // FP64 value at the returned x (ys and ss are free until the next step)
+#pragma unroll
+        for (int kk = 0; kk < E::K && kk < 2; ++kk) (kk == 0 ? sh.ys : sh.ss)[j] = 0.0;
+        wave_sync();
+        f = group_value<OBJ, G, double>(L, d, sh.xs, sh.ys);
+      }
       if (j == 0) {
         a.out_f[idx] = f;
         a.out_iters[idx] = k;
@@ -221,39 +297,17 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     }
 
     // -- Armijo backtracking (Alg. 6) ---------------------------------------
-    // A round evaluates R consecutive trials of the sequence at once, each
-    // spread over tp = G / R lanes (lane c of a trial takes terms c, c + tp,
-    // ...); the first trial that passes is the step Alg. 6 returns.
-    int taken = -1;
-    for (int base = 0; base < a.iter_ls; base += R) {
-      const int t = base + trial_slot;
-      double alpha;
-      if (t < kTabTrials) {
-        alpha = alpha_tab[t];
-      } else {
-        alpha = alpha_tab[kTabTrials - 1];
-        for (int q = kTabTrials - 1; q < t; ++q) alpha = alpha * a.shrink;
-      }
-      double *tvr = sh.tt + trial_slot * mp;
-      for (int i = term_slot; i < m; i += tp) {
-        double w[E::W], out[E::K];
-#pragma unroll
-        for (int q = 0; q < E::W; ++q) w[q] = sh.xs[i + q] + alpha * sh.ps[i + q];
-        E::template term<double>(w, out);
-#pragma unroll
-        for (int kk = 0; kk < E::K; ++kk) tvr[kk * R * mp + i] = out[kk];
-      }
-      wave_sync();
-      double sums[E::K];
-#pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) sums[kk] = sum_ordered<G>(tvr + kk * R * mp, mp);
-      const double ft = E::template outer<double>(d, sums);
-      const bool ok = t < a.iter_ls && ft <= f + (a.armijo_c * alpha) * ddir;
-      const uint64_t hit = L.ballot(ok) & leaders;
-      wave_sync();  // every lane has read tv before it is written again
-      if (hit != 0ull) {
-        taken = base + (__ffsll((unsigned long long)hit) - 1) / tp;
-        break;
+    int taken;
+    if (hi) {
+      taken = armijo_search<OBJ, G, double>(L, a, alpha_tab, sh, d, m, mp, R, leaders, f, ddir);
+    } else {
+      taken = armijo_search<OBJ, G, T>(L, a, alpha_tab, sh, d, m, mp, R, leaders, f, ddir);
+      if (taken < 0) {
+        ls_trials += a.iter_ls;
+        hi = true;  // escalate: FP32 cannot resolve this decrease
+        fresh = true;
+        zero_terms();
+        continue;
       }
     }
     const int nshrink = taken >= 0 ? taken : a.iter_ls;
@@ -346,7 +400,7 @@ __global__ __launch_bounds__(kSumBlock) void summary_kernel(int64_t n, const dou
   }
 }
 
-template <int OBJ, int G>
+template <int OBJ, int G, class T>
 hipError_t launch_g(const BfgsArgs &a, int blocks, hipStream_t s) {
   using E = Elem<OBJ>;
   const int m = E::terms(a.d);
@@ -355,19 +409,33 @@ hipError_t launch_g(const BfgsArgs &a, int blocks, hipStream_t s) {
   const int stride = group_stride(G, E::K, R, (m + CH - 1) / CH * CH);
   const size_t lds = sizeof(double) * (size_t)stride * (kBfgsBlock / 64) * (64 / G);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((bfgs_kernel<OBJ, G>), dim3(blocks), dim3(kBfgsBlock), lds, s, a);
+  hipLaunchKernelGGL((bfgs_kernel<OBJ, G, T>), dim3(blocks), dim3(kBfgsBlock), lds, s, a);
   return hipGetLastError();
 }
 
-template <int OBJ>
+template <int OBJ, class T>
 hipError_t launch_obj(const BfgsArgs &a, int G, int blocks, hipStream_t s) {
   switch (G) {
-    case 2: return launch_g<OBJ, 2>(a, blocks, s);
-    case 4: return launch_g<OBJ, 4>(a, blocks, s);
-    case 8: return launch_g<OBJ, 8>(a, blocks, s);
-    case 16: return launch_g<OBJ, 16>(a, blocks, s);
-    case 32: return launch_g<OBJ, 32>(a, blocks, s);
-    case 64: return launch_g<OBJ, 64>(a, blocks, s);
+    case 2: return launch_g<OBJ, 2, T>(a, blocks, s);
+    case 4: return launch_g<OBJ, 4, T>(a, blocks, s);
+    case 8: return launch_g<OBJ, 8, T>(a, blocks, s);
+    case 16: return launch_g<OBJ, 16, T>(a, blocks, s);
+    case 32: return launch_g<OBJ, 32, T>(a, blocks, s);
+    case 64: return launch_g<OBJ, 64, T>(a, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class T>
+hipError_t launch_prec(int objective, const BfgsArgs &a, int G, int blocks, hipStream_t s) {
+  switch (objective) {
+    case kRosenbrock: return launch_obj<kRosenbrock, T>(a, G, blocks, s);
+    case kRastrigin: return launch_obj<kRastrigin, T>(a, G, blocks, s);
+    case kAckley: return launch_obj<kAckley, T>(a, G, blocks, s);
+    case kStyblinskiTang: return launch_obj<kStyblinskiTang, T>(a, G, blocks, s);
+    case kGoldsteinPrice: return launch_obj<kGoldsteinPrice, T>(a, G, blocks, s);
+    case kSphere: return launch_obj<kSphere, T>(a, G, blocks, s);
+    case kQuartic: return launch_obj<kQuartic, T>(a, G, blocks, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -435,16 +503,8 @@ hipError_t launch_bfgs(const Launch &L) {
   const int64_t want = (p.n_starts + starts_per_block - 1) / starts_per_block;
   const int64_t cap = (int64_t)cus * 8;
   const int blocks = (int)(want < cap ? want : cap);
-  switch (p.objective) {
-    case kRosenbrock: return launch_obj<kRosenbrock>(a, G, blocks, L.stream);
-    case kRastrigin: return launch_obj<kRastrigin>(a, G, blocks, L.stream);
-    case kAckley: return launch_obj<kAckley>(a, G, blocks, L.stream);
-    case kStyblinskiTang: return launch_obj<kStyblinskiTang>(a, G, blocks, L.stream);
-    case kGoldsteinPrice: return launch_obj<kGoldsteinPrice>(a, G, blocks, L.stream);
-    case kSphere: return launch_obj<kSphere>(a, G, blocks, L.stream);
-    case kQuartic: return launch_obj<kQuartic>(a, G, blocks, L.stream);
-    default: return hipErrorInvalidValue;
-  }
+  if (p.precision == ZEUS_MIXED) return launch_prec<float>(p.objective, a, G, blocks, L.stream);
+  return launch_prec<double>(p.objective, a, G, blocks, L.stream);
 }
 
 hipError_t launch_summary(const Launch &L) {

@@ -204,7 +204,9 @@ __device__ __forceinline__ dual<double> dcos(dual<double> a) {
   return {c, -(a.t * s)};
 }
 __device__ __forceinline__ dual<float> dcos(dual<float> a) {
-  return {cosf(a.v), -(a.t * sinf(a.v))};
+  float s, c;
+  sincosf(a.v, &s, &c);
+  return {c, -(a.t * s)};
 }
 // exp(a + b eps) = e^a + b e^a eps
 template <class T>

@@ -42,12 +42,12 @@ struct Chunk {
   __device__ __forceinline__ static int padded(int n) { return (n + CH - 1) / CH * CH; }
 };
 
-template <int G>
-__device__ __forceinline__ double sum_ordered(const double *a, int n) {
+template <int G, class T>
+__device__ __forceinline__ T sum_ordered(const T *a, int n) {
   constexpr int CH = Chunk<G>::CH;
-  double acc = 0.0;
+  T acc = T(0);
   for (int c0 = 0; c0 < n; c0 += CH) {
-    double v[CH];
+    T v[CH];
 #pragma unroll
     for (int q = 0; q < CH; ++q) v[q] = a[c0 + q];
 #pragma unroll
@@ -76,57 +76,58 @@ __device__ __forceinline__ double dot_ordered(const double *a, const double *b, 
 
 // Sequential sums S_k = tv[k][0] + ... + tv[k][m-1] for the K term sums of a
 // [K][G] term buffer whose entries from m on are zero.
-template <int K, int G>
-__device__ __forceinline__ void ordered_sums(const double *tv, int m, double *s) {
+template <int K, int G, class T>
+__device__ __forceinline__ void ordered_sums(const T *tv, int m, T *s) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) s[k] = sum_ordered<G>(tv + k * G, m);
+  for (int k = 0; k < K; ++k) s[k] = sum_ordered<G, T>(tv + k * G, m);
 }
 
 // Value of the objective at the point whose coordinates are xs[0..d-1] in the
-// group's LDS: lane c < m evaluates term c and stores it in tv[k*G + c], then
-// every lane adds the terms up in index order.  tv[k*G + c] must be zero for
-// c >= m.  All lanes of the group must call it.
-template <int OBJ, int G>
+// group's LDS, evaluated in number type T: lane c < m evaluates term c and
+// stores it in tv[k*G + c], then every lane adds the terms up in index order.
+// tv[k*G + c] must be zero for c >= m.  All lanes of the group must call it.
+template <int OBJ, int G, class T>
 __device__ __forceinline__ double group_value(const GroupLanes<G> &L, int d, const double *xs,
-                                              double *tv) {
+                                              T *tv) {
   using E = Elem<OBJ>;
   const int m = E::terms(d);
   if (L.j < m) {
-    double w[E::W], out[E::K];
+    T w[E::W], out[E::K];
 #pragma unroll
-    for (int q = 0; q < E::W; ++q) w[q] = xs[L.j + q];
-    E::template term<double>(w, out);
+    for (int q = 0; q < E::W; ++q) w[q] = (T)xs[L.j + q];
+    E::template term<T>(w, out);
 #pragma unroll
     for (int k = 0; k < E::K; ++k) tv[k * G + L.j] = out[k];
   }
   wave_sync();
-  double s[E::K];
-  ordered_sums<E::K, G>(tv, m, s);
-  return E::template outer<double>(d, s);
+  T s[E::K];
+  ordered_sums<E::K, G, T>(tv, m, s);
+  return (double)E::template outer<T>(d, s);
 }
 
-// Value and gradient at xs (forward mode, Alg. 5): lane j < d returns df/dx_j
-// in *gj; every lane returns f.  Lane j evaluates on dual numbers seeded with
-// e_j the terms whose window holds x_j (in ascending term order, the order in
-// which the full pass adds them), and its own term's value for the shared sums.
-template <int OBJ, int G>
+// Value and gradient at xs (forward mode, Alg. 5) in number type T: lane
+// j < d returns df/dx_j in *gj; every lane returns f.  Lane j evaluates on
+// dual numbers seeded with e_j the terms whose window holds x_j (in ascending
+// term order, the order in which the full pass adds them), and its own term's
+// value for the shared sums.
+template <int OBJ, int G, class T>
 __device__ __forceinline__ double group_value_grad(const GroupLanes<G> &L, int d,
-                                                   const double *xs, double *tv, double *gj) {
+                                                   const double *xs, T *tv, double *gj) {
   using E = Elem<OBJ>;
   const int m = E::terms(d);
   const int j = L.j;
-  double tan[E::K];
+  T tan[E::K];
 #pragma unroll
-  for (int k = 0; k < E::K; ++k) tan[k] = 0.0;
+  for (int k = 0; k < E::K; ++k) tan[k] = T(0);
   if (j < d) {
 #pragma unroll
     for (int back = E::W - 1; back >= 0; --back) {
       const int i = j - back;  // term i holds x_j at window slot `back`
       if (i >= 0 && i < m) {
-        dual<double> w[E::W], out[E::K];
+        dual<T> w[E::W], out[E::K];
 #pragma unroll
-        for (int q = 0; q < E::W; ++q) w[q] = dual<double>{xs[i + q], q == back ? 1.0 : 0.0};
-        E::template term<dual<double>>(w, out);
+        for (int q = 0; q < E::W; ++q) w[q] = dual<T>{(T)xs[i + q], q == back ? T(1) : T(0)};
+        E::template term<dual<T>>(w, out);
 #pragma unroll
         for (int k = 0; k < E::K; ++k) tan[k] = tan[k] + out[k].t;
         if (back == 0)
@@ -136,14 +137,14 @@ __device__ __forceinline__ double group_value_grad(const GroupLanes<G> &L, int d
     }
   }
   wave_sync();
-  double sv[E::K];
-  ordered_sums<E::K, G>(tv, m, sv);
-  dual<double> sd[E::K];
+  T sv[E::K];
+  ordered_sums<E::K, G, T>(tv, m, sv);
+  dual<T> sd[E::K];
 #pragma unroll
-  for (int k = 0; k < E::K; ++k) sd[k] = dual<double>{sv[k], tan[k]};
-  const dual<double> r = E::template outer<dual<double>>(d, sd);
-  *gj = (j < d) ? r.t : 0.0;
-  return r.v;
+  for (int k = 0; k < E::K; ++k) sd[k] = dual<T>{sv[k], tan[k]};
+  const dual<T> r = E::template outer<dual<T>>(d, sd);
+  *gj = (j < d) ? (double)r.t : 0.0;
+  return (double)r.v;
 }
 
 }  // namespace zeus

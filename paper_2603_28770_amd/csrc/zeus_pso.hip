@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(PsoArgs a) {
     }
     wave_sync();
     if (live) {
-      const double f = group_value<OBJ, G>(L, d, xs, tv);
+      const double f = group_value<OBJ, G, double>(L, d, xs, tv);
       bool improved = true;
       double pf = f;
       if (a.t > 0) {

@@ -101,7 +101,9 @@ def test_workspace_bytes(Z):
     pb = Z.make_problem(_p(n=65536, dim=10))
     b = Z.zeus_workspace_bytes(pb)
     n, d = 65536, 10
-    assert 3 * 8 * n * d + 8 * n <= b <= 3 * 8 * n * d + 8 * n + 64 * 1024
+    # swarm state x, v, px, pf plus the double-buffered block results of at
+    # most 512 blocks (value, key, index and a position each)
+    assert 3 * 8 * n * d + 8 * n <= b <= 3 * 8 * n * d + 8 * n + 2 * 512 * (d + 3) * 8 + 64 * 1024
     with pytest.raises(Z.ZeusError):
         Z.zeus_workspace_bytes(Z.make_problem(_p(dim=0)))
 
