@@ -179,6 +179,17 @@ zeus_err zeus_context_get_profile(zeus_context *ctx, zeus_profile *out);
 zeus_err zeus_minimize(zeus_context *ctx, const zeus_problem *problem,
                        const zeus_result *out);
 
+/* Blocking solve of n independent problems (a batch of uneven requests:
+ * objectives, dimensions, start counts and budgets may all differ).  outs[r]
+ * receives problem r's results (host memory, as for zeus_minimize).  Requests
+ * that share objective, precision and lane count run as one launch group:
+ * one swarm launch per sweep and one persistent BFGS launch over all their
+ * starts; different groups run concurrently on up to four streams.  Every
+ * problem is validated first; if any is invalid nothing runs and the message
+ * names it.  Each request's results are bit-identical to solving it alone. */
+zeus_err zeus_minimize_batch(zeus_context *ctx, const zeus_problem *problems, int32_t n,
+                             const zeus_result *outs);
+
 /* Asynchronous solve on `stream` (a hipStream_t; NULL = the context's stream)
  * with caller-owned device memory: `workspace` of at least
  * zeus_workspace_bytes() bytes (256-byte aligned) and device result arrays in

@@ -1,12 +1,15 @@
 // zeus_api.cpp -- the C ABI declared in include/zeus.h: validation, device
-// workspace planning, contexts, and the launch sequence of one solve:
-//   workspace init -> swarm init -> iter_pso swarm updates -> BFGS -> summary
-// all enqueued on one HIP stream with no host round trip in between.
+// workspace planning, contexts, and the launch sequence of a solve or a batch:
+//   table upload -> counter reset -> swarm sweeps -> swarm best -> BFGS ->
+//   summary
+// enqueued per launch group on one HIP stream with no host round trip in
+// between (groups of a batch on up to four streams).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -94,8 +97,7 @@ namespace zeus {
 
 namespace {
 struct Layout {
-  size_t queue, best, gx, best_store, gx_store, part_key, part_f, part_idx, part_x, x, v, px,
-      pf, total;
+  size_t best, gx, best_store, gx_store, part_key, part_f, part_idx, part_x, x, v, px, pf, total;
 };
 Layout layout(int64_t n, int dim) {
   const size_t P = (size_t)pso_blocks(n, dim), N = (size_t)n, D = (size_t)dim;
@@ -106,7 +108,6 @@ Layout layout(int64_t n, int dim) {
     o += align_up(bytes);
     return at;
   };
-  l.queue = take(sizeof(uint64_t));
   l.best = take(sizeof(PsoBest));
   l.gx = take(sizeof(double) * D);
   l.best_store = take(2 * sizeof(PsoBest));
@@ -130,7 +131,6 @@ Workspace carve_workspace(void *base, int64_t n, int dim) {
   const Layout l = layout(n, dim);
   char *p = static_cast<char *>(base);
   Workspace w;
-  w.queue = reinterpret_cast<uint64_t *>(p + l.queue);
   w.best = reinterpret_cast<PsoBest *>(p + l.best);
   w.gx = reinterpret_cast<double *>(p + l.gx);
   w.best_store = reinterpret_cast<PsoBest *>(p + l.best_store);
@@ -153,21 +153,27 @@ struct zeus_context {
   int device = 0;
   hipStream_t stream = nullptr;
   std::mutex mu;
-  // device buffers cached for the blocking entry point
+  // device buffers cached for the blocking entry points
   void *ws = nullptr;
   size_t ws_cap = 0;
   void *res = nullptr;
   size_t res_cap = 0;
+  // extra streams so that independent launch groups of a batch overlap
+  std::vector<hipStream_t> aux;
   // profiling
   bool profiling = false;
   struct Pending {
-    hipEvent_t ev[4];  // before PSO, after PSO, after BFGS, after summary
+    hipEvent_t ev[4];  // before the swarm, after the swarm, after BFGS, after summary
   };
   std::vector<Pending> pending;
   zeus_profile prof{};
 };
 
 namespace {
+
+constexpr size_t kHdrBytes = 256;  // BatchDev, padded
+
+size_t table_bytes(int nreq) { return align_up(sizeof(zeus::ReqDev) * (size_t)nreq); }
 
 zeus_err ensure(void **buf, size_t *cap, size_t need) {
   if (*cap >= need) return ZEUS_OK;
@@ -202,49 +208,194 @@ zeus_err drain_profile(zeus_context *ctx) {
   return ZEUS_OK;
 }
 
-// Enqueues the whole solve.  `out` holds device pointers.
-zeus_err enqueue_solve(zeus_context *ctx, const zeus_problem *pb, void *ws_base,
-                       const zeus_result *out, hipStream_t stream) {
-  zeus::Launch L;
-  L.pb = pb;
-  L.out = out;
-  L.ws = zeus::carve_workspace(ws_base, pb->n_starts, pb->dim);
-  L.stream = stream;
+// One request of a launch group: its problem, device outputs and workspace.
+struct Planned {
+  const zeus_problem *pb;
+  zeus_result dev;          // device pointers
+  zeus::Workspace ws;
+};
+
+// Enqueues the whole method for a group of requests that share objective,
+// precision and lane counts: table upload, counter reset, swarm sweeps
+// 0..max iter_pso, swarm finish, one BFGS launch over all their starts, one
+// summary block per request, then the optional swarm-state copies.
+zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void *hdr_table,
+                       hipStream_t stream) {
+  const zeus_problem &p0 = *reqs[0].pb;
+  zeus::Group g;
+  g.objective = p0.objective;
+  g.precision = p0.precision;
+  g.g_pso = zeus::pso_group_lanes(p0.dim);
+  g.g_bfgs = zeus::group_lanes(p0.dim);
+  g.nreq = (int)reqs.size();
+  g.max_iter_pso = 0;
+  g.pso_grid = 0;
+  g.total_starts = 0;
+  g.hdr = static_cast<zeus::BatchDev *>(hdr_table);
+  g.reqs = reinterpret_cast<const zeus::ReqDev *>(static_cast<char *>(hdr_table) + kHdrBytes);
+  g.stream = stream;
+  std::vector<zeus::ReqDev> host(reqs.size());
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const zeus_problem &p = *reqs[r].pb;
+    zeus::ReqDev &q = host[r];
+    std::memset(&q, 0, sizeof(q));
+    q.n = p.n_starts;
+    q.d = p.dim;
+    q.iter_pso = p.iter_pso;
+    q.iter_bfgs = p.iter_bfgs;
+    q.iter_ls = p.iter_ls;
+    q.trace_len = reqs[r].dev.trace ? reqs[r].dev.trace_len : 0;
+    q.lo = p.lower;
+    q.hi = p.upper;
+    q.vh = p.v_half > 0.0 ? p.v_half : (p.upper - p.lower);
+    q.w = p.w;
+    q.c1 = p.c1;
+    q.c2 = p.c2;
+    q.armijo_c = p.armijo_c;
+    q.shrink = p.ls_shrink;
+    q.tol = p.grad_tol;
+    q.k0 = p.seed;
+    q.k1 = p.request_id;
+    q.ws = reqs[r].ws;
+    q.out_f = reqs[r].dev.f;
+    q.out_x = reqs[r].dev.x;
+    q.out_iters = reqs[r].dev.iters;
+    q.out_status = reqs[r].dev.status;
+    q.out_ls = reqs[r].dev.ls_trials;
+    q.trace = q.trace_len ? reqs[r].dev.trace : nullptr;
+    q.summary = reqs[r].dev.summary;
+    q.start_offset = g.total_starts;
+    q.block_offset = g.pso_grid;
+    g.total_starts += p.n_starts;
+    g.pso_grid += q.ws.pso_blocks;
+    if (p.iter_pso > g.max_iter_pso) g.max_iter_pso = p.iter_pso;
+  }
+  hipError_t e = hipMemcpyAsync(const_cast<zeus::ReqDev *>(g.reqs), host.data(),
+                                sizeof(zeus::ReqDev) * host.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "request table upload");
   zeus_context::Pending pend{};
   const bool prof = ctx->profiling;
   if (prof)
     for (auto &ev : pend.ev)
       if (hipEventCreate(&ev) != hipSuccess) return fail(ZEUS_EHIP, "hipEventCreate failed");
-  hipError_t e;
   if (prof) (void)hipEventRecord(pend.ev[0], stream);
-  if ((e = zeus::launch_ws_init(L)) != hipSuccess) return hip_fail(e, "workspace init launch");
-  if ((e = zeus::launch_pso_init(L)) != hipSuccess) return hip_fail(e, "swarm init launch");
-  for (int t = 1; t <= pb->iter_pso; ++t)
-    if ((e = zeus::launch_pso_step(L, t)) != hipSuccess) return hip_fail(e, "swarm update launch");
-  if ((e = zeus::launch_pso_finish(L)) != hipSuccess) return hip_fail(e, "swarm best launch");
+  if ((e = zeus::launch_ws_init(g)) != hipSuccess) return hip_fail(e, "counter reset launch");
+  for (int t = 0; t <= g.max_iter_pso; ++t)
+    if ((e = zeus::launch_pso(g, t)) != hipSuccess) return hip_fail(e, "swarm launch");
+  if ((e = zeus::launch_pso_finish(g)) != hipSuccess) return hip_fail(e, "swarm best launch");
   if (prof) (void)hipEventRecord(pend.ev[1], stream);
-  if ((e = zeus::launch_bfgs(L)) != hipSuccess) return hip_fail(e, "BFGS launch");
+  if ((e = zeus::launch_bfgs(g)) != hipSuccess) return hip_fail(e, "BFGS launch");
   if (prof) (void)hipEventRecord(pend.ev[2], stream);
-  if ((e = zeus::launch_summary(L)) != hipSuccess) return hip_fail(e, "summary launch");
+  if ((e = zeus::launch_summary(g)) != hipSuccess) return hip_fail(e, "summary launch");
   if (prof) (void)hipEventRecord(pend.ev[3], stream);
-  const size_t nd = sizeof(double) * (size_t)pb->n_starts * pb->dim;
-  const size_t n8 = sizeof(double) * (size_t)pb->n_starts;
-  struct Copy {
-    void *dst;
-    const void *src;
-    size_t bytes;
-  } copies[] = {{out->seeds, L.ws.x, nd}, {out->pso_v, L.ws.v, nd}, {out->pso_px, L.ws.px, nd},
-                {out->pso_pf, L.ws.pf, n8}, {out->pso_best_x, L.ws.gx, sizeof(double) * pb->dim}};
-  for (auto &c : copies)
-    if (c.dst && (e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
-      return hip_fail(e, "hipMemcpyAsync");
+  for (const Planned &q : reqs) {
+    const size_t nd = sizeof(double) * (size_t)q.pb->n_starts * q.pb->dim;
+    const size_t n8 = sizeof(double) * (size_t)q.pb->n_starts;
+    struct Copy {
+      void *dst;
+      const void *src;
+      size_t bytes;
+    } copies[] = {{q.dev.seeds, q.ws.x, nd}, {q.dev.pso_v, q.ws.v, nd}, {q.dev.pso_px, q.ws.px, nd},
+                  {q.dev.pso_pf, q.ws.pf, n8}, {q.dev.pso_best_x, q.ws.gx, sizeof(double) * q.pb->dim}};
+    for (auto &c : copies)
+      if (c.dst && (e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+  }
   if (prof) {
     ctx->pending.push_back(pend);
-    ctx->prof.pso_launches += 3 + pb->iter_pso;
+    ctx->prof.pso_launches += 3 + g.max_iter_pso;
     ctx->prof.bfgs_launches += 1;
     ctx->prof.reduce_launches += 1;
   }
   return ZEUS_OK;
+}
+
+// Device result layout of one request for the blocking entry points.
+struct ResLayout {
+  size_t f, x, it, st, ls, seed, v, px, pf, gx, tr, sum, total;
+};
+
+ResLayout res_layout(const zeus_problem &pb, const zeus_result &out) {
+  const size_t n = (size_t)pb.n_starts, d = (size_t)pb.dim;
+  const size_t tl = out.trace ? (size_t)out.trace_len : 0;
+  ResLayout l;
+  size_t o = 0;
+  l.f = o; o += align_up(8 * n);
+  l.x = o; o += align_up(8 * n * d);
+  l.it = o; o += align_up(4 * n);
+  l.st = o; o += align_up(4 * n);
+  l.ls = o; o += out.ls_trials ? align_up(4 * n) : 0;
+  l.seed = o; o += out.seeds ? align_up(8 * n * d) : 0;
+  l.v = o; o += out.pso_v ? align_up(8 * n * d) : 0;
+  l.px = o; o += out.pso_px ? align_up(8 * n * d) : 0;
+  l.pf = o; o += out.pso_pf ? align_up(8 * n) : 0;
+  l.gx = o; o += out.pso_best_x ? align_up(8 * d) : 0;
+  l.tr = o; o += tl ? align_up(8 * n * tl * d) : 0;
+  l.sum = o; o += align_up(sizeof(zeus_summary));
+  l.total = o;
+  return l;
+}
+
+zeus_result carve_result(char *R, const ResLayout &l, const zeus_result &out) {
+  zeus_result dev{};
+  dev.f = reinterpret_cast<double *>(R + l.f);
+  dev.x = reinterpret_cast<double *>(R + l.x);
+  dev.iters = reinterpret_cast<int32_t *>(R + l.it);
+  dev.status = reinterpret_cast<int32_t *>(R + l.st);
+  dev.ls_trials = out.ls_trials ? reinterpret_cast<int32_t *>(R + l.ls) : nullptr;
+  dev.seeds = out.seeds ? reinterpret_cast<double *>(R + l.seed) : nullptr;
+  dev.pso_v = out.pso_v ? reinterpret_cast<double *>(R + l.v) : nullptr;
+  dev.pso_px = out.pso_px ? reinterpret_cast<double *>(R + l.px) : nullptr;
+  dev.pso_pf = out.pso_pf ? reinterpret_cast<double *>(R + l.pf) : nullptr;
+  dev.pso_best_x = out.pso_best_x ? reinterpret_cast<double *>(R + l.gx) : nullptr;
+  dev.trace = out.trace && out.trace_len ? reinterpret_cast<double *>(R + l.tr) : nullptr;
+  dev.trace_len = dev.trace ? out.trace_len : 0;
+  dev.summary = reinterpret_cast<zeus_summary *>(R + l.sum);
+  return dev;
+}
+
+zeus_err copy_back(const zeus_problem &pb, const zeus_result &out, const zeus_result &dev,
+                   hipStream_t s) {
+  const size_t n = (size_t)pb.n_starts, d = (size_t)pb.dim;
+  const size_t tl = dev.trace ? (size_t)dev.trace_len : 0;
+  struct Back {
+    void *dst;
+    const void *src;
+    size_t bytes;
+  } backs[] = {{out.f, dev.f, 8 * n},
+               {out.x, dev.x, 8 * n * d},
+               {out.iters, dev.iters, 4 * n},
+               {out.status, dev.status, 4 * n},
+               {out.ls_trials, dev.ls_trials, 4 * n},
+               {out.seeds, dev.seeds, 8 * n * d},
+               {out.pso_v, dev.pso_v, 8 * n * d},
+               {out.pso_px, dev.pso_px, 8 * n * d},
+               {out.pso_pf, dev.pso_pf, 8 * n},
+               {out.pso_best_x, dev.pso_best_x, 8 * d},
+               {out.trace, dev.trace, 8 * n * tl * d},
+               {out.summary, dev.summary, sizeof(zeus_summary)}};
+  for (auto &b : backs)
+    if (b.dst && b.src && b.bytes) {
+      hipError_t e = hipMemcpyAsync(b.dst, b.src, b.bytes, hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
+    }
+  return ZEUS_OK;
+}
+
+// Launch groups of a batch: requests that share objective, precision and
+// lane counts run in one group.
+struct GroupKey {
+  int objective, precision, g_pso, g_bfgs;
+  bool operator<(const GroupKey &o) const {
+    if (objective != o.objective) return objective < o.objective;
+    if (precision != o.precision) return precision < o.precision;
+    if (g_pso != o.g_pso) return g_pso < o.g_pso;
+    return g_bfgs < o.g_bfgs;
+  }
+};
+
+GroupKey key_of(const zeus_problem &p) {
+  return GroupKey{p.objective, p.precision, zeus::pso_group_lanes(p.dim), zeus::group_lanes(p.dim)};
 }
 
 }  // namespace
@@ -253,7 +404,7 @@ extern "C" {
 
 uint32_t zeus_abi_version(void) { return ZEUS_ABI_VERSION; }
 
-const char *zeus_version(void) { return "zeus-mi355x 0.1.0 (gfx950)"; }
+const char *zeus_version(void) { return "zeus-mi355x 0.2.0 (gfx950)"; }
 
 const char *zeus_last_error(void) { return g_last_error.c_str(); }
 
@@ -267,7 +418,7 @@ zeus_err zeus_workspace_bytes(const zeus_problem *problem, size_t *bytes) {
   if (!bytes) return fail(ZEUS_EINVAL, "bytes is NULL");
   zeus_err e = check_problem(problem);
   if (e != ZEUS_OK) return e;
-  *bytes = zeus::workspace_bytes(problem->n_starts, problem->dim);
+  *bytes = kHdrBytes + table_bytes(1) + zeus::workspace_bytes(problem->n_starts, problem->dim);
   return ZEUS_OK;
 }
 
@@ -303,9 +454,11 @@ zeus_err zeus_context_destroy(zeus_context *ctx) {
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
     (void)hipStreamSynchronize(ctx->stream);
+    for (hipStream_t s : ctx->aux) (void)hipStreamSynchronize(s);
     (void)drain_profile(ctx);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->res) (void)hipFree(ctx->res);
+    for (hipStream_t s : ctx->aux) (void)hipStreamDestroy(s);
     (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;
@@ -341,7 +494,8 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, voi
   if (e != ZEUS_OK) return e;
   if ((e = check_result(out, problem)) != ZEUS_OK) return e;
   const zeus_problem pb = *problem;
-  const size_t need = zeus::workspace_bytes(pb.n_starts, pb.dim);
+  size_t need = 0;
+  (void)zeus_workspace_bytes(&pb, &need);
   if (!workspace || workspace_bytes < need)
     return fail(ZEUS_EINVAL, "workspace missing or smaller than zeus_workspace_bytes()");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
@@ -350,82 +504,99 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, voi
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
-  return enqueue_solve(ctx, &pb, workspace, out, s);
+  char *base = static_cast<char *>(workspace);
+  std::vector<Planned> one(1);
+  one[0].pb = &pb;
+  one[0].dev = *out;
+  if (!one[0].dev.trace || one[0].dev.trace_len == 0) {
+    one[0].dev.trace = nullptr;
+    one[0].dev.trace_len = 0;
+  }
+  one[0].ws = zeus::carve_workspace(base + kHdrBytes + table_bytes(1), pb.n_starts, pb.dim);
+  return enqueue_group(ctx, one, base, s);
 }
 
 zeus_err zeus_minimize(zeus_context *ctx, const zeus_problem *problem, const zeus_result *out) {
+  return zeus_minimize_batch(ctx, problem, 1, out);
+}
+
+zeus_err zeus_minimize_batch(zeus_context *ctx, const zeus_problem *problems, int32_t n,
+                             const zeus_result *outs) {
   g_last_error.clear();
   if (!ctx) return fail(ZEUS_EINVAL, "ctx is NULL");
-  zeus_err e = check_problem(problem);
-  if (e != ZEUS_OK) return e;
-  if ((e = check_result(out, problem)) != ZEUS_OK) return e;
-  const zeus_problem pb = *problem;
-  const size_t n = (size_t)pb.n_starts, d = (size_t)pb.dim;
-  const size_t tl = out->trace ? (size_t)out->trace_len : 0;
-  // device result layout (each piece 256-aligned)
-  size_t off_f = 0, off_x, off_it, off_st, off_ls, off_seed, off_v, off_px, off_pf, off_gx,
-         off_tr, off_sum, total;
-  {
-    size_t o = 0;
-    off_f = o; o += align_up(8 * n);
-    off_x = o; o += align_up(8 * n * d);
-    off_it = o; o += align_up(4 * n);
-    off_st = o; o += align_up(4 * n);
-    off_ls = o; o += out->ls_trials ? align_up(4 * n) : 0;
-    off_seed = o; o += out->seeds ? align_up(8 * n * d) : 0;
-    off_v = o; o += out->pso_v ? align_up(8 * n * d) : 0;
-    off_px = o; o += out->pso_px ? align_up(8 * n * d) : 0;
-    off_pf = o; o += out->pso_pf ? align_up(8 * n) : 0;
-    off_gx = o; o += out->pso_best_x ? align_up(8 * d) : 0;
-    off_tr = o; o += tl ? align_up(8 * n * tl * d) : 0;
-    off_sum = o; o += align_up(sizeof(zeus_summary));
-    total = o;
+  if (n < 1 || !problems || !outs) return fail(ZEUS_EINVAL, "need n >= 1 problems and results");
+  for (int32_t r = 0; r < n; ++r) {
+    zeus_err e = check_problem(&problems[r]);
+    if (e == ZEUS_OK) e = check_result(&outs[r], &problems[r]);
+    if (e != ZEUS_OK) return fail(e, "request " + std::to_string(r) + ": " + g_last_error);
   }
-  DeviceGuard g(ctx->device);
-  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  // groups, in the order of their first request
+  std::map<GroupKey, std::vector<int32_t>> groups;
+  std::vector<GroupKey> order;
+  for (int32_t r = 0; r < n; ++r) {
+    const GroupKey k = key_of(problems[r]);
+    auto it = groups.find(k);
+    if (it == groups.end()) {
+      order.push_back(k);
+      groups[k].push_back(r);
+    } else {
+      it->second.push_back(r);
+    }
+  }
+  // one allocation for results, one for workspaces and tables
+  std::vector<ResLayout> rl(n);
+  std::vector<size_t> res_off(n), ws_off(n);
+  size_t res_total = 0, ws_total = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    rl[r] = res_layout(problems[r], outs[r]);
+    res_off[r] = res_total;
+    res_total += rl[r].total;
+    ws_off[r] = ws_total;
+    ws_total += zeus::workspace_bytes(problems[r].n_starts, problems[r].dim);
+  }
+  std::vector<size_t> tab_off(order.size());
+  for (size_t gi = 0; gi < order.size(); ++gi) {
+    tab_off[gi] = ws_total;
+    ws_total += kHdrBytes + table_bytes((int)groups[order[gi]].size());
+  }
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if ((e = ensure(&ctx->ws, &ctx->ws_cap, zeus::workspace_bytes(pb.n_starts, pb.dim))) != ZEUS_OK)
-    return e;
-  if ((e = ensure(&ctx->res, &ctx->res_cap, total)) != ZEUS_OK) return e;
-  char *R = static_cast<char *>(ctx->res);
-  zeus_result dev{};
-  dev.f = reinterpret_cast<double *>(R + off_f);
-  dev.x = reinterpret_cast<double *>(R + off_x);
-  dev.iters = reinterpret_cast<int32_t *>(R + off_it);
-  dev.status = reinterpret_cast<int32_t *>(R + off_st);
-  dev.ls_trials = out->ls_trials ? reinterpret_cast<int32_t *>(R + off_ls) : nullptr;
-  dev.seeds = out->seeds ? reinterpret_cast<double *>(R + off_seed) : nullptr;
-  dev.pso_v = out->pso_v ? reinterpret_cast<double *>(R + off_v) : nullptr;
-  dev.pso_px = out->pso_px ? reinterpret_cast<double *>(R + off_px) : nullptr;
-  dev.pso_pf = out->pso_pf ? reinterpret_cast<double *>(R + off_pf) : nullptr;
-  dev.pso_best_x = out->pso_best_x ? reinterpret_cast<double *>(R + off_gx) : nullptr;
-  dev.trace = tl ? reinterpret_cast<double *>(R + off_tr) : nullptr;
-  dev.trace_len = (int32_t)tl;
-  dev.summary = reinterpret_cast<zeus_summary *>(R + off_sum);
-  if ((e = enqueue_solve(ctx, &pb, ctx->ws, &dev, ctx->stream)) != ZEUS_OK) return e;
+  zeus_err e;
+  if ((e = ensure(&ctx->ws, &ctx->ws_cap, ws_total)) != ZEUS_OK) return e;
+  if ((e = ensure(&ctx->res, &ctx->res_cap, res_total)) != ZEUS_OK) return e;
+  // independent groups run on separate streams so that their kernels overlap
+  const size_t want_streams = order.size() < 4 ? order.size() : 4;
+  while (ctx->aux.size() + 1 < want_streams) {
+    hipStream_t s;
+    hipError_t he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_fail(he, "hipStreamCreate");
+    ctx->aux.push_back(s);
+  }
+  std::vector<zeus_result> dev(n);
+  for (int32_t r = 0; r < n; ++r)
+    dev[r] = carve_result(static_cast<char *>(ctx->res) + res_off[r], rl[r], outs[r]);
+  for (size_t gi = 0; gi < order.size(); ++gi) {
+    hipStream_t s = gi % want_streams == 0 ? ctx->stream : ctx->aux[gi % want_streams - 1];
+    const std::vector<int32_t> &members = groups[order[gi]];
+    std::vector<Planned> plan(members.size());
+    for (size_t k = 0; k < members.size(); ++k) {
+      const int32_t r = members[k];
+      plan[k].pb = &problems[r];
+      plan[k].dev = dev[r];
+      plan[k].ws = zeus::carve_workspace(static_cast<char *>(ctx->ws) + ws_off[r],
+                                         problems[r].n_starts, problems[r].dim);
+    }
+    if ((e = enqueue_group(ctx, plan, static_cast<char *>(ctx->ws) + tab_off[gi], s)) != ZEUS_OK)
+      return e;
+    for (int32_t r : members)
+      if ((e = copy_back(problems[r], outs[r], dev[r], s)) != ZEUS_OK) return e;
+  }
   hipError_t he;
-  struct Back {
-    void *dst;
-    const void *src;
-    size_t bytes;
-  } backs[] = {{out->f, dev.f, 8 * n},
-               {out->x, dev.x, 8 * n * d},
-               {out->iters, dev.iters, 4 * n},
-               {out->status, dev.status, 4 * n},
-               {out->ls_trials, dev.ls_trials, 4 * n},
-               {out->seeds, dev.seeds, 8 * n * d},
-               {out->pso_v, dev.pso_v, 8 * n * d},
-               {out->pso_px, dev.pso_px, 8 * n * d},
-               {out->pso_pf, dev.pso_pf, 8 * n},
-               {out->pso_best_x, dev.pso_best_x, 8 * d},
-               {out->trace, dev.trace, 8 * n * tl * d},
-               {out->summary, dev.summary, sizeof(zeus_summary)}};
-  for (auto &b : backs)
-    if (b.dst && b.bytes &&
-        (he = hipMemcpyAsync(b.dst, b.src, b.bytes, hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
-      return hip_fail(he, "hipMemcpyAsync D2H");
-  if ((he = hipStreamSynchronize(ctx->stream)) != hipSuccess)
-    return hip_fail(he, "hipStreamSynchronize");
+  if ((he = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
+  for (size_t k = 0; k + 1 < want_streams; ++k)
+    if ((he = hipStreamSynchronize(ctx->aux[k])) != hipSuccess)
+      return hip_fail(he, "hipStreamSynchronize");
   return ZEUS_OK;
 }
 

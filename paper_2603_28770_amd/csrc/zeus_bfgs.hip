@@ -30,22 +30,15 @@
 namespace zeus {
 namespace {
 
-struct BfgsArgs {
-  int64_t n;
-  int d;
-  int iter_bfgs;
-  int iter_ls;
-  int trace_len;
-  double armijo_c, shrink, tol;
-  const double *x0;   // [n][d] starting points
-  uint64_t *queue;    // next unclaimed start
-  double *out_f;
-  double *out_x;
-  int32_t *out_iters;
-  int32_t *out_status;
-  int32_t *out_ls;    // nullable
-  double *trace;      // nullable, [n][trace_len][d]
-  int trials_per_round;  // R, a power of two <= G
+// A start's request, as a group keeps it while working on the start.
+struct ReqLocal {
+  int d, m, dp, mp;          // dimension, terms, both padded to the chunk size
+  int iter_bfgs, iter_ls, trace_len;
+  double armijo_c, tol;
+  const double *x0;
+  double *out_f, *out_x;
+  int32_t *out_iters, *out_status, *out_ls;
+  double *trace;
 };
 
 // Per-group LDS slice.  Every vector is zero beyond the dimension, so the
@@ -58,17 +51,18 @@ struct GroupShm {
   double *ss;  // [G] s = x_new - x
   double *us;  // [G] u = H y
   double *tg;  // [K][G] term values of a gradient evaluation
-  double *tt;  // [K][R][mp] term values of the trials of a line-search round
+  double *tt;  // [K][R][G] term values of the trials of a line-search round
+  double *al;  // [kTabTrials] step lengths of the start's request
 };
-
-// Doubles per group slice (mp = m rounded up to the chunk size).
-__device__ __host__ __forceinline__ int group_stride(int G, int K, int R, int mp) {
-  return 6 * G + K * G + K * R * mp;
-}
 
 // Step lengths alpha_t = shrink^t of the first kTabTrials trials, each the
 // product of the previous one and shrink, as Alg. 6 forms them.
-constexpr int kTabTrials = 64;
+constexpr int kTabTrials = 32;
+
+// Doubles per group slice.
+__device__ __host__ __forceinline__ int group_stride(int G, int K, int R) {
+  return 6 * G + K * G + K * R * G + kTabTrials;
+}
 
 // One Armijo search (Alg. 6) with the objective evaluated in number type U.
 // A round evaluates R consecutive trials of the sequence at once, each spread
@@ -76,36 +70,35 @@ constexpr int kTabTrials = 64;
 // first trial that passes is the step Alg. 6 returns.  Returns its index, or
 // -1 when none of the iter_ls trials passes.
 template <int OBJ, int G, class U>
-__device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const BfgsArgs &a,
-                                             const double *alpha_tab, const GroupShm &sh, int d,
-                                             int m, int mp, int R, uint64_t leaders, double f,
-                                             double ddir) {
+__device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const ReqLocal &q,
+                                             double shrink, const GroupShm &sh, int R,
+                                             uint64_t leaders, double f, double ddir) {
   using E = Elem<OBJ>;
   const int tp = G / R, trial_slot = L.j / tp, term_slot = L.j % tp;
-  U *tvr = reinterpret_cast<U *>(sh.tt) + trial_slot * mp;
-  for (int base = 0; base < a.iter_ls; base += R) {
+  U *tvr = reinterpret_cast<U *>(sh.tt) + trial_slot * G;
+  for (int base = 0; base < q.iter_ls; base += R) {
     const int t = base + trial_slot;
     double alpha;
     if (t < kTabTrials) {
-      alpha = alpha_tab[t];
+      alpha = sh.al[t];
     } else {
-      alpha = alpha_tab[kTabTrials - 1];
-      for (int q = kTabTrials - 1; q < t; ++q) alpha = alpha * a.shrink;
+      alpha = sh.al[kTabTrials - 1];
+      for (int e = kTabTrials - 1; e < t; ++e) alpha = alpha * shrink;
     }
-    for (int i = term_slot; i < m; i += tp) {
+    for (int i = term_slot; i < q.m; i += tp) {
       U w[E::W], out[E::K];
 #pragma unroll
-      for (int q = 0; q < E::W; ++q) w[q] = (U)(sh.xs[i + q] + alpha * sh.ps[i + q]);
+      for (int e = 0; e < E::W; ++e) w[e] = (U)(sh.xs[i + e] + alpha * sh.ps[i + e]);
       E::template term<U>(w, out);
 #pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) tvr[kk * R * mp + i] = out[kk];
+      for (int kk = 0; kk < E::K; ++kk) tvr[kk * R * G + i] = out[kk];
     }
     wave_sync();
     U sums[E::K];
 #pragma unroll
-    for (int kk = 0; kk < E::K; ++kk) sums[kk] = sum_ordered<G, U>(tvr + kk * R * mp, mp);
-    const double ft = (double)E::template outer<U>(d, sums);
-    const bool ok = t < a.iter_ls && ft <= f + (a.armijo_c * alpha) * ddir;
+    for (int kk = 0; kk < E::K; ++kk) sums[kk] = sum_ordered<G, U>(tvr + kk * R * G, q.mp);
+    const double ft = (double)E::template outer<U>(q.d, sums);
+    const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
     const uint64_t hit = L.ballot(ok) & leaders;
     wave_sync();  // every lane has read the term buffer before it is reused
     if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1) / tp;
@@ -124,32 +117,17 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const BfgsA
 // no step.  Convergence and non-finite outcomes are therefore always decided
 // on FP64 values; the value reported for a start is FP64 at its final x.
 template <int OBJ, int G, class T>
-__global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
+__global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, int nreq,
+                                                          BatchDev *hdr, int64_t total, int R) {
   using E = Elem<OBJ>;
   constexpr bool kMixed = sizeof(T) != sizeof(double);
   constexpr int S = 64 / G;  // groups per wave
   extern __shared__ double smem[];
   const GroupLanes<G> L;
   const int j = L.j;
-  const int d = a.d;
-  const bool own = j < d;
-  const int m = E::terms(d);
-  const int dp = Chunk<G>::padded(d), mp = Chunk<G>::padded(m);
-  const int R = a.trials_per_round;      // line-search trials per round
-  uint64_t leaders = 0;                  // bit r*(G/R) of every trial r of a round
+  uint64_t leaders = 0;      // bit r*(G/R) of every trial r of a round
   for (int r = 0; r < R; ++r) leaders |= 1ull << (r * (G / R));
-
-  __shared__ double alpha_tab[kTabTrials];
-  const int stride = group_stride(G, E::K, R, mp);
-  for (int i = threadIdx.x; i < stride * (kBfgsBlock / G); i += kBfgsBlock) smem[i] = 0.0;
-  if (threadIdx.x == 0) {
-    double al = 1.0;
-    for (int t = 0; t < kTabTrials; ++t) {
-      alpha_tab[t] = al;
-      al = al * a.shrink;
-    }
-  }
-  __syncthreads();
+  const int stride = group_stride(G, E::K, R);
   GroupShm sh;
   {
     double *base = smem + (size_t)((threadIdx.x >> 6) * S + L.grp) * stride;
@@ -161,8 +139,12 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     sh.us = base + 5 * G;
     sh.tg = base + 6 * G;
     sh.tt = base + 6 * G + E::K * G;
+    sh.al = base + 6 * G + E::K * G + E::K * R * G;
   }
 
+  ReqLocal q{};
+  double shrink = 0.5;
+  bool own = false;
   double h[G];  // row j of H; h[c] = 0 for c >= d except h[j] = 1 when j >= d
   double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
   int64_t idx = -1;
@@ -171,7 +153,7 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
   bool hi = !kMixed;  // evaluating in FP64 (always, unless mixed precision)
   // term buffers back to zero (their padding), e.g. between FP32 and FP64 use
   auto zero_terms = [&]() {
-    for (int q = j; q < E::K * G + E::K * R * mp; q += G) sh.tg[q] = 0.0;
+    for (int e = j; e < E::K * G + E::K * R * G; e += G) sh.tg[e] = 0.0;
     wave_sync();
   };
 
@@ -179,11 +161,43 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     // -- claim a start when idle ------------------------------------------
     if (idx < 0) {
       unsigned long long got = 0;
-      if (j == 0) got = atomicAdd((unsigned long long *)a.queue, 1ull);
+      if (j == 0) got = atomicAdd((unsigned long long *)&hdr->queue, 1ull);
       got = __shfl(got, L.grp * G, 64);
-      if (got >= (unsigned long long)a.n) break;
-      idx = (int64_t)got;
-      xj = own ? a.x0[idx * d + j] : 0.0;  // x <- swarm[i]
+      if (got >= (unsigned long long)total) break;
+      // the request holding global start `got`
+      int lo = 0, hi2 = nreq - 1;
+      while (lo < hi2) {
+        const int mid = (lo + hi2 + 1) >> 1;
+        if (reqs[mid].start_offset <= (int64_t)got) lo = mid;
+        else hi2 = mid - 1;
+      }
+      const ReqDev &rq = reqs[lo];
+      idx = (int64_t)got - rq.start_offset;
+      q.d = rq.d;
+      q.m = E::terms(q.d);
+      q.dp = Chunk<G>::padded(q.d);
+      q.mp = Chunk<G>::padded(q.m);
+      q.iter_bfgs = rq.iter_bfgs;
+      q.iter_ls = rq.iter_ls;
+      q.trace_len = rq.trace ? rq.trace_len : 0;
+      q.armijo_c = rq.armijo_c;
+      q.tol = rq.tol;
+      q.x0 = rq.ws.x;
+      q.out_f = rq.out_f;
+      q.out_x = rq.out_x;
+      q.out_iters = rq.out_iters;
+      q.out_status = rq.out_status;
+      q.out_ls = rq.out_ls;
+      q.trace = rq.trace;
+      shrink = rq.shrink;
+      own = j < q.d;
+      zero_terms();
+      for (int t = j; t < kTabTrials; t += G) {  // step lengths of this request
+        double al = 1.0;
+        for (int e = 0; e < t; ++e) al = al * shrink;
+        sh.al[t] = al;
+      }
+      xj = own ? q.x0[idx * q.d + j] : 0.0;  // x <- swarm[i]
       sh.xs[j] = xj;
 #pragma unroll
       for (int c = 0; c < G; ++c) h[c] = (c == j) ? 1.0 : 0.0;  // H <- I
@@ -191,9 +205,9 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
       ls_trials = 0;
       fresh = true;
       hi = !kMixed;
-      if (kMixed) zero_terms();
     }
     wave_sync();
+    const int d = q.d, dp = q.dp;
 
     // -- value and gradient at xs (dual numbers, one direction per lane) ----
     double gn, fn;
@@ -238,13 +252,13 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     fresh = false;
     sh.gs[j] = gj;
     wave_sync();
-    if (a.trace && own && k < a.trace_len) a.trace[(idx * a.trace_len + k) * d + j] = xj;
+    if (q.trace_len && own && k < q.trace_len) q.trace[(idx * q.trace_len + k) * d + j] = xj;
 
     // -- termination: non-finite, ||g|| < Theta, budget ---------------------
     const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
     const bool any_bad = L.ballot(bad) != 0ull;
     const double gg = dot_ordered<G>(sh.gs, sh.gs, dp);
-    if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * a.tol)) {
+    if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * q.tol)) {
       hi = true;  // escalate: re-evaluate this point in FP64
       fresh = true;
       zero_terms();
@@ -253,12 +267,12 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     int status = -1;
     if (any_bad)
       status = ZEUS_ST_NONFINITE;
-    else if (sqrt(gg) < a.tol)
+    else if (sqrt(gg) < q.tol)
       status = ZEUS_ST_CONVERGED;
-    else if (k == a.iter_bfgs)
+    else if (k == q.iter_bfgs)
       status = ZEUS_ST_MAXITER;
     if (status >= 0) {
-      if (own) a.out_x[idx * d + j] = xj;
+      if (own) q.out_x[idx * d + j] = xj;
       if (kMixed && !hi) {
         // FP64 value at the returned x (ys and ss are free until the next step)
 #pragma unroll
@@ -267,14 +281,14 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
         f = group_value<OBJ, G, double>(L, d, sh.xs, sh.ys);
       }
       if (j == 0) {
-        a.out_f[idx] = f;
-        a.out_iters[idx] = k;
-        a.out_status[idx] = status;
-        if (a.out_ls) a.out_ls[idx] = ls_trials;
+        q.out_f[idx] = f;
+        q.out_iters[idx] = k;
+        q.out_status[idx] = status;
+        if (q.out_ls) q.out_ls[idx] = ls_trials;
       }
-      if (a.trace && own)
-        for (int kk = k + 1; kk < a.trace_len; ++kk)
-          a.trace[(idx * a.trace_len + kk) * d + j] = __builtin_nan("");
+      if (q.trace_len && own)
+        for (int kk = k + 1; kk < q.trace_len; ++kk)
+          q.trace[(idx * q.trace_len + kk) * d + j] = __builtin_nan("");
       idx = -1;
       continue;
     }
@@ -299,25 +313,25 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
     // -- Armijo backtracking (Alg. 6) ---------------------------------------
     int taken;
     if (hi) {
-      taken = armijo_search<OBJ, G, double>(L, a, alpha_tab, sh, d, m, mp, R, leaders, f, ddir);
+      taken = armijo_search<OBJ, G, double>(L, q, shrink, sh, R, leaders, f, ddir);
     } else {
-      taken = armijo_search<OBJ, G, T>(L, a, alpha_tab, sh, d, m, mp, R, leaders, f, ddir);
+      taken = armijo_search<OBJ, G, T>(L, q, shrink, sh, R, leaders, f, ddir);
       if (taken < 0) {
-        ls_trials += a.iter_ls;
+        ls_trials += q.iter_ls;
         hi = true;  // escalate: FP32 cannot resolve this decrease
         fresh = true;
         zero_terms();
         continue;
       }
     }
-    const int nshrink = taken >= 0 ? taken : a.iter_ls;
-    ls_trials += taken >= 0 ? taken + 1 : a.iter_ls;
+    const int nshrink = taken >= 0 ? taken : q.iter_ls;
+    ls_trials += taken >= 0 ? taken + 1 : q.iter_ls;
     double alpha;
     if (nshrink < kTabTrials) {
-      alpha = alpha_tab[nshrink];
+      alpha = sh.al[nshrink];
     } else {
-      alpha = alpha_tab[kTabTrials - 1];
-      for (int q = kTabTrials - 1; q < nshrink; ++q) alpha = alpha * a.shrink;
+      alpha = sh.al[kTabTrials - 1];
+      for (int e = kTabTrials - 1; e < nshrink; ++e) alpha = alpha * shrink;
     }
 
     // -- step ----------------------------------------------------------------
@@ -327,18 +341,17 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(BfgsArgs a) {
   }
 }
 
-// Best-of-N and counts over all starts (one block; deterministic).
+// Best-of-N and counts over all starts of one request per block
+// (deterministic: (f, index) minimum over finite f, exact integer sums).
 constexpr int kSumBlock = 1024;
 
-__global__ __launch_bounds__(kSumBlock) void summary_kernel(int64_t n, const double *f,
-                                                            const int32_t *status,
-                                                            const int32_t *iters,
-                                                            const int32_t *ls,
-                                                            const PsoBest *pso,
-                                                            zeus_summary *out) {
+__global__ __launch_bounds__(kSumBlock) void summary_kernel(const ReqDev *reqs) {
   __shared__ double sk[kSumBlock / 64];
   __shared__ int64_t si[kSumBlock / 64];
   __shared__ int64_t sc[4][kSumBlock / 64];
+  const ReqDev &rq = reqs[blockIdx.x];
+  const int64_t n = rq.n;
+  const double *f = rq.out_f;
   double key = __builtin_huge_val();
   int64_t idx = INT64_MAX;
   int64_t nconv = 0, nnf = 0, it = 0, lt = 0;
@@ -348,11 +361,11 @@ __global__ __launch_bounds__(kSumBlock) void summary_kernel(int64_t n, const dou
       key = fi;
       idx = i;
     }
-    const int32_t st = status[i];
+    const int32_t st = rq.out_status[i];
     nconv += st == ZEUS_ST_CONVERGED;
     nnf += st == ZEUS_ST_NONFINITE;
-    it += iters[i];
-    if (ls) lt += ls[i];
+    it += rq.out_iters[i];
+    if (rq.out_ls) lt += rq.out_ls[i];
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -389,62 +402,60 @@ __global__ __launch_bounds__(kSumBlock) void summary_kernel(int64_t n, const dou
       lt += sc[3][wv];
     }
     const bool found = idx != INT64_MAX;
+    zeus_summary *out = rq.summary;
     out->best_index = found ? idx : -1;
     out->best_f = found ? f[idx] : __builtin_nan("");
     out->n_converged = nconv;
     out->n_nonfinite = nnf;
     out->total_iters = it;
     out->total_ls_trials = lt;
-    out->pso_best_index = pso->idx;
-    out->pso_best_f = pso->f;
+    out->pso_best_index = rq.ws.best->idx;
+    out->pso_best_f = rq.ws.best->f;
   }
 }
 
 template <int OBJ, int G, class T>
-hipError_t launch_g(const BfgsArgs &a, int blocks, hipStream_t s) {
+hipError_t launch_g(const Group &g, int R, int blocks) {
   using E = Elem<OBJ>;
-  const int m = E::terms(a.d);
-  const int R = a.trials_per_round;
-  constexpr int CH = G < 8 ? G : 8;
-  const int stride = group_stride(G, E::K, R, (m + CH - 1) / CH * CH);
-  const size_t lds = sizeof(double) * (size_t)stride * (kBfgsBlock / 64) * (64 / G);
+  const size_t lds = sizeof(double) * (size_t)group_stride(G, E::K, R) * (kBfgsBlock / G);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((bfgs_kernel<OBJ, G, T>), dim3(blocks), dim3(kBfgsBlock), lds, s, a);
+  hipLaunchKernelGGL((bfgs_kernel<OBJ, G, T>), dim3(blocks), dim3(kBfgsBlock), lds, g.stream,
+                     g.reqs, g.nreq, g.hdr, g.total_starts, R);
   return hipGetLastError();
 }
 
 template <int OBJ, class T>
-hipError_t launch_obj(const BfgsArgs &a, int G, int blocks, hipStream_t s) {
-  switch (G) {
-    case 2: return launch_g<OBJ, 2, T>(a, blocks, s);
-    case 4: return launch_g<OBJ, 4, T>(a, blocks, s);
-    case 8: return launch_g<OBJ, 8, T>(a, blocks, s);
-    case 16: return launch_g<OBJ, 16, T>(a, blocks, s);
-    case 32: return launch_g<OBJ, 32, T>(a, blocks, s);
-    case 64: return launch_g<OBJ, 64, T>(a, blocks, s);
+hipError_t launch_obj(const Group &g, int R, int blocks) {
+  switch (g.g_bfgs) {
+    case 2: return launch_g<OBJ, 2, T>(g, R, blocks);
+    case 4: return launch_g<OBJ, 4, T>(g, R, blocks);
+    case 8: return launch_g<OBJ, 8, T>(g, R, blocks);
+    case 16: return launch_g<OBJ, 16, T>(g, R, blocks);
+    case 32: return launch_g<OBJ, 32, T>(g, R, blocks);
+    case 64: return launch_g<OBJ, 64, T>(g, R, blocks);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <class T>
-hipError_t launch_prec(int objective, const BfgsArgs &a, int G, int blocks, hipStream_t s) {
-  switch (objective) {
-    case kRosenbrock: return launch_obj<kRosenbrock, T>(a, G, blocks, s);
-    case kRastrigin: return launch_obj<kRastrigin, T>(a, G, blocks, s);
-    case kAckley: return launch_obj<kAckley, T>(a, G, blocks, s);
-    case kStyblinskiTang: return launch_obj<kStyblinskiTang, T>(a, G, blocks, s);
-    case kGoldsteinPrice: return launch_obj<kGoldsteinPrice, T>(a, G, blocks, s);
-    case kSphere: return launch_obj<kSphere, T>(a, G, blocks, s);
-    case kQuartic: return launch_obj<kQuartic, T>(a, G, blocks, s);
+hipError_t launch_prec(const Group &g, int R, int blocks) {
+  switch (g.objective) {
+    case kRosenbrock: return launch_obj<kRosenbrock, T>(g, R, blocks);
+    case kRastrigin: return launch_obj<kRastrigin, T>(g, R, blocks);
+    case kAckley: return launch_obj<kAckley, T>(g, R, blocks);
+    case kStyblinskiTang: return launch_obj<kStyblinskiTang, T>(g, R, blocks);
+    case kGoldsteinPrice: return launch_obj<kGoldsteinPrice, T>(g, R, blocks);
+    case kSphere: return launch_obj<kSphere, T>(g, R, blocks);
+    case kQuartic: return launch_obj<kQuartic, T>(g, R, blocks);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-// Lanes per start: the smallest power of two >= dim, at least kMinLanes
-// (more lanes per start than coordinates buy more line-search trials per
-// round; ZEUS_MIN_LANES overrides the floor for experiments).
+// Lanes per start: the smallest power of two >= dim, at least 4 (more lanes
+// per start than coordinates buy more line-search trials per round;
+// ZEUS_MIN_LANES overrides the floor for experiments).
 int group_lanes(int dim) {
   static int floor_lanes = [] {
     const char *e = getenv("ZEUS_MIN_LANES");
@@ -471,46 +482,25 @@ int trials_per_round(int G) {
   return want < G ? want : G;
 }
 
-hipError_t launch_bfgs(const Launch &L) {
-  const zeus_problem &p = *L.pb;
-  BfgsArgs a;
-  a.n = p.n_starts;
-  a.d = p.dim;
-  a.iter_bfgs = p.iter_bfgs;
-  a.iter_ls = p.iter_ls;
-  a.trace_len = L.out->trace ? L.out->trace_len : 0;
-  a.armijo_c = p.armijo_c;
-  a.shrink = p.ls_shrink;
-  a.tol = p.grad_tol;
-  a.x0 = L.ws.x;
-  a.queue = L.ws.queue;
-  a.out_f = L.out->f;
-  a.out_x = L.out->x;
-  a.out_iters = L.out->iters;
-  a.out_status = L.out->status;
-  a.out_ls = L.out->ls_trials;
-  a.trace = a.trace_len > 0 ? L.out->trace : nullptr;
-  const int G = group_lanes(p.dim);
-  if (G > kMaxDim) return hipErrorInvalidValue;
-  a.trials_per_round = trials_per_round(G);
-  const int64_t starts_per_block = (int64_t)(kBfgsBlock / G);
+hipError_t launch_bfgs(const Group &g) {
+  if (g.g_bfgs > kMaxDim) return hipErrorInvalidValue;
+  const int R = trials_per_round(g.g_bfgs);
+  const int64_t starts_per_block = (int64_t)(kBfgsBlock / g.g_bfgs);
   int dev = 0;
   (void)hipGetDevice(&dev);
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
   // enough resident blocks to fill the chip; the work counter balances them
-  const int64_t want = (p.n_starts + starts_per_block - 1) / starts_per_block;
+  const int64_t want = (g.total_starts + starts_per_block - 1) / starts_per_block;
   const int64_t cap = (int64_t)cus * 8;
   const int blocks = (int)(want < cap ? want : cap);
-  if (p.precision == ZEUS_MIXED) return launch_prec<float>(p.objective, a, G, blocks, L.stream);
-  return launch_prec<double>(p.objective, a, G, blocks, L.stream);
+  if (g.precision == ZEUS_MIXED) return launch_prec<float>(g, R, blocks);
+  return launch_prec<double>(g, R, blocks);
 }
 
-hipError_t launch_summary(const Launch &L) {
-  hipLaunchKernelGGL(summary_kernel, dim3(1), dim3(kSumBlock), 0, L.stream, L.pb->n_starts,
-                     L.out->f, L.out->status, L.out->iters, L.out->ls_trials, L.ws.best,
-                     L.out->summary);
+hipError_t launch_summary(const Group &g) {
+  hipLaunchKernelGGL(summary_kernel, dim3(g.nreq), dim3(kSumBlock), 0, g.stream, g.reqs);
   return hipGetLastError();
 }
 

@@ -190,10 +190,24 @@ __device__ __forceinline__ double dcos(double a) {
   zm::sincos(a, s, c);
   return c;
 }
-__device__ __forceinline__ float dcos(float a) { return cosf(a); }
-__device__ __forceinline__ float dsin(float a) { return sinf(a); }
+// FP32 (mixed precision): the hardware sine, cosine and exponential
+// (v_sin_f32, v_cos_f32, v_exp_f32; absolute error around 1e-6 for moderate
+// arguments), with the library functions beyond |x| = 2^10.  FP32 results only
+// steer a start until it escalates to FP64 near its minimum.
+__device__ __forceinline__ void sincos32(float a, float &s, float &c) {
+  if (__builtin_fabsf(a) <= 1024.0f) {
+    __sincosf(a, &s, &c);
+  } else {
+    sincosf(a, &s, &c);
+  }
+}
+__device__ __forceinline__ float dcos(float a) {
+  float s, c;
+  sincos32(a, s, c);
+  return c;
+}
 __device__ __forceinline__ double dexp(double a) { return zm::exp(a); }
-__device__ __forceinline__ float dexp(float a) { return expf(a); }
+__device__ __forceinline__ float dexp(float a) { return __expf(a); }
 __device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ float dsqrt(float a) { return sqrtf(a); }
 
@@ -205,7 +219,7 @@ __device__ __forceinline__ dual<double> dcos(dual<double> a) {
 }
 __device__ __forceinline__ dual<float> dcos(dual<float> a) {
   float s, c;
-  sincosf(a.v, &s, &c);
+  sincos32(a.v, s, c);
   return {c, -(a.t * s)};
 }
 // exp(a + b eps) = e^a + b e^a eps

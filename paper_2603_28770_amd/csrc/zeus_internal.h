@@ -16,8 +16,9 @@ constexpr int kMaxDim = 64;
 constexpr int kPsoBlock = 256;
 constexpr int kBfgsBlock = 256;
 
-// Most blocks a swarm launch uses (the grid strides over the particles; every
-// block re-reduces the previous launch's P block results, so P stays small).
+// Most blocks a swarm launch gives one request (the blocks stride over its
+// particles; each re-reduces the previous launch's block results, so this
+// stays small).
 constexpr int kPsoMaxBlocks = 512;
 
 // A swarm best, kept on the device.
@@ -26,12 +27,11 @@ struct PsoBest {
   int64_t idx;   // particle index
 };
 
-// Device workspace carved out of one allocation (all offsets 256-aligned).
-// The swarm kernels exchange their block results through double-buffered
-// slots: sweep t writes slot t & 1, sweep t+1 reads it after the kernel
-// boundary, so no launch needs a device-wide fence.
+// Device workspace of one request (all pieces 256-byte aligned).  The swarm
+// kernels exchange their block results through double-buffered slots: sweep
+// t writes slot t & 1, sweep t+1 reads it after the kernel boundary, so no
+// launch needs a device-wide fence.
 struct Workspace {
-  uint64_t *queue;         // next unclaimed BFGS start
   PsoBest *best;           // swarm best after the last sweep
   double *gx;              // [dim] its position
   PsoBest *best_store;     // [2] swarm best after sweep t, slot t & 1
@@ -48,24 +48,54 @@ struct Workspace {
 size_t workspace_bytes(int64_t n, int dim);
 Workspace carve_workspace(void *base, int64_t n, int dim);
 
-struct Launch {
-  const zeus_problem *pb;
-  const zeus_result *out;  // device pointers
-  Workspace ws;
+// One request of a launch as the kernels see it (a table in device memory).
+// A launch serves requests that share objective, precision and lane counts.
+struct ReqDev {
+  int64_t n;                 // particles == starts
+  int d, iter_pso, iter_bfgs, iter_ls, trace_len, pad0;
+  double lo, hi, vh;         // box and velocity half-range
+  double w, c1, c2;          // swarm coefficients
+  double armijo_c, shrink, tol;
+  uint64_t k0, k1;           // Philox key (seed, request id)
+  Workspace ws;              // swarm state
+  double *out_f, *out_x;     // results (device)
+  int32_t *out_iters, *out_status, *out_ls;
+  double *trace;
+  zeus_summary *summary;
+  int64_t start_offset;      // first start of this request in the BFGS launch
+  int block_offset;          // first block of this request in a swarm launch
+  int pad1;
+};
+
+// Shared counters of one launch group.
+struct BatchDev {
+  uint64_t queue;            // next unclaimed BFGS start over all requests
+};
+
+// A launch group: device table of nreq requests plus its counters.
+struct Group {
+  int objective;
+  int precision;
+  int g_pso, g_bfgs;         // lanes per particle / per start
+  int nreq;
+  int max_iter_pso;
+  int pso_grid;              // total swarm blocks (sum of P)
+  int64_t total_starts;
+  const ReqDev *reqs;        // device
+  BatchDev *hdr;             // device
   hipStream_t stream;
 };
 
 // Kernel launchers (return the first HIP error, hipSuccess otherwise).
-hipError_t launch_ws_init(const Launch &L);
-hipError_t launch_pso_init(const Launch &L);
-hipError_t launch_pso_step(const Launch &L, int t);
-hipError_t launch_pso_finish(const Launch &L);
-hipError_t launch_bfgs(const Launch &L);
-hipError_t launch_summary(const Launch &L);
+hipError_t launch_ws_init(const Group &g);
+hipError_t launch_pso(const Group &g, int t);
+hipError_t launch_pso_finish(const Group &g);
+hipError_t launch_bfgs(const Group &g);
+hipError_t launch_summary(const Group &g);
 
 // Lanes per start of the BFGS kernel for a dimension (power of two >= dim).
 int group_lanes(int dim);
-// Lanes per particle of the swarm kernels, and their grid size.
+// Lanes per particle of the swarm kernels, and one request's grid size.
 int pso_group_lanes(int dim);
 int pso_blocks(int64_t n, int dim);
 

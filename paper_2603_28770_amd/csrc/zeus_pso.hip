@@ -4,8 +4,9 @@
 // One group of G lanes per particle: lane j draws, updates and stores
 // coordinate j (consecutive lanes touch consecutive addresses), the group
 // evaluates the objective term-parallel and keeps the personal best.
-// Blocks are persistent: a launch runs min(#particle groups, 2048) blocks that
-// stride over the particles.
+// A launch serves a table of requests (one request, or a bucket of a batch);
+// each request owns P = min(#particle groups, 512) consecutive blocks that
+// stride over its particles.
 //
 // Global best.  The paper's kernels take it with an atomicMin on the value and
 // an unsynchronised copy of the position, which lets two winners interleave
@@ -25,16 +26,18 @@
 namespace zeus {
 namespace {
 
-struct PsoArgs {
-  int64_t n;
-  int d;
-  int t;             // sweep: 0 initialises, t >= 1 is update t
-  double lo, hi;     // sampling box
-  double vh;         // velocity half-range
-  double w, c1, c2;  // inertia, cognitive, social
-  uint64_t k0, k1;   // Philox key (seed, request id)
-  Workspace ws;
-};
+// Index of the table entry whose [offset, next offset) holds v (offsets are
+// ascending and start at 0).
+template <class Off>
+__device__ __forceinline__ int find_entry(const ReqDev *reqs, int nreq, int64_t v, Off off) {
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off(reqs[mid]) <= v) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // Block-wide minimum of (key, idx) carrying two payloads; the result is left
 // in every thread.
@@ -80,7 +83,7 @@ __device__ void block_argmin(double &key, int64_t &idx, double &val, int64_t &au
 // of that sweep and the global best after sweep done-1.  Leaves its position
 // in gx_sh[0..d) for every thread of the block.  When `publish`, the result is
 // also stored for later launches (and in final_best / final_gx if given).
-__device__ void global_best_after(const PsoArgs &a, int done, double *gx_sh, bool publish,
+__device__ void global_best_after(const ReqDev &a, int done, double *gx_sh, bool publish,
                                   PsoBest *final_best, double *final_gx) {
   const int P = a.ws.pso_blocks, d = a.d, slot = done & 1;
   double key = __builtin_huge_val(), val = __builtin_nan("");
@@ -120,13 +123,17 @@ __device__ void global_best_after(const PsoArgs &a, int done, double *gx_sh, boo
 }
 
 template <int OBJ, int G>
-__global__ __launch_bounds__(kPsoBlock) void pso_kernel(PsoArgs a) {
+__global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int nreq, int t) {
   using E = Elem<OBJ>;
   constexpr int kGroups = kPsoBlock / G;
   __shared__ double xs_all[kGroups][G];
   __shared__ double tv_all[kGroups][E::K * G];
   __shared__ double uw_all[kGroups][2][G + 4];  // the group's uniforms, two streams
   __shared__ double gx_sh[kMaxDim];
+  const int r = find_entry(reqs, nreq, blockIdx.x, [](const ReqDev &q) { return (int64_t)q.block_offset; });
+  const ReqDev &a = reqs[r];
+  if (t > a.iter_pso) return;  // this request's swarm is done
+  const int blk = (int)blockIdx.x - a.block_offset;  // block within the request
   const GroupLanes<G> L;
   const int gib = threadIdx.x / G;  // group in block
   double *xs = xs_all[gib], *tv = tv_all[gib];
@@ -136,25 +143,25 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(PsoArgs a) {
   for (int q = threadIdx.x; q < kGroups * E::K * G; q += kPsoBlock) (&tv_all[0][0])[q] = 0.0;
   __syncthreads();
 
-  if (a.t > 0) global_best_after(a, a.t - 1, gx_sh, blockIdx.x == 0, nullptr, nullptr);
-  const double gxj = (a.t > 0 && j < d) ? gx_sh[j] : 0.0;
+  if (t > 0) global_best_after(a, t - 1, gx_sh, blk == 0, nullptr, nullptr);
+  const double gxj = (t > 0 && j < d) ? gx_sh[j] : 0.0;
 
   // this block's best particle of the sweep, tracked by each group's lane 0
   double key = __builtin_huge_val(), val = __builtin_nan("");
   int64_t idx = INT64_MAX, unused = 0;
-  const uint64_t tag_a = a.t == 0 ? kTagX0 : kTagR1, tag_b = a.t == 0 ? kTagV0 : kTagR2;
+  const uint64_t tag_a = t == 0 ? kTagX0 : kTagR1, tag_b = t == 0 ? kTagV0 : kTagR2;
   const int64_t stride = (int64_t)P * kGroups;
-  for (int64_t i = (int64_t)blockIdx.x * kGroups + gib;; i += stride) {
+  for (int64_t i = (int64_t)blk * kGroups + gib;; i += stride) {
     const bool live = i < a.n;
     if (__ballot(live) == 0ull) break;  // the whole wave is past the end
     // one Philox block per lane: lane l < 2 nb draws block (l mod nb) of
     // stream a (l < nb) or b and shares its four words through LDS
     if (live && j < 2 * nb) {
       const int sb = j >= nb, jb = sb ? j - nb : j;
-      const u64x4 r = philox4x64_10((uint64_t)jb, (uint64_t)i, (uint64_t)a.t, sb ? tag_b : tag_a,
-                                    a.k0, a.k1);
+      const u64x4 rw = philox4x64_10((uint64_t)jb, (uint64_t)i, (uint64_t)t, sb ? tag_b : tag_a,
+                                     a.k0, a.k1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) uw_all[gib][sb][jb * 4 + q] = u01(r.w[q]);
+      for (int q = 0; q < 4; ++q) uw_all[gib][sb][jb * 4 + q] = u01(rw.w[q]);
     }
     wave_sync();
     const bool own = live && j < d;
@@ -162,7 +169,7 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(PsoArgs a) {
     if (own) {
       const int64_t o = i * d + j;
       const double ua = uw_all[gib][0][j], ub = uw_all[gib][1][j];
-      if (a.t == 0) {
+      if (t == 0) {
         const double vlo = -a.vh, vhi = a.vh;
         // UniformSample(lo, hi) = lo + u (hi - lo)
         x = a.lo + ua * (a.hi - a.lo);
@@ -188,7 +195,7 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(PsoArgs a) {
       const double f = group_value<OBJ, G, double>(L, d, xs, tv);
       bool improved = true;
       double pf = f;
-      if (a.t > 0) {
+      if (t > 0) {
         const double old = a.ws.pf[i];
         improved = rank_key(f) < rank_key(old);  // personal best, strict
         pf = improved ? f : old;
@@ -208,76 +215,45 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(PsoArgs a) {
   block_argmin(key, idx, val, unused);
   // stage (1): this block's result and its winner's personal-best position
   // (written by this block in this launch, so visible after the barrier)
-  const int slot = a.t & 1;
+  const int slot = t & 1;
   if (threadIdx.x == 0) {
-    a.ws.part_key[slot * P + blockIdx.x] = key;
-    a.ws.part_idx[slot * P + blockIdx.x] = idx;
-    a.ws.part_f[slot * P + blockIdx.x] = val;
+    a.ws.part_key[slot * P + blk] = key;
+    a.ws.part_idx[slot * P + blk] = idx;
+    a.ws.part_f[slot * P + blk] = val;
   }
   if (idx != INT64_MAX)
     for (int jj = threadIdx.x; jj < d; jj += kPsoBlock)
-      a.ws.part_x[((size_t)slot * P + blockIdx.x) * d + jj] = a.ws.px[idx * d + jj];
+      a.ws.part_x[((size_t)slot * P + blk) * d + jj] = a.ws.px[idx * d + jj];
 }
 
-// Stage (3): publish the swarm best after the last sweep.
-__global__ __launch_bounds__(kPsoBlock) void pso_finish_kernel(PsoArgs a) {
+// Stage (3): publish every request's swarm best after its last sweep (one
+// block per request).
+__global__ __launch_bounds__(kPsoBlock) void pso_finish_kernel(const ReqDev *reqs) {
   __shared__ double gx_sh[kMaxDim];
-  global_best_after(a, a.t, gx_sh, true, a.ws.best, a.ws.gx);
+  const ReqDev &a = reqs[blockIdx.x];
+  global_best_after(a, a.iter_pso, gx_sh, true, a.ws.best, a.ws.gx);
 }
 
-__global__ void ws_init_kernel(Workspace ws) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *ws.queue = 0ull;
-}
-
-PsoArgs make_args(const Launch &L, int t) {
-  const zeus_problem &p = *L.pb;
-  PsoArgs a;
-  a.n = p.n_starts;
-  a.d = p.dim;
-  a.t = t;
-  a.lo = p.lower;
-  a.hi = p.upper;
-  a.vh = p.v_half > 0.0 ? p.v_half : (p.upper - p.lower);
-  a.w = p.w;
-  a.c1 = p.c1;
-  a.c2 = p.c2;
-  a.k0 = p.seed;
-  a.k1 = p.request_id;
-  a.ws = L.ws;
-  return a;
+__global__ void ws_init_kernel(BatchDev *hdr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->queue = 0ull;
 }
 
 template <int OBJ, int G>
-hipError_t launch_g(const PsoArgs &a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((pso_kernel<OBJ, G>), dim3(blocks), dim3(kPsoBlock), 0, s, a);
+hipError_t launch_g(const Group &g, int t) {
+  hipLaunchKernelGGL((pso_kernel<OBJ, G>), dim3(g.pso_grid), dim3(kPsoBlock), 0, g.stream, g.reqs,
+                     g.nreq, t);
   return hipGetLastError();
 }
 
 template <int OBJ>
-hipError_t launch_obj(const PsoArgs &a, int G, int blocks, hipStream_t s) {
-  switch (G) {
-    case 2: return launch_g<OBJ, 2>(a, blocks, s);
-    case 4: return launch_g<OBJ, 4>(a, blocks, s);
-    case 8: return launch_g<OBJ, 8>(a, blocks, s);
-    case 16: return launch_g<OBJ, 16>(a, blocks, s);
-    case 32: return launch_g<OBJ, 32>(a, blocks, s);
-    case 64: return launch_g<OBJ, 64>(a, blocks, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_pso(const Launch &L, int t) {
-  const PsoArgs a = make_args(L, t);
-  const int G = pso_group_lanes(L.pb->dim);
-  const int blocks = L.ws.pso_blocks;
-  switch (L.pb->objective) {
-    case kRosenbrock: return launch_obj<kRosenbrock>(a, G, blocks, L.stream);
-    case kRastrigin: return launch_obj<kRastrigin>(a, G, blocks, L.stream);
-    case kAckley: return launch_obj<kAckley>(a, G, blocks, L.stream);
-    case kStyblinskiTang: return launch_obj<kStyblinskiTang>(a, G, blocks, L.stream);
-    case kGoldsteinPrice: return launch_g<kGoldsteinPrice, 2>(a, blocks, L.stream);
-    case kSphere: return launch_obj<kSphere>(a, G, blocks, L.stream);
-    case kQuartic: return launch_obj<kQuartic>(a, G, blocks, L.stream);
+hipError_t launch_obj(const Group &g, int t) {
+  switch (g.g_pso) {
+    case 2: return launch_g<OBJ, 2>(g, t);
+    case 4: return launch_g<OBJ, 4>(g, t);
+    case 8: return launch_g<OBJ, 8>(g, t);
+    case 16: return launch_g<OBJ, 16>(g, t);
+    case 32: return launch_g<OBJ, 32>(g, t);
+    case 64: return launch_g<OBJ, 64>(g, t);
     default: return hipErrorInvalidValue;
   }
 }
@@ -296,18 +272,26 @@ int pso_blocks(int64_t n, int dim) {
   return (int)(want < kPsoMaxBlocks ? want : kPsoMaxBlocks);
 }
 
-hipError_t launch_ws_init(const Launch &L) {
-  hipLaunchKernelGGL(ws_init_kernel, dim3(1), dim3(64), 0, L.stream, L.ws);
+hipError_t launch_ws_init(const Group &g) {
+  hipLaunchKernelGGL(ws_init_kernel, dim3(1), dim3(64), 0, g.stream, g.hdr);
   return hipGetLastError();
 }
 
-hipError_t launch_pso_init(const Launch &L) { return launch_pso(L, 0); }
+hipError_t launch_pso(const Group &g, int t) {
+  switch (g.objective) {
+    case kRosenbrock: return launch_obj<kRosenbrock>(g, t);
+    case kRastrigin: return launch_obj<kRastrigin>(g, t);
+    case kAckley: return launch_obj<kAckley>(g, t);
+    case kStyblinskiTang: return launch_obj<kStyblinskiTang>(g, t);
+    case kGoldsteinPrice: return launch_g<kGoldsteinPrice, 2>(g, t);
+    case kSphere: return launch_obj<kSphere>(g, t);
+    case kQuartic: return launch_obj<kQuartic>(g, t);
+    default: return hipErrorInvalidValue;
+  }
+}
 
-hipError_t launch_pso_step(const Launch &L, int t) { return launch_pso(L, t); }
-
-hipError_t launch_pso_finish(const Launch &L) {
-  const PsoArgs a = make_args(L, L.pb->iter_pso);
-  hipLaunchKernelGGL(pso_finish_kernel, dim3(1), dim3(kPsoBlock), 0, L.stream, a);
+hipError_t launch_pso_finish(const Group &g) {
+  hipLaunchKernelGGL(pso_finish_kernel, dim3(g.nreq), dim3(kPsoBlock), 0, g.stream, g.reqs);
   return hipGetLastError();
 }
 

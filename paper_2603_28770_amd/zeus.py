@@ -26,7 +26,7 @@ ST_MAXITER, ST_CONVERGED, ST_STOPPED, ST_NONFINITE = 0, 1, 2, 3
 EXPORTS = ("zeus_abi_version", "zeus_version", "zeus_last_error", "zeus_validate",
            "zeus_workspace_bytes", "zeus_context_create", "zeus_context_destroy",
            "zeus_context_set_profiling", "zeus_context_get_profile", "zeus_minimize",
-           "zeus_minimize_async")
+           "zeus_minimize_batch", "zeus_minimize_async")
 
 
 class zeus_problem(C.Structure):
@@ -87,6 +87,7 @@ def _load():
     L.zeus_context_set_profiling.argtypes = [C.c_void_p, C.c_int]
     L.zeus_context_get_profile.argtypes = [C.c_void_p, P(zeus_profile)]
     L.zeus_minimize.argtypes = [C.c_void_p, P(zeus_problem), P(zeus_result)]
+    L.zeus_minimize_batch.argtypes = [C.c_void_p, P(zeus_problem), C.c_int32, P(zeus_result)]
     L.zeus_minimize_async.argtypes = [C.c_void_p, P(zeus_problem), C.c_void_p, C.c_size_t,
                                       P(zeus_result), C.c_void_p]
     for name in EXPORTS:
@@ -166,9 +167,7 @@ def _np_ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p).value
 
 
-def zeus_minimize(ctx, problem, *, trace_len=0, pso_state=False, ls_trials=True) -> dict:
-    """Blocking solve; returns host numpy arrays."""
-    pb = problem if isinstance(problem, zeus_problem) else make_problem(problem)
+def _host_outputs(pb, trace_len, pso_state, ls_trials):
     n, d = pb.n_starts, pb.dim
     o = {"f": np.empty(n), "x": np.empty((n, d)), "iters": np.empty(n, np.int32),
          "status": np.empty(n, np.int32)}
@@ -187,9 +186,37 @@ def zeus_minimize(ctx, problem, *, trace_len=0, pso_state=False, ls_trials=True)
                     pso_best_x=_np_ptr(o.get("pso_best_x")), trace=_np_ptr(o.get("trace")),
                     trace_len=int(trace_len), reserved0=0,
                     summary=C.cast(C.pointer(s), C.c_void_p).value)
+    return o, s, r
+
+
+def _summary_dict(s):
+    return {k: getattr(s, k) for k, _ in zeus_summary._fields_}
+
+
+def zeus_minimize(ctx, problem, *, trace_len=0, pso_state=False, ls_trials=True) -> dict:
+    """Blocking solve; returns host numpy arrays."""
+    pb = problem if isinstance(problem, zeus_problem) else make_problem(problem)
+    o, s, r = _host_outputs(pb, trace_len, pso_state, ls_trials)
     _check(lib.zeus_minimize(ctx, C.byref(pb), C.byref(r)))
-    o["summary"] = {k: getattr(s, k) for k, _ in zeus_summary._fields_}
+    o["summary"] = _summary_dict(s)
     return o
+
+
+def zeus_minimize_batch(ctx, problems, *, trace_len=0, pso_state=False, ls_trials=True) -> list:
+    """Blocking solve of a list of problems (dicts or zeus_problem)."""
+    pbs = (zeus_problem * len(problems))(
+        *[p if isinstance(p, zeus_problem) else make_problem(p) for p in problems])
+    outs, sums = [], []
+    res = (zeus_result * len(problems))()
+    for k in range(len(problems)):
+        o, s, r = _host_outputs(pbs[k], trace_len, pso_state, ls_trials)
+        outs.append(o)
+        sums.append(s)
+        res[k] = r
+    _check(lib.zeus_minimize_batch(ctx, pbs, len(problems), res))
+    for o, s in zip(outs, sums):
+        o["summary"] = _summary_dict(s)
+    return outs
 
 
 def zeus_minimize_async(ctx, problem, workspace_ptr: int, workspace_bytes: int,

@@ -1,0 +1,78 @@
+"""zeus_minimize_batch on the GPU: uneven requests (objectives, dimensions,
+start counts, budgets and precisions all differ) solved in one call give, for
+every request, exactly what the request gives alone, and FP64 requests match
+the oracle bit for bit."""
+import numpy as np
+import pytest
+
+from paper_2603_28770_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Z():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28770_amd import zeus
+    return zeus
+
+
+@pytest.fixture(scope="module")
+def ctx(Z):
+    c = Z.zeus_context_create(0)
+    yield c
+    Z.zeus_context_destroy(c)
+
+
+def _mix(count, seed, dmax=64, nmin=64, nspan=8.0):
+    """An uneven request mix like the batched workload, at test sizes."""
+    g = np.random.Generator(np.random.Philox(key=seed))
+    u = g.random((count, 5))
+    out = []
+    for r in range(count):
+        obj = W.MIX[min(int(u[r, 0] * 4), 3)]
+        d = 2 + int(u[r, 1] * (dmax - 1))
+        n = int(nmin * nspan ** u[r, 2])
+        lo, hi = W.BOXES[obj]
+        out.append(W.problem(name=f"r{r}", objective=obj, dim=d, n=n, lower=lo, upper=hi,
+                             iter_pso=int(u[r, 3] * 21), iter_bfgs=300, seed=seed,
+                             request_id=r, precision="mixed" if u[r, 4] < 0.3 else "fp64",
+                             grad_tol=1e-4 if u[r, 4] < 0.3 else 1e-6))
+    return out
+
+
+KEYS = ("f", "x", "iters", "status", "ls_trials", "seeds")
+
+
+def test_batch_equals_alone(Z, ctx):
+    reqs = _mix(24, 11)
+    print(f"\n[batch] {len(reqs)} requests, d {min(r['dim'] for r in reqs)}..{max(r['dim'] for r in reqs)}",
+          flush=True)
+    outs = Z.zeus_minimize_batch(ctx, reqs, pso_state=True)
+    for r, (p, b) in enumerate(zip(reqs, outs)):
+        a = Z.zeus_minimize(ctx, p, pso_state=True)
+        for k in KEYS:
+            assert np.array_equal(a[k], b[k], equal_nan=True), (r, k)
+        assert a["summary"] == b["summary"], r
+
+
+def test_batch_fp64_matches_oracle(Z, ctx, oracle_mod):
+    reqs = [p for p in _mix(16, 5, dmax=24, nmin=32, nspan=4.0) if p["precision"] == "fp64"]
+    outs = Z.zeus_minimize_batch(ctx, reqs, pso_state=True)
+    for p, g in zip(reqs, outs):
+        sw = oracle_mod.pso(p)
+        o = oracle_mod.bfgs(p, sw["x"])
+        assert np.array_equal(g["seeds"], sw["x"])
+        for k in ("f", "x"):
+            assert np.array_equal(g[k], o[k], equal_nan=True), (p["name"], k)
+        assert np.array_equal(g["iters"], o["iters"]) and np.array_equal(g["status"], o["status"])
+
+
+def test_batch_rejects_any_invalid(Z, ctx):
+    reqs = _mix(3, 2)
+    reqs[1] = dict(reqs[1], dim=0)
+    with pytest.raises(Z.ZeusError) as e:
+        Z.zeus_minimize_batch(ctx, reqs)
+    assert e.value.code == Z.EINVAL and "request 1" in str(e.value)
