@@ -195,6 +195,36 @@ static dual d_exp(dual a) { double e = zo_exp(a.v); return dd(e, a.t * e); }
 /* sqrt(a + b eps) = sqrt a + b / (2 sqrt a) eps */
 static dual d_sqrt(dual a) { double s = sqrt(a.v); return dd(s, a.t / (2.0 * s)); }
 
+/* ======================================================================== */
+/* Sums.  The paper fixes no order for the sums over an objective's terms or */
+/* over coordinates (dot products), so one is chosen here: every such sum is */
+/* a balanced pairwise sum.  A sum of n > 1 values is the sum of its first h */
+/* values plus the sum of the remaining n - h, h being the largest power of  */
+/* two below n; a sum of one value is that value.                           */
+/* ======================================================================== */
+
+static int pw_split(int n) {
+  int h = 1;
+  while (2 * h < n) h *= 2;
+  return h;
+}
+
+/* sum_{i<n} a_i b_i, each product rounded, then added pairwise */
+static double pw_dot(const double *a, const double *b, int n) {
+  if (n <= 0) return 0.0;
+  if (n == 1) return a[0] * b[0];
+  int h = pw_split(n);
+  return pw_dot(a, b, h) + pw_dot(a + h, b + h, n - h);
+}
+
+/* sum of the terms lo .. lo+n-1 of an objective, each term a dual number */
+typedef dual (*term_fn)(const dual *x, int i);
+static dual pw_terms(term_fn term, const dual *x, int lo, int n) {
+  if (n == 1) return term(x, lo);
+  int h = pw_split(n);
+  return d_add(pw_terms(term, x, lo, h), pw_terms(term, x, lo + h, n - h));
+}
+
 static const double ZO_TWO_PI = 6.283185307179586;  /* 2*pi rounded to double */
 static const double ZO_E = 2.718281828459045;       /* e rounded to double    */
 
@@ -205,36 +235,31 @@ static const double ZO_E = 2.718281828459045;       /* e rounded to double    */
 
 /* Sec. V-B: sum_{i=1}^{d-1} [(1 - x_i)^2 + 100 (x_{i+1} - x_i^2)^2]
  * (the paper's upper index n needs x_{n+1}; the sum stops at d-1). */
+static dual rosenbrock_term(const dual *x, int i) {
+  dual a = d_ksub(1.0, x[i]);
+  dual b = d_sub(x[i + 1], d_mul(x[i], x[i]));
+  return d_add(d_mul(a, a), d_scale(100.0, d_mul(b, b)));
+}
 static dual obj_rosenbrock(const dual *x, int d) {
-  dual s = dd(0.0, 0.0);
-  for (int i = 0; i + 1 < d; ++i) {
-    dual a = d_ksub(1.0, x[i]);
-    dual b = d_sub(x[i + 1], d_mul(x[i], x[i]));
-    dual term = d_add(d_mul(a, a), d_scale(100.0, d_mul(b, b)));
-    s = d_add(s, term);
-  }
-  return s;
+  return pw_terms(rosenbrock_term, x, 0, d - 1);
 }
 
 /* Sec. V-B: A*d + sum [x_i^2 - A cos(2 pi x_i)], A = 10. */
+static dual rastrigin_term(const dual *x, int i) {
+  dual c = d_cos(d_scale(ZO_TWO_PI, x[i]));
+  return d_sub(d_mul(x[i], x[i]), d_scale(10.0, c));
+}
 static dual obj_rastrigin(const dual *x, int d) {
-  dual s = dd(0.0, 0.0);
-  for (int i = 0; i < d; ++i) {
-    dual c = d_cos(d_scale(ZO_TWO_PI, x[i]));
-    dual term = d_sub(d_mul(x[i], x[i]), d_scale(10.0, c));
-    s = d_add(s, term);
-  }
-  return d_addk(10.0 * (double)d, s);
+  return d_addk(10.0 * (double)d, pw_terms(rastrigin_term, x, 0, d));
 }
 
 /* Sec. V-B: -20 exp(-0.2 sqrt(sum x_i^2 / d)) - exp(sum cos(2 pi x_i) / d)
  *           + 20 + e. */
+static dual square_term(const dual *x, int i) { return d_mul(x[i], x[i]); }
+static dual cos2pi_term(const dual *x, int i) { return d_cos(d_scale(ZO_TWO_PI, x[i])); }
 static dual obj_ackley(const dual *x, int d) {
-  dual s1 = dd(0.0, 0.0), s2 = dd(0.0, 0.0);
-  for (int i = 0; i < d; ++i) {
-    s1 = d_add(s1, d_mul(x[i], x[i]));
-    s2 = d_add(s2, d_cos(d_scale(ZO_TWO_PI, x[i])));
-  }
+  dual s1 = pw_terms(square_term, x, 0, d);
+  dual s2 = pw_terms(cos2pi_term, x, 0, d);
   dual a = d_scale(-20.0, d_exp(d_scale(-0.2, d_sqrt(d_divk(s1, (double)d)))));
   dual b = d_exp(d_divk(s2, (double)d));
   dual r = d_sub(a, b);
@@ -244,15 +269,13 @@ static dual obj_ackley(const dual *x, int d) {
 }
 
 /* Styblinski-Tang: 0.5 * sum (x_i^4 - 16 x_i^2 + 5 x_i). */
+static dual st_term(const dual *x, int i) {
+  dual x2 = d_mul(x[i], x[i]);
+  dual x4 = d_mul(x2, x2);
+  return d_add(d_sub(x4, d_scale(16.0, x2)), d_scale(5.0, x[i]));
+}
 static dual obj_styblinski_tang(const dual *x, int d) {
-  dual s = dd(0.0, 0.0);
-  for (int i = 0; i < d; ++i) {
-    dual x2 = d_mul(x[i], x[i]);
-    dual x4 = d_mul(x2, x2);
-    dual term = d_add(d_sub(x4, d_scale(16.0, x2)), d_scale(5.0, x[i]));
-    s = d_add(s, term);
-  }
-  return d_scale(0.5, s);
+  return d_scale(0.5, pw_terms(st_term, x, 0, d));
 }
 
 /* Sec. V-B: Goldstein-Price, d = 2. */
@@ -278,20 +301,15 @@ static dual obj_goldstein_price(const dual *x, int d) {
 
 /* test-only: 0.5 * sum x_i^2 */
 static dual obj_sphere(const dual *x, int d) {
-  dual s = dd(0.0, 0.0);
-  for (int i = 0; i < d; ++i) s = d_add(s, d_mul(x[i], x[i]));
-  return d_scale(0.5, s);
+  return d_scale(0.5, pw_terms(square_term, x, 0, d));
 }
 
 /* test-only: sum x_i^4 */
-static dual obj_quartic(const dual *x, int d) {
-  dual s = dd(0.0, 0.0);
-  for (int i = 0; i < d; ++i) {
-    dual x2 = d_mul(x[i], x[i]);
-    s = d_add(s, d_mul(x2, x2));
-  }
-  return s;
+static dual fourth_term(const dual *x, int i) {
+  dual x2 = d_mul(x[i], x[i]);
+  return d_mul(x2, x2);
 }
+static dual obj_quartic(const dual *x, int d) { return pw_terms(fourth_term, x, 0, d); }
 
 static dual eval_dual(int objective, const dual *x, int d) {
   switch (objective) {
@@ -497,18 +515,16 @@ double zo_line_search(const zo_problem *pb, const double *x, double f0,
  *   H+ = H - rho (s u' + u s') + (rho^2 y'u + rho) s s'.
  * Skipped when y's is not > 0 (the update would divide by it). */
 int zo_bfgs_update(double *H, const double *s, const double *y, int d) {
-  double sy = 0.0;
-  for (int i = 0; i < d; ++i) sy = sy + y[i] * s[i];
+  double sy = pw_dot(y, s, d);
   if (!(sy > 0.0)) return 0;
   double rho = 1.0 / sy;
-  double *u = (double *)malloc(sizeof(double) * (size_t)d);
+  double *u = (double *)calloc((size_t)d, sizeof(double));
   for (int i = 0; i < d; ++i) {
     double acc = 0.0;
     for (int j = 0; j < d; ++j) acc = fma(H[i * d + j], y[j], acc);
     u[i] = acc;
   }
-  double yu = 0.0;
-  for (int i = 0; i < d; ++i) yu = yu + y[i] * u[i];
+  double yu = pw_dot(y, u, d);
   double beta = (rho * rho) * yu + rho;
   /* row i: H_ij + a_i u_j + e_i s_j with a_i = -rho s_i and
    * e_i = beta s_i - rho u_i, each element by two fused multiply-adds */
@@ -555,9 +571,7 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
   for (;;) {
     if (trace && k < out->trace_len) memcpy(trace + (int64_t)k * d, x, sizeof(double) * (size_t)d);
     if (!isfinite(f) || !all_finite(g, d)) { status = ZO_NONFINITE; break; }
-    double gg = 0.0;
-    for (int i = 0; i < d; ++i) gg = gg + g[i] * g[i];
-    double gnorm = sqrt(gg);
+    double gnorm = sqrt(pw_dot(g, g, d));
     {
       double m = rel_margin(gnorm, pb->grad_tol);
       note_margin(m, k, &min_margin, &tie_iter);
@@ -571,20 +585,16 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
       for (int j = 0; j < d; ++j) acc = fma(H[i * d + j], g[j], acc);
       p[i] = -acc;
     }
-    double ddir = 0.0;
-    for (int i = 0; i < d; ++i) ddir = ddir + g[i] * p[i];
+    double ddir = pw_dot(g, p, d);
     {
-      double pn = 0.0;
-      for (int i = 0; i < d; ++i) pn = pn + p[i] * p[i];
-      double m = fabs(ddir) / (gnorm * sqrt(pn));
+      double m = fabs(ddir) / (gnorm * sqrt(pw_dot(p, p, d)));
       if (!isnan(m)) note_margin(m, k, &min_margin, &tie_iter);
     }
     if (!(ddir < 0.0)) {  /* not a descent direction: restart from H = I */
       for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) H[i * d + j] = (i == j) ? 1.0 : 0.0;
       for (int i = 0; i < d; ++i) p[i] = -g[i];
-      ddir = 0.0;
-      for (int i = 0; i < d; ++i) ddir = ddir + g[i] * p[i];
+      ddir = pw_dot(g, p, d);
       ++resets;
     }
 
@@ -601,9 +611,8 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
     for (int i = 0; i < d; ++i) s[i] = xn[i] - x[i];
     for (int i = 0; i < d; ++i) y[i] = gn[i] - g[i];
     {
-      double sy = 0.0, ss = 0.0, yy = 0.0;
-      for (int i = 0; i < d; ++i) { sy = sy + y[i] * s[i]; ss += s[i] * s[i]; yy += y[i] * y[i]; }
-      double m = fabs(sy) / (sqrt(ss) * sqrt(yy));
+      double sy = pw_dot(y, s, d);
+      double m = fabs(sy) / (sqrt(pw_dot(s, s, d)) * sqrt(pw_dot(y, y, d)));
       if (!isnan(m)) note_margin(m, k, &min_margin, &tie_iter);
     }
     if (!zo_bfgs_update(H, s, y, d)) ++skips;

@@ -25,6 +25,23 @@ def test_minima_closed_forms(oracle_mod, d):
     assert O.f("sphere", np.zeros(d)) == 0.0 and O.f("quartic", np.zeros(d)) == 0.0
 
 
+def test_term_sums_are_balanced_pairwise(oracle_mod):
+    """The paper leaves the order of the sum over terms open; the oracle adds
+    pairwise (first h terms + the rest, h the largest power of two below the
+    count).  Worked by hand with squares 2^54 (x = 2^27) and ones, where
+    ulp(2^54) = 4 and 2^54 + 2 is a tie that rounds to even (2^54):
+      d=8, x = (2^27, 1 x7): ((2^54+1)+(1+1)) + ((1+1)+(1+1)) = 2^54 + 4,
+           so 0.5 sum = 2^53 + 2 (left to right: every +1 is lost, 2^53);
+      d=7, x = (1 x6, 2^27): (1+1+1+1) + ((1+1) + 2^54) = 2^54 + 4, so
+           2^53 + 2 (left to right: 6 + 2^54 rounds to 2^54 + 8, 2^53 + 4)."""
+    O = oracle_mod
+    assert O.f("sphere", [2.0 ** 27] + [1.0] * 7) == 2.0 ** 53 + 2
+    assert O.f("sphere", [1.0] * 6 + [2.0 ** 27]) == 2.0 ** 53 + 2
+    # the same sums through the dual-number path (value part of the gradient pass)
+    f, _ = O.grad("sphere", [2.0 ** 27] + [1.0] * 7)
+    assert f == 2.0 ** 53 + 2
+
+
 def test_goldstein_price_values(oracle_mod):
     assert oracle_mod.f("goldstein_price", [0.0, -1.0]) == 3.0
     # by hand: A = 1 + 3^2 * 3 = 28, B = 30 + (-1)^2 * 37 = 67
