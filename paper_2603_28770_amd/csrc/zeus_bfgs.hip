@@ -15,9 +15,10 @@
 //    Alg. 6 would return, in one objective evaluation instead of several;
 //  * the small vectors a lane needs in full (x, p, g, s, y, u) are exchanged
 //    through the group's slice of LDS;
-//  * starts are claimed from an agent-scope work counter, so a group that
-//    finishes early takes the next start instead of idling; results do not
-//    depend on which group ran which start.
+//  * each group first takes the start with its own index, then claims starts
+//    from an agent-scope work counter, so a group that finishes early takes
+//    the next start instead of idling; results do not depend on which group
+//    ran which start.
 // The loop is flattened so that every trip does one gradient evaluation and
 // one line search for every group of a wave, whatever iteration each group's
 // start is in.
@@ -30,52 +31,61 @@
 namespace zeus {
 namespace {
 
-// A start's request, as a group keeps it while working on the start.
-struct ReqLocal {
-  int d, m, dp, mp;          // dimension, terms, both padded to the chunk size
-  int iter_bfgs, iter_ls, trace_len;
-  double armijo_c, tol;
-  const double *x0;
-  double *out_f, *out_x;
-  int32_t *out_iters, *out_status, *out_ls;
-  double *trace;
+// The scalars of a start's request that every iteration reads, kept in the
+// group's LDS slice (registers hold only the request index; output pointers
+// are read from the request table when a start retires).
+struct ReqHot {
+  int d, m;                  // dimension, number of terms
+  int iter_bfgs, iter_ls, trace_len, ri;
+  double armijo_c, tol, shrink;
 };
-
-// Per-group LDS slice.  Every vector is zero beyond the dimension, so the
-// loops below run over whole chunks without per-element tests.
-struct GroupShm {
-  double *xs;  // [G] iterate under evaluation (x, then x_new)
-  double *ps;  // [G] search direction
-  double *gs;  // [G] gradient at the current iterate
-  double *ys;  // [G] y = g_new - g
-  double *ss;  // [G] s = x_new - x
-  double *us;  // [G] u = H y
-  double *tg;  // [K][G] term values of a gradient evaluation
-  double *tt;  // [K][R][G] term values of the trials of a line-search round
-  double *al;  // [kTabTrials] step lengths of the start's request
-};
+constexpr int kHotDoubles = (sizeof(ReqHot) + 7) / 8;
 
 // Step lengths alpha_t = shrink^t of the first kTabTrials trials, each the
 // product of the previous one and shrink, as Alg. 6 forms them.
 constexpr int kTabTrials = 32;
 
+// Per-group LDS slice: the vectors that every lane of the group reads in
+// full.  Entries from the dimension on are zero.
+struct GroupShm {
+  double *xs;  // [G] iterate under evaluation (x, then x_new)
+  double *ps;  // [G] search direction
+  double *vs;  // [G] operand of the next matrix-vector product (y, then g)
+  double *ss;  // [G] s = x_new - x
+  double *us;  // [G] u = H y
+  double *al;  // [kTabTrials] step lengths of the start's request
+  ReqHot *q;   // the start's request
+};
+
 // Doubles per group slice.
-__device__ __host__ __forceinline__ int group_stride(int G, int K, int R) {
-  return 6 * G + K * G + K * R * G + kTabTrials;
+__device__ __host__ __forceinline__ constexpr int group_stride(int G) {
+  return 5 * G + kTabTrials + kHotDoubles;
 }
+
+// Line-search trials per round: R trials of G / R lanes each.
+template <int G>
+constexpr int kRound = G < 4 ? G : 4;
 
 // One Armijo search (Alg. 6) with the objective evaluated in number type U.
 // A round evaluates R consecutive trials of the sequence at once, each spread
-// over tp = G / R lanes (lane c of a trial takes terms c, c + tp, ...); the
-// first trial that passes is the step Alg. 6 returns.  Returns its index, or
-// -1 when none of the iter_ls trials passes.
+// over TP = G / R lanes: lane c of a trial evaluates the term slots
+// cR .. cR + R - 1 (zero past the last term) and adds them pairwise, and the
+// trial's lanes finish the pairwise sum across lanes.  The first trial that
+// passes is the step Alg. 6 returns.  Returns its index, or -1 when none of
+// the iter_ls trials passes.
 template <int OBJ, int G, class U>
-__device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const ReqLocal &q,
-                                             double shrink, const GroupShm &sh, int R,
-                                             uint64_t leaders, double f, double ddir) {
+__device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const GroupShm &sh, double f,
+                                             double ddir) {
   using E = Elem<OBJ>;
-  const int tp = G / R, trial_slot = L.j / tp, term_slot = L.j % tp;
-  U *tvr = reinterpret_cast<U *>(sh.tt) + trial_slot * G;
+  constexpr int R = kRound<G>, TP = G / R;
+  constexpr uint64_t leaders = [] {  // bit r * TP for every trial r of a round
+    uint64_t b = 0;
+    for (int r = 0; r < R; ++r) b |= 1ull << (r * TP);
+    return b;
+  }();
+  const int trial_slot = L.j / TP, c = L.j % TP;
+  const ReqHot &q = *sh.q;
+  const int d = q.d, m = q.m;
   for (int base = 0; base < q.iter_ls; base += R) {
     const int t = base + trial_slot;
     double alpha;
@@ -83,25 +93,31 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const ReqLo
       alpha = sh.al[t];
     } else {
       alpha = sh.al[kTabTrials - 1];
-      for (int e = kTabTrials - 1; e < t; ++e) alpha = alpha * shrink;
+      for (int e = kTabTrials - 1; e < t; ++e) alpha = alpha * q.shrink;
     }
-    for (int i = term_slot; i < q.m; i += tp) {
-      U w[E::W], out[E::K];
+    U tv[E::K][R];
 #pragma unroll
-      for (int e = 0; e < E::W; ++e) w[e] = (U)(sh.xs[i + e] + alpha * sh.ps[i + e]);
-      E::template term<U>(w, out);
+    for (int b = 0; b < R; ++b) {
+      const int i = c * R + b;
+      U out[E::K];
 #pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) tvr[kk * R * G + i] = out[kk];
+      for (int kk = 0; kk < E::K; ++kk) out[kk] = U(0);
+      if (i < m) {
+        U w[E::W];
+#pragma unroll
+        for (int e = 0; e < E::W; ++e) w[e] = (U)(sh.xs[i + e] + alpha * sh.ps[i + e]);
+        E::template term<U>(w, out);
+      }
+#pragma unroll
+      for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = out[kk];
     }
-    wave_sync();
     U sums[E::K];
 #pragma unroll
-    for (int kk = 0; kk < E::K; ++kk) sums[kk] = sum_ordered<G, U>(tvr + kk * R * G, q.mp);
-    const double ft = (double)E::template outer<U>(q.d, sums);
+    for (int kk = 0; kk < E::K; ++kk) sums[kk] = lane_tree_sum<TP, U>(reg_tree_sum<R, U>(tv[kk]));
+    const double ft = (double)E::template outer<U>(d, sums);
     const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
     const uint64_t hit = L.ballot(ok) & leaders;
-    wave_sync();  // every lane has read the term buffer before it is reused
-    if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1) / tp;
+    if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1) / TP;
   }
   return -1;
 }
@@ -116,53 +132,52 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const ReqLo
 // (b) an FP32 value or gradient is not finite, or (c) an FP32 line search finds
 // no step.  Convergence and non-finite outcomes are therefore always decided
 // on FP64 values; the value reported for a start is FP64 at its final x.
+//
+// Every reduction below runs with all lanes of the group active: the control
+// flow splits only on values the whole group shares.
 template <int OBJ, int G, class T>
 __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, int nreq,
-                                                          BatchDev *hdr, int64_t total, int R) {
+                                                          BatchDev *hdr, int64_t total) {
   using E = Elem<OBJ>;
   constexpr bool kMixed = sizeof(T) != sizeof(double);
   constexpr int S = 64 / G;  // groups per wave
   extern __shared__ double smem[];
   const GroupLanes<G> L;
   const int j = L.j;
-  uint64_t leaders = 0;      // bit r*(G/R) of every trial r of a round
-  for (int r = 0; r < R; ++r) leaders |= 1ull << (r * (G / R));
-  const int stride = group_stride(G, E::K, R);
   GroupShm sh;
   {
-    double *base = smem + (size_t)((threadIdx.x >> 6) * S + L.grp) * stride;
+    double *base = smem + (size_t)((threadIdx.x >> 6) * S + L.grp) * group_stride(G);
     sh.xs = base;
     sh.ps = base + G;
-    sh.gs = base + 2 * G;
-    sh.ys = base + 3 * G;
-    sh.ss = base + 4 * G;
-    sh.us = base + 5 * G;
-    sh.tg = base + 6 * G;
-    sh.tt = base + 6 * G + E::K * G;
-    sh.al = base + 6 * G + E::K * G + E::K * R * G;
+    sh.vs = base + 2 * G;
+    sh.ss = base + 3 * G;
+    sh.us = base + 4 * G;
+    sh.al = base + 5 * G;
+    sh.q = reinterpret_cast<ReqHot *>(sh.al + kTabTrials);
   }
 
-  ReqLocal q{};
-  double shrink = 0.5;
   bool own = false;
   double h[G];  // row j of H; h[c] = 0 for c >= d except h[j] = 1 when j >= d
   double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
   int64_t idx = -1;
   int k = 0, ls_trials = 0;
-  bool fresh = false;
+  bool fresh = false, first = true;
   bool hi = !kMixed;  // evaluating in FP64 (always, unless mixed precision)
-  // term buffers back to zero (their padding), e.g. between FP32 and FP64 use
-  auto zero_terms = [&]() {
-    for (int e = j; e < E::K * G + E::K * R * G; e += G) sh.tg[e] = 0.0;
-    wave_sync();
-  };
 
   for (;;) {
     // -- claim a start when idle ------------------------------------------
     if (idx < 0) {
+      // the first start of a group is its own index; later ones come from
+      // the counter, after the starts taken that way
+      const unsigned long long groups = (unsigned long long)gridDim.x * (kBfgsBlock / G);
       unsigned long long got = 0;
-      if (j == 0) got = atomicAdd((unsigned long long *)&hdr->queue, 1ull);
-      got = __shfl(got, L.grp * G, 64);
+      if (first) {
+        got = (unsigned long long)blockIdx.x * (kBfgsBlock / G) + (threadIdx.x >> 6) * S + L.grp;
+        first = false;
+      } else {
+        if (j == 0) got = groups + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
+        got = __shfl(got, L.grp * G, 64);
+      }
       if (got >= (unsigned long long)total) break;
       // the request holding global start `got`
       int lo = 0, hi2 = nreq - 1;
@@ -173,31 +188,27 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
       }
       const ReqDev &rq = reqs[lo];
       idx = (int64_t)got - rq.start_offset;
-      q.d = rq.d;
-      q.m = E::terms(q.d);
-      q.dp = Chunk<G>::padded(q.d);
-      q.mp = Chunk<G>::padded(q.m);
-      q.iter_bfgs = rq.iter_bfgs;
-      q.iter_ls = rq.iter_ls;
-      q.trace_len = rq.trace ? rq.trace_len : 0;
-      q.armijo_c = rq.armijo_c;
-      q.tol = rq.tol;
-      q.x0 = rq.ws.x;
-      q.out_f = rq.out_f;
-      q.out_x = rq.out_x;
-      q.out_iters = rq.out_iters;
-      q.out_status = rq.out_status;
-      q.out_ls = rq.out_ls;
-      q.trace = rq.trace;
-      shrink = rq.shrink;
-      own = j < q.d;
-      zero_terms();
+      const int d0 = rq.d;
+      const double shrink = rq.shrink;
+      if (j == 0) {
+        ReqHot &w = *sh.q;
+        w.d = d0;
+        w.m = E::terms(d0);
+        w.iter_bfgs = rq.iter_bfgs;
+        w.iter_ls = rq.iter_ls;
+        w.trace_len = rq.trace ? rq.trace_len : 0;
+        w.ri = lo;
+        w.armijo_c = rq.armijo_c;
+        w.tol = rq.tol;
+        w.shrink = shrink;
+      }
+      own = j < d0;
       for (int t = j; t < kTabTrials; t += G) {  // step lengths of this request
         double al = 1.0;
         for (int e = 0; e < t; ++e) al = al * shrink;
         sh.al[t] = al;
       }
-      xj = own ? q.x0[idx * q.d + j] : 0.0;  // x <- swarm[i]
+      xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
       sh.xs[j] = xj;
 #pragma unroll
       for (int c = 0; c < G; ++c) h[c] = (c == j) ? 1.0 : 0.0;  // H <- I
@@ -207,30 +218,32 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
       hi = !kMixed;
     }
     wave_sync();
-    const int d = q.d, dp = q.dp;
+    const ReqHot &q = *sh.q;
+    const int d = q.d;
 
     // -- value and gradient at xs (dual numbers, one direction per lane) ----
     double gn, fn;
     if (hi)
-      fn = group_value_grad<OBJ, G, double>(L, d, sh.xs, sh.tg, &gn);
+      fn = group_value_grad<OBJ, G, double>(L, d, sh.xs, &gn);
     else
-      fn = group_value_grad<OBJ, G, T>(L, d, sh.xs, reinterpret_cast<T *>(sh.tg), &gn);
+      fn = group_value_grad<OBJ, G, T>(L, d, sh.xs, &gn);
 
-    // -- after a step: s, y and the rank-2 inverse-Hessian update -----------
+    // -- after a step: y and the rank-2 inverse-Hessian update --------------
     if (!fresh) {
-      const double yj = gn - gj;
-      sh.ys[j] = yj;
-      sh.ss[j] = sj;
-      wave_sync();
-      const double sy = dot_ordered<G>(sh.ys, sh.ss, dp);
+      const double yj = gn - gj;  // zero beyond the dimension
+      const double sy = lane_tree_sum<G, double>(yj * sj);
       if (sy > 0.0) {  // curvature condition; skip the update otherwise
         const double rho = 1.0 / sy;
+        sh.vs[j] = yj;
+        wave_sync();
         double uj = 0.0;
 #pragma unroll
-        for (int c = 0; c < G; ++c) uj = __builtin_fma(h[c], sh.ys[c], uj);
-        sh.us[j] = own ? uj : 0.0;
+        for (int c = 0; c < G; ++c) uj = __builtin_fma(h[c], sh.vs[c], uj);
+        uj = own ? uj : 0.0;
+        const double yu = lane_tree_sum<G, double>(yj * uj);
+        sh.us[j] = uj;
+        sh.ss[j] = sj;
         wave_sync();
-        const double yu = dot_ordered<G>(sh.ys, sh.us, dp);
         const double beta = (rho * rho) * yu + rho;
         // H+ = H - rho (s u' + u s') + beta s s'   (row j, u = H y)
         const double au = -rho * sj;
@@ -244,24 +257,20 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
             if (c >= d) h[c] = (c == j) ? 1.0 : 0.0;
         }
       }
-      xj = own ? sh.xs[j] : 0.0;  // x <- x_new
       ++k;
     }
     gj = gn;
     f = fn;
     fresh = false;
-    sh.gs[j] = gj;
-    wave_sync();
-    if (q.trace_len && own && k < q.trace_len) q.trace[(idx * q.trace_len + k) * d + j] = xj;
+    if (q.trace_len && own && k < q.trace_len) reqs[q.ri].trace[(idx * q.trace_len + k) * d + j] = xj;
 
     // -- termination: non-finite, ||g|| < Theta, budget ---------------------
     const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
     const bool any_bad = L.ballot(bad) != 0ull;
-    const double gg = dot_ordered<G>(sh.gs, sh.gs, dp);
+    const double gg = lane_tree_sum<G, double>(gj * gj);
     if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * q.tol)) {
       hi = true;  // escalate: re-evaluate this point in FP64
       fresh = true;
-      zero_terms();
       continue;
     }
     int status = -1;
@@ -272,55 +281,50 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     else if (k == q.iter_bfgs)
       status = ZEUS_ST_MAXITER;
     if (status >= 0) {
-      if (own) q.out_x[idx * d + j] = xj;
-      if (kMixed && !hi) {
-        // FP64 value at the returned x (ys and ss are free until the next step)
-#pragma unroll
-        for (int kk = 0; kk < E::K && kk < 2; ++kk) (kk == 0 ? sh.ys : sh.ss)[j] = 0.0;
-        wave_sync();
-        f = group_value<OBJ, G, double>(L, d, sh.xs, sh.ys);
-      }
+      const ReqDev &rq = reqs[q.ri];
+      const int tl = q.trace_len;
+      if (own) rq.out_x[idx * d + j] = xj;
+      if (kMixed && !hi) f = group_value<OBJ, G, double>(L, d, sh.xs);  // FP64 value at x
       if (j == 0) {
-        q.out_f[idx] = f;
-        q.out_iters[idx] = k;
-        q.out_status[idx] = status;
-        if (q.out_ls) q.out_ls[idx] = ls_trials;
+        rq.out_f[idx] = f;
+        rq.out_iters[idx] = k;
+        rq.out_status[idx] = status;
+        if (rq.out_ls) rq.out_ls[idx] = ls_trials;
       }
-      if (q.trace_len && own)
-        for (int kk = k + 1; kk < q.trace_len; ++kk)
-          q.trace[(idx * q.trace_len + kk) * d + j] = __builtin_nan("");
+      if (tl && own)
+        for (int kk = k + 1; kk < tl; ++kk)
+          rq.trace[(idx * tl + kk) * d + j] = __builtin_nan("");
       idx = -1;
       continue;
     }
 
     // -- search direction p = -H g (reset to -g if not a descent direction) -
+    sh.vs[j] = gj;
+    wave_sync();
     double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < G; ++c) acc = __builtin_fma(h[c], sh.gs[c], acc);
+    for (int c = 0; c < G; ++c) acc = __builtin_fma(h[c], sh.vs[c], acc);
     pj = own ? -acc : 0.0;
-    sh.ps[j] = pj;
-    wave_sync();
-    double ddir = dot_ordered<G>(sh.gs, sh.ps, dp);
+    double ddir = lane_tree_sum<G, double>(gj * pj);
     if (!(ddir < 0.0)) {
 #pragma unroll
       for (int c = 0; c < G; ++c) h[c] = (c == j) ? 1.0 : 0.0;
       pj = own ? -gj : 0.0;
-      sh.ps[j] = pj;
-      wave_sync();
-      ddir = dot_ordered<G>(sh.gs, sh.ps, dp);
+      ddir = lane_tree_sum<G, double>(gj * pj);
     }
+    sh.ps[j] = pj;
+    wave_sync();
 
     // -- Armijo backtracking (Alg. 6) ---------------------------------------
     int taken;
     if (hi) {
-      taken = armijo_search<OBJ, G, double>(L, q, shrink, sh, R, leaders, f, ddir);
+      taken = armijo_search<OBJ, G, double>(L, sh, f, ddir);
     } else {
-      taken = armijo_search<OBJ, G, T>(L, q, shrink, sh, R, leaders, f, ddir);
+      taken = armijo_search<OBJ, G, T>(L, sh, f, ddir);
       if (taken < 0) {
         ls_trials += q.iter_ls;
         hi = true;  // escalate: FP32 cannot resolve this decrease
         fresh = true;
-        zero_terms();
         continue;
       }
     }
@@ -331,13 +335,15 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
       alpha = sh.al[nshrink];
     } else {
       alpha = sh.al[kTabTrials - 1];
-      for (int e = kTabTrials - 1; e < nshrink; ++e) alpha = alpha * shrink;
+      for (int e = kTabTrials - 1; e < nshrink; ++e) alpha = alpha * q.shrink;
     }
 
-    // -- step ----------------------------------------------------------------
+    // -- step: x_new = x + alpha p, s = x_new - x -----------------------------
     const double xnew = xj + alpha * pj;
     sj = own ? xnew - xj : 0.0;
-    sh.xs[j] = own ? xnew : 0.0;
+    xj = own ? xnew : 0.0;
+    wave_sync();  // every lane has read xs in the line search
+    sh.xs[j] = xj;
   }
 }
 
@@ -414,39 +420,46 @@ __global__ __launch_bounds__(kSumBlock) void summary_kernel(const ReqDev *reqs) 
   }
 }
 
+// The kernel is persistent: it gets as many blocks as can be resident at once
+// (more would only start once the work counter is spent).
 template <int OBJ, int G, class T>
-hipError_t launch_g(const Group &g, int R, int blocks) {
-  using E = Elem<OBJ>;
-  const size_t lds = sizeof(double) * (size_t)group_stride(G, E::K, R) * (kBfgsBlock / G);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
+hipError_t launch_g(const Group &g, int64_t want, int cus) {
+  const size_t lds = sizeof(double) * (size_t)group_stride(G) * (kBfgsBlock / G);
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void *>(&bfgs_kernel<OBJ, G, T>), kBfgsBlock, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  const int64_t cap = (int64_t)cus * per_cu;
+  const int blocks = (int)(want < cap ? want : cap);
   hipLaunchKernelGGL((bfgs_kernel<OBJ, G, T>), dim3(blocks), dim3(kBfgsBlock), lds, g.stream,
-                     g.reqs, g.nreq, g.hdr, g.total_starts, R);
+                     g.reqs, g.nreq, g.hdr, g.total_starts);
   return hipGetLastError();
 }
 
 template <int OBJ, class T>
-hipError_t launch_obj(const Group &g, int R, int blocks) {
+hipError_t launch_obj(const Group &g, int64_t want, int cus) {
   switch (g.g_bfgs) {
-    case 2: return launch_g<OBJ, 2, T>(g, R, blocks);
-    case 4: return launch_g<OBJ, 4, T>(g, R, blocks);
-    case 8: return launch_g<OBJ, 8, T>(g, R, blocks);
-    case 16: return launch_g<OBJ, 16, T>(g, R, blocks);
-    case 32: return launch_g<OBJ, 32, T>(g, R, blocks);
-    case 64: return launch_g<OBJ, 64, T>(g, R, blocks);
+    case 2: return launch_g<OBJ, 2, T>(g, want, cus);
+    case 4: return launch_g<OBJ, 4, T>(g, want, cus);
+    case 8: return launch_g<OBJ, 8, T>(g, want, cus);
+    case 16: return launch_g<OBJ, 16, T>(g, want, cus);
+    case 32: return launch_g<OBJ, 32, T>(g, want, cus);
+    case 64: return launch_g<OBJ, 64, T>(g, want, cus);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <class T>
-hipError_t launch_prec(const Group &g, int R, int blocks) {
+hipError_t launch_prec(const Group &g, int64_t want, int cus) {
   switch (g.objective) {
-    case kRosenbrock: return launch_obj<kRosenbrock, T>(g, R, blocks);
-    case kRastrigin: return launch_obj<kRastrigin, T>(g, R, blocks);
-    case kAckley: return launch_obj<kAckley, T>(g, R, blocks);
-    case kStyblinskiTang: return launch_obj<kStyblinskiTang, T>(g, R, blocks);
-    case kGoldsteinPrice: return launch_obj<kGoldsteinPrice, T>(g, R, blocks);
-    case kSphere: return launch_obj<kSphere, T>(g, R, blocks);
-    case kQuartic: return launch_obj<kQuartic, T>(g, R, blocks);
+    case kRosenbrock: return launch_obj<kRosenbrock, T>(g, want, cus);
+    case kRastrigin: return launch_obj<kRastrigin, T>(g, want, cus);
+    case kAckley: return launch_obj<kAckley, T>(g, want, cus);
+    case kStyblinskiTang: return launch_obj<kStyblinskiTang, T>(g, want, cus);
+    case kGoldsteinPrice: return launch_obj<kGoldsteinPrice, T>(g, want, cus);
+    case kSphere: return launch_obj<kSphere, T>(g, want, cus);
+    case kQuartic: return launch_obj<kQuartic, T>(g, want, cus);
     default: return hipErrorInvalidValue;
   }
 }
@@ -471,32 +484,17 @@ int group_lanes(int dim) {
 
 // Line-search trials evaluated per round (a power of two <= G; default 4,
 // ZEUS_LS_TRIALS overrides it for experiments).
-int trials_per_round(int G) {
-  static int want = [] {
-    const char *e = getenv("ZEUS_LS_TRIALS");
-    int v = e ? atoi(e) : 4;
-    int r = 1;
-    while (r < v && r < 64) r <<= 1;
-    return r;
-  }();
-  return want < G ? want : G;
-}
-
 hipError_t launch_bfgs(const Group &g) {
   if (g.g_bfgs > kMaxDim) return hipErrorInvalidValue;
-  const int R = trials_per_round(g.g_bfgs);
   const int64_t starts_per_block = (int64_t)(kBfgsBlock / g.g_bfgs);
   int dev = 0;
   (void)hipGetDevice(&dev);
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
-  // enough resident blocks to fill the chip; the work counter balances them
   const int64_t want = (g.total_starts + starts_per_block - 1) / starts_per_block;
-  const int64_t cap = (int64_t)cus * 8;
-  const int blocks = (int)(want < cap ? want : cap);
-  if (g.precision == ZEUS_MIXED) return launch_prec<float>(g, R, blocks);
-  return launch_prec<double>(g, R, blocks);
+  if (g.precision == ZEUS_MIXED) return launch_prec<float>(g, want, cus);
+  return launch_prec<double>(g, want, cus);
 }
 
 hipError_t launch_summary(const Group &g) {

@@ -1,6 +1,7 @@
 // zeus_group.h -- a group of G lanes (G a power of two, G <= 64, so a group
 // never spans two wavefronts) working on one particle or one start.  Lane j
-// owns coordinate j; the group exchanges vectors through its own slice of LDS.
+// owns coordinate j; the group exchanges whole vectors through its own slice
+// of LDS and reduces across its lanes in registers.
 #pragma once
 
 #include "zeus_device.h"
@@ -31,94 +32,105 @@ struct GroupLanes {
   }
 };
 
-// Index-order reductions over zero-padded LDS vectors.  Entries from n up to
-// the next multiple of the chunk size CH are exact zeros, so they can be added
-// without a per-element test: x + 0 == x (up to the sign of a zero result),
-// and the result rounds exactly like a left-to-right loop over the first n
-// entries starting from 0.0.  Each chunk's loads are issued together.
-template <int G>
-struct Chunk {
-  static constexpr int CH = G < 8 ? G : 8;
-  __device__ __forceinline__ static int padded(int n) { return (n + CH - 1) / CH * CH; }
-};
-
-template <int G, class T>
-__device__ __forceinline__ T sum_ordered(const T *a, int n) {
-  constexpr int CH = Chunk<G>::CH;
-  T acc = T(0);
-  for (int c0 = 0; c0 < n; c0 += CH) {
-    T v[CH];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) v[q] = a[c0 + q];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) acc = acc + v[q];
-  }
-  return acc;
+// ---------------------------------------------------------------------------
+// Sums.  Every sum over an objective's terms or over coordinates is the
+// balanced pairwise sum: a sum of n > 1 values is the sum of its first h
+// values plus the sum of the rest, h the largest power of two below n.  Over
+// a zero-padded power-of-two block of P >= n slots this is the complete
+// binary tree ((v0 + v1) + (v2 + v3)) + ..., because a subtree holding only
+// padding contributes an exact zero (x + 0 == x up to the sign of a zero).
+//
+// Across lanes the tree is a butterfly: at each level a lane adds the partial
+// sum of the lane that mirrors it in the next larger aligned block.  IEEE
+// addition is commutative, so both partners get the same bits and after
+// log2(N) levels every lane of an aligned N-lane block holds the block's sum.
+// The first four levels use DPP lane permutations (quad_perm, row_half_mirror,
+// row_mirror) that stay inside rows of 16 lanes; the last two go through
+// ds_bpermute.  Callers must have every lane of the block active.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// sum_i a_i b_i in index order, products and sums rounded separately
-template <int G>
-__device__ __forceinline__ double dot_ordered(const double *a, const double *b, int n) {
-  constexpr int CH = Chunk<G>::CH;
-  double acc = 0.0;
-  for (int c0 = 0; c0 < n; c0 += CH) {
-    double va[CH], vb[CH];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      va[q] = a[c0 + q];
-      vb[q] = b[c0 + q];
-    }
-#pragma unroll
-    for (int q = 0; q < CH; ++q) acc = acc + va[q] * vb[q];
-  }
-  return acc;
+constexpr int kDppXor1 = 0xB1;        // quad_perm(1,0,3,2)
+constexpr int kDppXor2 = 0x4E;        // quad_perm(2,3,0,1)
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within 16
+
+template <int N, class T>
+__device__ __forceinline__ T lane_tree_sum(T v) {
+  static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two <= 64");
+  if constexpr (N >= 2) v = v + dpp_move<kDppXor1>(v);
+  if constexpr (N >= 4) v = v + dpp_move<kDppXor2>(v);
+  if constexpr (N >= 8) v = v + dpp_move<kDppHalfMirror>(v);
+  if constexpr (N >= 16) v = v + dpp_move<kDppMirror>(v);
+  if constexpr (N >= 32) v = v + __shfl_xor(v, 16, 64);
+  if constexpr (N >= 64) v = v + __shfl_xor(v, 32, 64);
+  return v;
 }
 
-// Sequential sums S_k = tv[k][0] + ... + tv[k][m-1] for the K term sums of a
-// [K][G] term buffer whose entries from m on are zero.
-template <int K, int G, class T>
-__device__ __forceinline__ void ordered_sums(const T *tv, int m, T *s) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) s[k] = sum_ordered<G, T>(tv + k * G, m);
+// Pairwise sum of B (a power of two) consecutive values held by one lane.
+template <int B, class T>
+__device__ __forceinline__ T reg_tree_sum(const T *v) {
+  if constexpr (B == 1) {
+    return v[0];
+  } else {
+    return reg_tree_sum<B / 2, T>(v) + reg_tree_sum<B / 2, T>(v + B / 2);
+  }
 }
 
 // Value of the objective at the point whose coordinates are xs[0..d-1] in the
 // group's LDS, evaluated in number type T: lane c < m evaluates term c and
-// stores it in tv[k*G + c], then every lane adds the terms up in index order.
-// tv[k*G + c] must be zero for c >= m.  All lanes of the group must call it.
+// the group adds the terms pairwise.  All lanes of the group must call it.
 template <int OBJ, int G, class T>
-__device__ __forceinline__ double group_value(const GroupLanes<G> &L, int d, const double *xs,
-                                              T *tv) {
+__device__ __forceinline__ double group_value(const GroupLanes<G> &L, int d, const double *xs) {
   using E = Elem<OBJ>;
   const int m = E::terms(d);
+  T out[E::K];
+#pragma unroll
+  for (int k = 0; k < E::K; ++k) out[k] = T(0);
   if (L.j < m) {
-    T w[E::W], out[E::K];
+    T w[E::W];
 #pragma unroll
     for (int q = 0; q < E::W; ++q) w[q] = (T)xs[L.j + q];
     E::template term<T>(w, out);
-#pragma unroll
-    for (int k = 0; k < E::K; ++k) tv[k * G + L.j] = out[k];
   }
-  wave_sync();
   T s[E::K];
-  ordered_sums<E::K, G, T>(tv, m, s);
+#pragma unroll
+  for (int k = 0; k < E::K; ++k) s[k] = lane_tree_sum<G, T>(out[k]);
   return (double)E::template outer<T>(d, s);
 }
 
 // Value and gradient at xs (forward mode, Alg. 5) in number type T: lane
-// j < d returns df/dx_j in *gj; every lane returns f.  Lane j evaluates on
-// dual numbers seeded with e_j the terms whose window holds x_j (in ascending
-// term order, the order in which the full pass adds them), and its own term's
-// value for the shared sums.
+// j < d returns df/dx_j in *gj (0 for j >= d); every lane returns f.  Lane j
+// evaluates on dual numbers seeded with e_j the terms whose window holds x_j
+// (in ascending term order) and keeps its own term's value for the shared
+// sums.  Every other term of Alg. 5's pass j has a zero tangent, and with at
+// most two nonzero tangents (window W <= 2) the pairwise sum of pass j adds
+// exactly these, so lane j gets the tangent of the full pass j.
 template <int OBJ, int G, class T>
 __device__ __forceinline__ double group_value_grad(const GroupLanes<G> &L, int d,
-                                                   const double *xs, T *tv, double *gj) {
+                                                   const double *xs, double *gj) {
   using E = Elem<OBJ>;
+  static_assert(E::W <= 2, "the tangent sum assumes at most two terms per coordinate");
   const int m = E::terms(d);
   const int j = L.j;
-  T tan[E::K];
+  T tan[E::K], val[E::K];
 #pragma unroll
-  for (int k = 0; k < E::K; ++k) tan[k] = T(0);
+  for (int k = 0; k < E::K; ++k) {
+    tan[k] = T(0);
+    val[k] = T(0);
+  }
   if (j < d) {
 #pragma unroll
     for (int back = E::W - 1; back >= 0; --back) {
@@ -132,16 +144,13 @@ __device__ __forceinline__ double group_value_grad(const GroupLanes<G> &L, int d
         for (int k = 0; k < E::K; ++k) tan[k] = tan[k] + out[k].t;
         if (back == 0)
 #pragma unroll
-          for (int k = 0; k < E::K; ++k) tv[k * G + j] = out[k].v;
+          for (int k = 0; k < E::K; ++k) val[k] = out[k].v;
       }
     }
   }
-  wave_sync();
-  T sv[E::K];
-  ordered_sums<E::K, G, T>(tv, m, sv);
   dual<T> sd[E::K];
 #pragma unroll
-  for (int k = 0; k < E::K; ++k) sd[k] = dual<T>{sv[k], tan[k]};
+  for (int k = 0; k < E::K; ++k) sd[k] = dual<T>{lane_tree_sum<G, T>(val[k]), tan[k]};
   const dual<T> r = E::template outer<dual<T>>(d, sd);
   *gj = (j < d) ? (double)r.t : 0.0;
   return (double)r.v;

@@ -127,7 +127,6 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
   using E = Elem<OBJ>;
   constexpr int kGroups = kPsoBlock / G;
   __shared__ double xs_all[kGroups][G];
-  __shared__ double tv_all[kGroups][E::K * G];
   __shared__ double uw_all[kGroups][2][G + 4];  // the group's uniforms, two streams
   __shared__ double gx_sh[kMaxDim];
   const int r = find_entry(reqs, nreq, blockIdx.x, [](const ReqDev &q) { return (int64_t)q.block_offset; });
@@ -136,12 +135,9 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
   const int blk = (int)blockIdx.x - a.block_offset;  // block within the request
   const GroupLanes<G> L;
   const int gib = threadIdx.x / G;  // group in block
-  double *xs = xs_all[gib], *tv = tv_all[gib];
+  double *xs = xs_all[gib];
   const int d = a.d, j = L.j, P = a.ws.pso_blocks;
   const int nb = (d + 3) >> 2;  // Philox blocks per stream
-  // term buffers: entries past the last term stay zero (see ordered_sums)
-  for (int q = threadIdx.x; q < kGroups * E::K * G; q += kPsoBlock) (&tv_all[0][0])[q] = 0.0;
-  __syncthreads();
 
   if (t > 0) global_best_after(a, t - 1, gx_sh, blk == 0, nullptr, nullptr);
   const double gxj = (t > 0 && j < d) ? gx_sh[j] : 0.0;
@@ -192,7 +188,7 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
     }
     wave_sync();
     if (live) {
-      const double f = group_value<OBJ, G, double>(L, d, xs, tv);
+      const double f = group_value<OBJ, G, double>(L, d, xs);
       bool improved = true;
       double pf = f;
       if (t > 0) {
