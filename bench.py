@@ -80,6 +80,18 @@ def algorithmic_flops(obj, d, n_starts, total_iters, total_ls_trials):
     return n_starts * (grad + 2 * d) + total_iters * per_iter + total_ls_trials * (fp + 2 * d)
 
 
+def profiled_traffic(workload):
+    """HBM bytes per launch of the BFGS kernel on this workload, read from the
+    committed rocprofv3 summary (FETCH_SIZE + WRITE_SIZE scaled by a copy
+    kernel's), or None when there is none or the kernel's sources have changed
+    since it was taken."""
+    from paper_2603_28770_amd import rocprof_summary as RS
+    s = RS.load(os.path.join(ROOT, "profiles", f"bfgs_kernel_{workload}.md"))
+    if not s or s.get("sources_sha256") != RS.sources_sha256("bfgs_kernel"):
+        return None
+    return s.get("traffic_bytes")
+
+
 def cpu_baseline(p):
     """The oracle on the full workload: its sequential PSO, then BFGS from every
     start with OpenMP over starts on all threads it is given."""
@@ -202,7 +214,7 @@ def main():
                       "reduce": prof["reduce_ms"] / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "bfgs_kernel",
+                     "traffic": profiled_traffic(args.workload), "kernel": "bfgs_kernel",
                      "flops_per_launch": flops},
     }
     if mixed is not None:

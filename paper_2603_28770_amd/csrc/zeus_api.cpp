@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -64,7 +65,7 @@ zeus_err check_problem(const zeus_problem *p) {
   if (p->required_converged < 0) return fail(ZEUS_EINVAL, "required_converged must be >= 0");
   if (p->required_converged != 0)
     return fail(ZEUS_EUNSUPPORTED, "early stopping (required_converged > 0) is not built");
-  if (p->dim > zeus::kMaxDim) return fail(ZEUS_EUNSUPPORTED, "dim > 64 is not built");
+  if (p->dim > zeus::kMaxDim) return fail(ZEUS_EUNSUPPORTED, "dim > 256 is not built");
   return ZEUS_OK;
 }
 
@@ -215,12 +216,23 @@ struct Planned {
   zeus::Workspace ws;
 };
 
+int max_dim(const std::vector<Planned> &reqs) {
+  int d = 0;
+  for (const Planned &q : reqs) d = q.pb->dim > d ? q.pb->dim : d;
+  return d;
+}
+
+// Device bytes of the H slots a group needs (0 unless its problems are wide).
+size_t hslot_bytes(int g_bfgs, int64_t total_starts, int dmax) {
+  return g_bfgs == zeus::kWideLanes ? align_up(zeus::wide_hslot_bytes(total_starts, dmax)) : 0;
+}
+
 // Enqueues the whole method for a group of requests that share objective,
 // precision and lane counts: table upload, counter reset, swarm sweeps
 // 0..max iter_pso, swarm finish, one BFGS launch over all their starts, one
 // summary block per request, then the optional swarm-state copies.
 zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void *hdr_table,
-                       hipStream_t stream) {
+                       void *hslots, hipStream_t stream) {
   const zeus_problem &p0 = *reqs[0].pb;
   zeus::Group g;
   g.objective = p0.objective;
@@ -234,6 +246,10 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
   g.hdr = static_cast<zeus::BatchDev *>(hdr_table);
   g.reqs = reinterpret_cast<const zeus::ReqDev *>(static_cast<char *>(hdr_table) + kHdrBytes);
   g.stream = stream;
+  g.hslots = static_cast<double *>(hslots);
+  g.wide_slots = 0;
+  g.wide_cs = 0;
+  g.wide_slot_doubles = 0;
   std::vector<zeus::ReqDev> host(reqs.size());
   for (size_t r = 0; r < reqs.size(); ++r) {
     const zeus_problem &p = *reqs[r].pb;
@@ -269,6 +285,13 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
     g.total_starts += p.n_starts;
     g.pso_grid += q.ws.pso_blocks;
     if (p.iter_pso > g.max_iter_pso) g.max_iter_pso = p.iter_pso;
+  }
+  if (g.g_bfgs == zeus::kWideLanes) {
+    const int dmax = max_dim(reqs);
+    g.wide_slots = zeus::wide_slots(g.total_starts);
+    g.wide_cs = zeus::wide_cs(dmax);
+    g.wide_slot_doubles = (int64_t)dmax * g.wide_cs;
+    if (!hslots) return fail(ZEUS_EINVAL, "wide problem without H slots");
   }
   hipError_t e = hipMemcpyAsync(const_cast<zeus::ReqDev *>(g.reqs), host.data(),
                                 sizeof(zeus::ReqDev) * host.size(), hipMemcpyHostToDevice, stream);
@@ -418,7 +441,8 @@ zeus_err zeus_workspace_bytes(const zeus_problem *problem, size_t *bytes) {
   if (!bytes) return fail(ZEUS_EINVAL, "bytes is NULL");
   zeus_err e = check_problem(problem);
   if (e != ZEUS_OK) return e;
-  *bytes = kHdrBytes + table_bytes(1) + zeus::workspace_bytes(problem->n_starts, problem->dim);
+  *bytes = kHdrBytes + table_bytes(1) + zeus::workspace_bytes(problem->n_starts, problem->dim) +
+           hslot_bytes(zeus::group_lanes(problem->dim), problem->n_starts, problem->dim);
   return ZEUS_OK;
 }
 
@@ -512,8 +536,12 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, voi
     one[0].dev.trace = nullptr;
     one[0].dev.trace_len = 0;
   }
+  const size_t ws_bytes = zeus::workspace_bytes(pb.n_starts, pb.dim);
   one[0].ws = zeus::carve_workspace(base + kHdrBytes + table_bytes(1), pb.n_starts, pb.dim);
-  return enqueue_group(ctx, one, base, s);
+  void *hslots = hslot_bytes(zeus::group_lanes(pb.dim), pb.n_starts, pb.dim)
+                     ? base + kHdrBytes + table_bytes(1) + ws_bytes
+                     : nullptr;
+  return enqueue_group(ctx, one, base, hslots, s);
 }
 
 zeus_err zeus_minimize(zeus_context *ctx, const zeus_problem *problem, const zeus_result *out) {
@@ -554,10 +582,20 @@ zeus_err zeus_minimize_batch(zeus_context *ctx, const zeus_problem *problems, in
     ws_off[r] = ws_total;
     ws_total += zeus::workspace_bytes(problems[r].n_starts, problems[r].dim);
   }
-  std::vector<size_t> tab_off(order.size());
+  std::vector<size_t> tab_off(order.size()), h_off(order.size());
   for (size_t gi = 0; gi < order.size(); ++gi) {
+    const std::vector<int32_t> &members = groups[order[gi]];
     tab_off[gi] = ws_total;
-    ws_total += kHdrBytes + table_bytes((int)groups[order[gi]].size());
+    ws_total += kHdrBytes + table_bytes((int)members.size());
+    int64_t starts = 0;
+    int dmax = 0;
+    for (int32_t r : members) {
+      starts += problems[r].n_starts;
+      dmax = problems[r].dim > dmax ? problems[r].dim : dmax;
+    }
+    const size_t hb = hslot_bytes(order[gi].g_bfgs, starts, dmax);
+    h_off[gi] = hb ? ws_total : SIZE_MAX;
+    ws_total += hb;
   }
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
@@ -587,7 +625,8 @@ zeus_err zeus_minimize_batch(zeus_context *ctx, const zeus_problem *problems, in
       plan[k].ws = zeus::carve_workspace(static_cast<char *>(ctx->ws) + ws_off[r],
                                          problems[r].n_starts, problems[r].dim);
     }
-    if ((e = enqueue_group(ctx, plan, static_cast<char *>(ctx->ws) + tab_off[gi], s)) != ZEUS_OK)
+    void *hs = h_off[gi] == SIZE_MAX ? nullptr : static_cast<char *>(ctx->ws) + h_off[gi];
+    if ((e = enqueue_group(ctx, plan, static_cast<char *>(ctx->ws) + tab_off[gi], hs, s)) != ZEUS_OK)
       return e;
     for (int32_t r : members)
       if ((e = copy_back(problems[r], outs[r], dev[r], s)) != ZEUS_OK) return e;

@@ -24,26 +24,10 @@
 // start is in.
 #include <cstdlib>
 
-#include "zeus_device.h"
-#include "zeus_group.h"
-#include "zeus_internal.h"
+#include "zeus_bfgs_common.h"
 
 namespace zeus {
 namespace {
-
-// The scalars of a start's request that every iteration reads, kept in the
-// group's LDS slice (registers hold only the request index; output pointers
-// are read from the request table when a start retires).
-struct ReqHot {
-  int d, m;                  // dimension, number of terms
-  int iter_bfgs, iter_ls, trace_len, ri;
-  double armijo_c, tol, shrink;
-};
-constexpr int kHotDoubles = (sizeof(ReqHot) + 7) / 8;
-
-// Step lengths alpha_t = shrink^t of the first kTabTrials trials, each the
-// product of the previous one and shrink, as Alg. 6 forms them.
-constexpr int kTabTrials = 32;
 
 // Per-group LDS slice: the vectors that every lane of the group reads in
 // full.  Entries from the dimension on are zero.
@@ -88,13 +72,7 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const Group
   const int d = q.d, m = q.m;
   for (int base = 0; base < q.iter_ls; base += R) {
     const int t = base + trial_slot;
-    double alpha;
-    if (t < kTabTrials) {
-      alpha = sh.al[t];
-    } else {
-      alpha = sh.al[kTabTrials - 1];
-      for (int e = kTabTrials - 1; e < t; ++e) alpha = alpha * q.shrink;
-    }
+    const double alpha = step_length(sh.al, q.shrink, t);
     U tv[E::K][R];
 #pragma unroll
     for (int b = 0; b < R; ++b) {
@@ -179,35 +157,13 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
         got = __shfl(got, L.grp * G, 64);
       }
       if (got >= (unsigned long long)total) break;
-      // the request holding global start `got`
-      int lo = 0, hi2 = nreq - 1;
-      while (lo < hi2) {
-        const int mid = (lo + hi2 + 1) >> 1;
-        if (reqs[mid].start_offset <= (int64_t)got) lo = mid;
-        else hi2 = mid - 1;
-      }
-      const ReqDev &rq = reqs[lo];
+      const int ri = request_of(reqs, nreq, (int64_t)got);
+      const ReqDev &rq = reqs[ri];
       idx = (int64_t)got - rq.start_offset;
       const int d0 = rq.d;
-      const double shrink = rq.shrink;
-      if (j == 0) {
-        ReqHot &w = *sh.q;
-        w.d = d0;
-        w.m = E::terms(d0);
-        w.iter_bfgs = rq.iter_bfgs;
-        w.iter_ls = rq.iter_ls;
-        w.trace_len = rq.trace ? rq.trace_len : 0;
-        w.ri = lo;
-        w.armijo_c = rq.armijo_c;
-        w.tol = rq.tol;
-        w.shrink = shrink;
-      }
+      if (j == 0) load_hot<OBJ>(*sh.q, rq, ri);
       own = j < d0;
-      for (int t = j; t < kTabTrials; t += G) {  // step lengths of this request
-        double al = 1.0;
-        for (int e = 0; e < t; ++e) al = al * shrink;
-        sh.al[t] = al;
-      }
+      fill_step_lengths(sh.al, rq.shrink, j, G);
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
       sh.xs[j] = xj;
 #pragma unroll
@@ -236,9 +192,7 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
         const double rho = 1.0 / sy;
         sh.vs[j] = yj;
         wave_sync();
-        double uj = 0.0;
-#pragma unroll
-        for (int c = 0; c < G; ++c) uj = __builtin_fma(h[c], sh.vs[c], uj);
+        double uj = row_dot<G>(h, sh.vs);
         uj = own ? uj : 0.0;
         const double yu = lane_tree_sum<G, double>(yj * uj);
         sh.us[j] = uj;
@@ -248,8 +202,7 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
         // H+ = H - rho (s u' + u s') + beta s s'   (row j, u = H y)
         const double au = -rho * sj;
         const double as = beta * sj - rho * uj;
-#pragma unroll
-        for (int c = 0; c < G; ++c) h[c] = __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], h[c]));
+        row_rank2<G>(h, au, sh.us, as, sh.ss);
         if (!__builtin_isfinite(au) || !__builtin_isfinite(as)) {
           // inf * 0 would have reached the padding: restore it
 #pragma unroll
@@ -301,10 +254,7 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     // -- search direction p = -H g (reset to -g if not a descent direction) -
     sh.vs[j] = gj;
     wave_sync();
-    double acc = 0.0;
-#pragma unroll
-    for (int c = 0; c < G; ++c) acc = __builtin_fma(h[c], sh.vs[c], acc);
-    pj = own ? -acc : 0.0;
+    pj = own ? -row_dot<G>(h, sh.vs) : 0.0;
     double ddir = lane_tree_sum<G, double>(gj * pj);
     if (!(ddir < 0.0)) {
 #pragma unroll
@@ -330,13 +280,7 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     }
     const int nshrink = taken >= 0 ? taken : q.iter_ls;
     ls_trials += taken >= 0 ? taken + 1 : q.iter_ls;
-    double alpha;
-    if (nshrink < kTabTrials) {
-      alpha = sh.al[nshrink];
-    } else {
-      alpha = sh.al[kTabTrials - 1];
-      for (int e = kTabTrials - 1; e < nshrink; ++e) alpha = alpha * q.shrink;
-    }
+    const double alpha = step_length(sh.al, q.shrink, nshrink);
 
     // -- step: x_new = x + alpha p, s = x_new - x -----------------------------
     const double xnew = xj + alpha * pj;
@@ -470,6 +414,7 @@ hipError_t launch_prec(const Group &g, int64_t want, int cus) {
 // per start than coordinates buy more line-search trials per round;
 // ZEUS_MIN_LANES overrides the floor for experiments).
 int group_lanes(int dim) {
+  if (dim > kMaxNarrowDim) return kWideLanes;
   static int floor_lanes = [] {
     const char *e = getenv("ZEUS_MIN_LANES");
     int v = e ? atoi(e) : 4;
@@ -485,16 +430,27 @@ int group_lanes(int dim) {
 // Line-search trials evaluated per round (a power of two <= G; default 4,
 // ZEUS_LS_TRIALS overrides it for experiments).
 hipError_t launch_bfgs(const Group &g) {
-  if (g.g_bfgs > kMaxDim) return hipErrorInvalidValue;
-  const int64_t starts_per_block = (int64_t)(kBfgsBlock / g.g_bfgs);
   int dev = 0;
   (void)hipGetDevice(&dev);
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
+  if (g.g_bfgs == kWideLanes) return launch_bfgs_wide(g, cus);
+  if (g.g_bfgs > kMaxNarrowDim) return hipErrorInvalidValue;
+  const int64_t starts_per_block = (int64_t)(kBfgsBlock / g.g_bfgs);
   const int64_t want = (g.total_starts + starts_per_block - 1) / starts_per_block;
   if (g.precision == ZEUS_MIXED) return launch_prec<float>(g, want, cus);
   return launch_prec<double>(g, want, cus);
+}
+
+int wide_slots(int64_t total_starts) {
+  return (int)(total_starts < kWideMaxSlots ? total_starts : kWideMaxSlots);
+}
+
+int wide_cs(int dmax) { return (dmax + 63) / 64 * 64; }
+
+size_t wide_hslot_bytes(int64_t total_starts, int dmax) {
+  return sizeof(double) * (size_t)wide_slots(total_starts) * (size_t)dmax * (size_t)wide_cs(dmax);
 }
 
 hipError_t launch_summary(const Group &g) {

@@ -1,0 +1,386 @@
+// zeus_bfgs_wide.hip -- the BFGS phase for 64 < d <= 256 (Alg. 4 / Alg. 10
+// with the dual-number gradient of Alg. 5 and the Armijo search of Alg. 6):
+// one block of 256 lanes per start.
+//
+//  * lane i owns coordinate i and row i of the inverse Hessian H;
+//  * a row of up to 256 doubles does not fit in registers, so H lives in a
+//    slot of device memory owned by the block, stored column by column
+//    (element (i, c) at c * CS + i, CS = the dimension rounded up to 64):
+//    every pass over H reads or writes consecutive addresses across the
+//    lanes.  A block keeps its slot for every start it runs;
+//  * per iteration H is read once by u = H y and once more by the rank-2
+//    update, which writes the new rows and forms p = -H_new g_new from them in
+//    the same pass (the search direction needs no third pass);
+//  * sums over coordinates and terms are the pairwise trees used everywhere:
+//    a butterfly inside each wavefront, then the four wavefront sums added
+//    pairwise through LDS;
+//  * the line search evaluates four trials per round, one per wavefront;
+//  * starts are claimed as by the narrow kernel: first the block's own index,
+//    then an agent-scope work counter.
+// The control flow is uniform across the block (one start per block), so
+// every barrier is reached by all its threads.
+#include "zeus_bfgs_common.h"
+
+namespace zeus {
+namespace {
+
+constexpr int kWide = kWideLanes;   // lanes (threads) per start
+constexpr int kWaves = kWide / 64;  // wavefronts per start == trials per round
+static_assert(kWaves == 4, "the pairwise combination of wave sums assumes four waves");
+
+struct WideShm {
+  double xs[kWide];  // iterate under evaluation (x, then x_new)
+  double ps[kWide];  // search direction
+  double vs[kWide];  // y, operand of u = H y
+  double gs[kWide];  // gradient, operand of p = -H g
+  double ss[kWide];  // s = x_new - x
+  double us[kWide];  // u = H y
+  double red[2][2][kWaves];  // [phase][sum][wave] partial sums
+  double al[kTabTrials];
+  int pass[2][kWaves];       // [phase][wave] line-search outcome
+  unsigned long long got;
+  ReqHot q;
+};
+
+// Pairwise sum over the block's 256 lanes of K values per lane.  Alternating
+// phases let one barrier per reduction suffice: a phase's slots are written
+// again only two reductions later, after every thread has passed the barrier
+// of the reduction in between (and so has read them).
+template <int K, class T>
+__device__ __forceinline__ void block_tree_sums(T (&v)[K], WideShm &sh, int &phase) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    v[k] = lane_tree_sum<64, T>(v[k]);
+    if (lane == 0) sh.red[phase][k][w] = (double)v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double *r = sh.red[phase][k];
+    v[k] = ((T)r[0] + (T)r[1]) + ((T)r[2] + (T)r[3]);
+  }
+  phase ^= 1;
+}
+
+__device__ __forceinline__ double block_tree_sum(double v, WideShm &sh, int &phase) {
+  double a[1] = {v};
+  block_tree_sums<1, double>(a, sh, phase);
+  return a[0];
+}
+
+// Objective value at xs in number type T (every thread returns it); lane j
+// also returns df/dx_j in *gj when `grad` (0 beyond the dimension).
+template <int OBJ, class T, bool kGrad>
+__device__ __forceinline__ double wide_eval(int d, const double *xs, double *gj, WideShm &sh,
+                                            int &phase) {
+  using E = Elem<OBJ>;
+  static_assert(E::W <= 2, "the tangent sum assumes at most two terms per coordinate");
+  const int m = E::terms(d);
+  const int j = threadIdx.x;
+  T tan[E::K], val[E::K];
+#pragma unroll
+  for (int k = 0; k < E::K; ++k) {
+    tan[k] = T(0);
+    val[k] = T(0);
+  }
+  if (kGrad) {
+    if (j < d) {
+#pragma unroll
+      for (int back = E::W - 1; back >= 0; --back) {
+        const int i = j - back;
+        if (i >= 0 && i < m) {
+          dual<T> w[E::W], out[E::K];
+#pragma unroll
+          for (int q = 0; q < E::W; ++q) w[q] = dual<T>{(T)xs[i + q], q == back ? T(1) : T(0)};
+          E::template term<dual<T>>(w, out);
+#pragma unroll
+          for (int k = 0; k < E::K; ++k) tan[k] = tan[k] + out[k].t;
+          if (back == 0)
+#pragma unroll
+            for (int k = 0; k < E::K; ++k) val[k] = out[k].v;
+        }
+      }
+    }
+  } else if (j < m) {
+    T w[E::W];
+#pragma unroll
+    for (int q = 0; q < E::W; ++q) w[q] = (T)xs[j + q];
+    E::template term<T>(w, val);
+  }
+  block_tree_sums<E::K, T>(val, sh, phase);
+  if (!kGrad) return (double)E::template outer<T>(d, val);
+  dual<T> sd[E::K];
+#pragma unroll
+  for (int k = 0; k < E::K; ++k) sd[k] = dual<T>{val[k], tan[k]};
+  const dual<T> r = E::template outer<dual<T>>(d, sd);
+  *gj = (j < d) ? (double)r.t : 0.0;
+  return (double)r.v;
+}
+
+// One Armijo search (Alg. 6) with the objective in number type U: wavefront w
+// evaluates trial base + w of each round; lane c of it takes the term slots
+// 4c .. 4c + 3 and adds them pairwise, the wavefront finishes the pairwise
+// sum.  Returns the index of the first passing trial, or -1.
+template <int OBJ, class U>
+__device__ __forceinline__ int wide_armijo(WideShm &sh, double f, double ddir, int &lsphase) {
+  using E = Elem<OBJ>;
+  constexpr int B = kWide / 64;  // term slots per lane
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const ReqHot &q = sh.q;
+  const int d = q.d, m = q.m;
+  for (int base = 0; base < q.iter_ls; base += kWaves) {
+    const int t = base + w;
+    const double alpha = step_length(sh.al, q.shrink, t);
+    U tv[E::K][B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int i = lane * B + b;
+      U out[E::K];
+#pragma unroll
+      for (int kk = 0; kk < E::K; ++kk) out[kk] = U(0);
+      if (i < m) {
+        U wv[E::W];
+#pragma unroll
+        for (int e = 0; e < E::W; ++e) wv[e] = (U)(sh.xs[i + e] + alpha * sh.ps[i + e]);
+        E::template term<U>(wv, out);
+      }
+#pragma unroll
+      for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = out[kk];
+    }
+    U sums[E::K];
+#pragma unroll
+    for (int kk = 0; kk < E::K; ++kk) sums[kk] = lane_tree_sum<64, U>(reg_tree_sum<B, U>(tv[kk]));
+    const double ft = (double)E::template outer<U>(d, sums);
+    const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
+    if (lane == 0) sh.pass[lsphase][w] = ok ? 1 : 0;
+    __syncthreads();
+    int first = -1;
+#pragma unroll
+    for (int v = kWaves - 1; v >= 0; --v)
+      if (sh.pass[lsphase][v]) first = v;
+    lsphase ^= 1;
+    if (first >= 0) return base + first;
+  }
+  return -1;
+}
+
+// See the narrow kernel for the mixed-precision rules (T = float): FP32
+// evaluation with escalation to FP64 near the minimum, on a non-finite value
+// or on a failed FP32 line search; H, s, y, p, g'p and Armijo stay FP64.
+template <int OBJ, class T>
+__global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, int nreq,
+                                                          BatchDev *hdr, int64_t total,
+                                                          double *hslots, int cs, int64_t slot) {
+  constexpr bool kMixed = sizeof(T) != sizeof(double);
+  __shared__ WideShm sh;
+  const int j = threadIdx.x;
+  double *H = hslots + (int64_t)blockIdx.x * slot;  // column c of row j at H[c * cs + j]
+  int phase = 0, lsphase = 0;
+  bool own = false, first = true, fresh = false, hi = !kMixed;
+  double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
+  int64_t idx = -1;
+  int k = 0, ls_trials = 0;
+  bool have_p = false;  // p = -H g already formed by the update pass
+
+  for (;;) {
+    if (idx < 0) {
+      if (j == 0) {
+        sh.got = first ? (unsigned long long)blockIdx.x
+                       : gridDim.x + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
+      }
+      first = false;
+      __syncthreads();
+      const unsigned long long got = sh.got;
+      if (got >= (unsigned long long)total) break;
+      const int ri = request_of(reqs, nreq, (int64_t)got);
+      const ReqDev &rq = reqs[ri];
+      idx = (int64_t)got - rq.start_offset;
+      const int d0 = rq.d;
+      if (j == 0) load_hot<OBJ>(sh.q, rq, ri);
+      fill_step_lengths(sh.al, rq.shrink, j, kWide);
+      own = j < d0;
+      xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
+      sh.xs[j] = xj;
+      if (own)  // H <- I
+        for (int c = 0; c < d0; ++c) H[(int64_t)c * cs + j] = (c == j) ? 1.0 : 0.0;
+      k = 0;
+      ls_trials = 0;
+      fresh = true;
+      hi = !kMixed;
+      have_p = false;
+    }
+    __syncthreads();  // xs and the request are visible; earlier reads are done
+    const ReqHot &q = sh.q;
+    const int d = q.d;
+
+    // -- value and gradient at xs -------------------------------------------
+    double gn, fn;
+    if (hi)
+      fn = wide_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase);
+    else
+      fn = wide_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase);
+
+    // -- after a step: y, u = H y, the rank-2 update and p = -H_new g_new ----
+    have_p = false;
+    if (!fresh) {
+      const double yj = gn - gj;
+      const double sy = block_tree_sum(yj * sj, sh, phase);
+      if (sy > 0.0) {
+        const double rho = 1.0 / sy;
+        sh.vs[j] = yj;
+        sh.gs[j] = gn;
+        __syncthreads();
+        double uj = 0.0;
+        if (own) {
+          const double *hc = H + j;
+#pragma unroll 8
+          for (int c = 0; c < d; ++c) uj = __builtin_fma(hc[(int64_t)c * cs], sh.vs[c], uj);
+        }
+        const double yu = block_tree_sum(yj * uj, sh, phase);
+        sh.us[j] = uj;
+        sh.ss[j] = sj;
+        __syncthreads();
+        const double beta = (rho * rho) * yu + rho;
+        const double au = -rho * sj;
+        const double as = beta * sj - rho * uj;
+        // H+ = H - rho (s u' + u s') + beta s s'   (row j), then p_j = -(H+ g)_j
+        double acc = 0.0;
+        if (own) {
+          double *hc = H + j;
+#pragma unroll 8
+          for (int c = 0; c < d; ++c) {
+            const double hn = __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], hc[(int64_t)c * cs]));
+            hc[(int64_t)c * cs] = hn;
+            acc = __builtin_fma(hn, sh.gs[c], acc);
+          }
+        }
+        pj = own ? -acc : 0.0;
+        have_p = true;
+      }
+      ++k;
+    }
+    gj = gn;
+    f = fn;
+    fresh = false;
+    if (q.trace_len && own && k < q.trace_len) reqs[q.ri].trace[(idx * q.trace_len + k) * d + j] = xj;
+
+    // -- termination ----------------------------------------------------------
+    const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
+    const bool any_bad = __syncthreads_or(bad) != 0;
+    const double gg = block_tree_sum(gj * gj, sh, phase);
+    if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * q.tol)) {
+      hi = true;
+      fresh = true;
+      continue;
+    }
+    int status = -1;
+    if (any_bad)
+      status = ZEUS_ST_NONFINITE;
+    else if (sqrt(gg) < q.tol)
+      status = ZEUS_ST_CONVERGED;
+    else if (k == q.iter_bfgs)
+      status = ZEUS_ST_MAXITER;
+    if (status >= 0) {
+      const ReqDev &rq = reqs[q.ri];
+      const int tl = q.trace_len;
+      if (own) rq.out_x[idx * d + j] = xj;
+      if (kMixed && !hi) f = wide_eval<OBJ, double, false>(d, sh.xs, nullptr, sh, phase);
+      if (j == 0) {
+        rq.out_f[idx] = f;
+        rq.out_iters[idx] = k;
+        rq.out_status[idx] = status;
+        if (rq.out_ls) rq.out_ls[idx] = ls_trials;
+      }
+      if (tl && own)
+        for (int kk = k + 1; kk < tl; ++kk) rq.trace[(idx * tl + kk) * d + j] = __builtin_nan("");
+      idx = -1;
+      continue;
+    }
+
+    // -- search direction p = -H g (formed above after an update) ------------
+    if (!have_p) {
+      sh.gs[j] = gj;
+      __syncthreads();
+      double acc = 0.0;
+      if (own) {
+        const double *hc = H + j;
+#pragma unroll 8
+        for (int c = 0; c < d; ++c) acc = __builtin_fma(hc[(int64_t)c * cs], sh.gs[c], acc);
+      }
+      pj = own ? -acc : 0.0;
+    }
+    double ddir = block_tree_sum(gj * pj, sh, phase);
+    if (!(ddir < 0.0)) {  // not a descent direction: H <- I, p = -g
+      if (own)
+        for (int c = 0; c < d; ++c) H[(int64_t)c * cs + j] = (c == j) ? 1.0 : 0.0;
+      pj = own ? -gj : 0.0;
+      ddir = block_tree_sum(gj * pj, sh, phase);
+    }
+    sh.ps[j] = pj;
+    __syncthreads();
+
+    // -- Armijo backtracking -----------------------------------------------------
+    int taken;
+    if (hi) {
+      taken = wide_armijo<OBJ, double>(sh, f, ddir, lsphase);
+    } else {
+      taken = wide_armijo<OBJ, T>(sh, f, ddir, lsphase);
+      if (taken < 0) {
+        ls_trials += q.iter_ls;
+        hi = true;
+        fresh = true;
+        continue;
+      }
+    }
+    const int nshrink = taken >= 0 ? taken : q.iter_ls;
+    ls_trials += taken >= 0 ? taken + 1 : q.iter_ls;
+    const double alpha = step_length(sh.al, q.shrink, nshrink);
+
+    // -- step -------------------------------------------------------------------
+    const double xnew = xj + alpha * pj;
+    sj = own ? xnew - xj : 0.0;
+    xj = own ? xnew : 0.0;
+    __syncthreads();  // every lane has read xs and ps in the line search
+    sh.xs[j] = xj;
+  }
+}
+
+template <int OBJ, class T>
+hipError_t launch_wide_t(const Group &g, int64_t want, int cus) {
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void *>(&bfgs_wide_kernel<OBJ, T>), kWide, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  int64_t cap = (int64_t)cus * per_cu;
+  if (cap > g.wide_slots) cap = g.wide_slots;
+  const int blocks = (int)(want < cap ? want : cap);
+  hipLaunchKernelGGL((bfgs_wide_kernel<OBJ, T>), dim3(blocks), dim3(kWide), 0, g.stream, g.reqs,
+                     g.nreq, g.hdr, g.total_starts, g.hslots, g.wide_cs, g.wide_slot_doubles);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_wide_prec(const Group &g, int64_t want, int cus) {
+  switch (g.objective) {
+    case kRosenbrock: return launch_wide_t<kRosenbrock, T>(g, want, cus);
+    case kRastrigin: return launch_wide_t<kRastrigin, T>(g, want, cus);
+    case kAckley: return launch_wide_t<kAckley, T>(g, want, cus);
+    case kStyblinskiTang: return launch_wide_t<kStyblinskiTang, T>(g, want, cus);
+    case kSphere: return launch_wide_t<kSphere, T>(g, want, cus);
+    case kQuartic: return launch_wide_t<kQuartic, T>(g, want, cus);
+    default: return hipErrorInvalidValue;  // Goldstein-Price has d == 2
+  }
+}
+
+}  // namespace
+
+hipError_t launch_bfgs_wide(const Group &g, int cus) {
+  if (!g.hslots || g.wide_slots < 1) return hipErrorInvalidValue;
+  const int64_t want = g.total_starts;
+  if (g.precision == ZEUS_MIXED) return launch_wide_prec<float>(g, want, cus);
+  return launch_wide_prec<double>(g, want, cus);
+}
+
+}  // namespace zeus

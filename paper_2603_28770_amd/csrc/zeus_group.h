@@ -89,26 +89,94 @@ __device__ __forceinline__ T reg_tree_sum(const T *v) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Row j of H against vectors that every lane reads from the group's LDS.  The
+// vectors are read in chunks, the next chunk's loads written before the
+// current chunk's arithmetic, so that the scheduler issues them early and a
+// wave waits for LDS about once per chunk instead of once per pair of
+// elements.
+// ---------------------------------------------------------------------------
+template <int G>
+constexpr int kRowChunk = G < 16 ? G : 16;
+
+template <int N>
+__device__ __forceinline__ void lds_load(double (&b)[N], const double *v) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) b[c] = v[c];
+}
+
+// sum_c h[c] v[c] as one fused multiply-add chain in column order.
+template <int G>
+__device__ __forceinline__ double row_dot(const double (&h)[G], const double *v) {
+  constexpr int CH = kRowChunk<G>, NC = G / CH;
+  double buf[2][CH];
+  lds_load(buf[0], v);
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (k + 1 < NC) lds_load(buf[(k + 1) & 1], v + (k + 1) * CH);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) acc = __builtin_fma(h[k * CH + c], buf[k & 1][c], acc);
+  }
+  return acc;
+}
+
+// h[c] <- fma(as, s[c], fma(au, u[c], h[c])) for every column c.
+template <int G>
+__device__ __forceinline__ void row_rank2(double (&h)[G], double au, const double *u, double as,
+                                          const double *s) {
+  constexpr int CH = kRowChunk<G> / 2 > 0 ? kRowChunk<G> / 2 : 1, NC = G / CH;
+  double bu[2][CH], bs[2][CH];
+  lds_load(bu[0], u);
+  lds_load(bs[0], s);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (k + 1 < NC) {
+      lds_load(bu[(k + 1) & 1], u + (k + 1) * CH);
+      lds_load(bs[(k + 1) & 1], s + (k + 1) * CH);
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      h[k * CH + c] = __builtin_fma(as, bs[k & 1][c], __builtin_fma(au, bu[k & 1][c], h[k * CH + c]));
+  }
+}
+
 // Value of the objective at the point whose coordinates are xs[0..d-1] in the
-// group's LDS, evaluated in number type T: lane c < m evaluates term c and
-// the group adds the terms pairwise.  All lanes of the group must call it.
-template <int OBJ, int G, class T>
-__device__ __forceinline__ double group_value(const GroupLanes<G> &L, int d, const double *xs) {
+// group's LDS, evaluated in number type T.  The group covers G * CPL term
+// slots: lane c evaluates the terms c, c + G, ..., c + (CPL-1) G (zero past
+// the last term); each block of G consecutive slots is summed by the lane
+// butterfly and the CPL block sums are added pairwise, which is the pairwise
+// tree over all G * CPL slots.  All lanes of the group must call it.
+template <int OBJ, int G, int CPL, class T>
+__device__ __forceinline__ double group_value_slots(const GroupLanes<G> &L, int d,
+                                                    const double *xs) {
   using E = Elem<OBJ>;
   const int m = E::terms(d);
-  T out[E::K];
+  T blk[E::K][CPL];
 #pragma unroll
-  for (int k = 0; k < E::K; ++k) out[k] = T(0);
-  if (L.j < m) {
-    T w[E::W];
+  for (int r = 0; r < CPL; ++r) {
+    const int i = L.j + G * r;
+    T out[E::K];
 #pragma unroll
-    for (int q = 0; q < E::W; ++q) w[q] = (T)xs[L.j + q];
-    E::template term<T>(w, out);
+    for (int k = 0; k < E::K; ++k) out[k] = T(0);
+    if (i < m) {
+      T w[E::W];
+#pragma unroll
+      for (int q = 0; q < E::W; ++q) w[q] = (T)xs[i + q];
+      E::template term<T>(w, out);
+    }
+#pragma unroll
+    for (int k = 0; k < E::K; ++k) blk[k][r] = lane_tree_sum<G, T>(out[k]);
   }
   T s[E::K];
 #pragma unroll
-  for (int k = 0; k < E::K; ++k) s[k] = lane_tree_sum<G, T>(out[k]);
+  for (int k = 0; k < E::K; ++k) s[k] = reg_tree_sum<CPL, T>(blk[k]);
   return (double)E::template outer<T>(d, s);
+}
+
+template <int OBJ, int G, class T>
+__device__ __forceinline__ double group_value(const GroupLanes<G> &L, int d, const double *xs) {
+  return group_value_slots<OBJ, G, 1, T>(L, d, xs);
 }
 
 // Value and gradient at xs (forward mode, Alg. 5) in number type T: lane

@@ -10,9 +10,15 @@
 
 namespace zeus {
 
-// Largest dimension the one-group-per-start kernels handle (a group is at most
-// one 64-lane wavefront; lane j owns row j of the inverse Hessian).
-constexpr int kMaxDim = 64;
+// Largest dimension of this build.  Up to kMaxNarrowDim a group of at most one
+// 64-lane wavefront runs a start with row j of the inverse Hessian in lane
+// j's registers; above it a block of kWideLanes lanes runs a start with the
+// rows in a device-memory slot of the block.
+constexpr int kMaxDim = 256;
+constexpr int kMaxNarrowDim = 64;
+constexpr int kWideLanes = 256;
+// Most H slots (resident wide blocks) a launch group uses.
+constexpr int kWideMaxSlots = 2048;
 constexpr int kPsoBlock = 256;
 constexpr int kBfgsBlock = 256;
 
@@ -84,18 +90,31 @@ struct Group {
   const ReqDev *reqs;        // device
   BatchDev *hdr;             // device
   hipStream_t stream;
+  // wide problems (g_bfgs == kWideLanes): the blocks' H slots
+  double *hslots;            // [wide_slots][wide_slot_doubles]
+  int wide_slots;
+  int wide_cs;               // column stride of a slot (max dim rounded up to 64)
+  int64_t wide_slot_doubles; // max dim * wide_cs
 };
+
+// H slots of a wide launch group whose largest dimension is dmax.
+int wide_slots(int64_t total_starts);
+int wide_cs(int dmax);
+size_t wide_hslot_bytes(int64_t total_starts, int dmax);
 
 // Kernel launchers (return the first HIP error, hipSuccess otherwise).
 hipError_t launch_ws_init(const Group &g);
 hipError_t launch_pso(const Group &g, int t);
 hipError_t launch_pso_finish(const Group &g);
 hipError_t launch_bfgs(const Group &g);
+hipError_t launch_bfgs_wide(const Group &g, int cus);
 hipError_t launch_summary(const Group &g);
 
-// Lanes per start of the BFGS kernel for a dimension (power of two >= dim).
+// Lanes per start of the BFGS kernel for a dimension (power of two >= dim, at
+// most 64; kWideLanes above kMaxNarrowDim).
 int group_lanes(int dim);
-// Lanes per particle of the swarm kernels, and one request's grid size.
+// Coordinate slots per particle of the swarm kernels (power of two >= dim;
+// lanes per particle are min(slots, 64)), and one request's grid size.
 int pso_group_lanes(int dim);
 int pso_blocks(int64_t n, int dim);
 

@@ -122,12 +122,13 @@ __device__ void global_best_after(const ReqDev &a, int done, double *gx_sh, bool
   }
 }
 
-template <int OBJ, int G>
+// G lanes per particle, each owning CPL coordinates j, j + G, ...
+template <int OBJ, int G, int CPL>
 __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int nreq, int t) {
-  using E = Elem<OBJ>;
   constexpr int kGroups = kPsoBlock / G;
-  __shared__ double xs_all[kGroups][G];
-  __shared__ double uw_all[kGroups][2][G + 4];  // the group's uniforms, two streams
+  constexpr int kSlots = G * CPL;
+  __shared__ double xs_all[kGroups][kSlots];
+  __shared__ double uw_all[kGroups][2][kSlots + 4];  // the group's uniforms, two streams
   __shared__ double gx_sh[kMaxDim];
   const int r = find_entry(reqs, nreq, blockIdx.x, [](const ReqDev &q) { return (int64_t)q.block_offset; });
   const ReqDev &a = reqs[r];
@@ -140,7 +141,9 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
   const int nb = (d + 3) >> 2;  // Philox blocks per stream
 
   if (t > 0) global_best_after(a, t - 1, gx_sh, blk == 0, nullptr, nullptr);
-  const double gxj = (t > 0 && j < d) ? gx_sh[j] : 0.0;
+  double gxj[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) gxj[c] = (t > 0 && j + G * c < d) ? gx_sh[j + G * c] : 0.0;
 
   // this block's best particle of the sweep, tracked by each group's lane 0
   double key = __builtin_huge_val(), val = __builtin_nan("");
@@ -150,52 +153,59 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
   for (int64_t i = (int64_t)blk * kGroups + gib;; i += stride) {
     const bool live = i < a.n;
     if (__ballot(live) == 0ull) break;  // the whole wave is past the end
-    // one Philox block per lane: lane l < 2 nb draws block (l mod nb) of
-    // stream a (l < nb) or b and shares its four words through LDS
-    if (live && j < 2 * nb) {
-      const int sb = j >= nb, jb = sb ? j - nb : j;
-      const u64x4 rw = philox4x64_10((uint64_t)jb, (uint64_t)i, (uint64_t)t, sb ? tag_b : tag_a,
-                                     a.k0, a.k1);
+    // Philox blocks b = j, j + G, ... below 2 nb: block (b mod nb) of stream a
+    // (b < nb) or b, its four words shared through LDS
+    if (live)
+      for (int b = j; b < 2 * nb; b += G) {
+        const int sb = b >= nb, jb = sb ? b - nb : b;
+        const u64x4 rw = philox4x64_10((uint64_t)jb, (uint64_t)i, (uint64_t)t, sb ? tag_b : tag_a,
+                                       a.k0, a.k1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) uw_all[gib][sb][jb * 4 + q] = u01(rw.w[q]);
-    }
+        for (int q = 0; q < 4; ++q) uw_all[gib][sb][jb * 4 + q] = u01(rw.w[q]);
+      }
     wave_sync();
-    const bool own = live && j < d;
-    double x = 0.0;
-    if (own) {
-      const int64_t o = i * d + j;
-      const double ua = uw_all[gib][0][j], ub = uw_all[gib][1][j];
+    double x[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int jj = j + G * c;
+      x[c] = 0.0;
+      if (!(live && jj < d)) continue;
+      const int64_t o = i * d + jj;
+      const double ua = uw_all[gib][0][jj], ub = uw_all[gib][1][jj];
       if (t == 0) {
         const double vlo = -a.vh, vhi = a.vh;
         // UniformSample(lo, hi) = lo + u (hi - lo)
-        x = a.lo + ua * (a.hi - a.lo);
+        x[c] = a.lo + ua * (a.hi - a.lo);
         const double v = vlo + ub * (vhi - vlo);
-        a.ws.x[o] = x;
+        a.ws.x[o] = x[c];
         a.ws.v[o] = v;
-        a.ws.px[o] = x;
+        a.ws.px[o] = x[c];
       } else {
         const double x0 = a.ws.x[o], v = a.ws.v[o];
         // v' = w v + c1 r1 (p - x) + c2 r2 (g - x);  x' = x + v'
         const double inertia = a.w * v;
         const double cog = (a.c1 * ua) * (a.ws.px[o] - x0);
-        const double soc = (a.c2 * ub) * (gxj - x0);
+        const double soc = (a.c2 * ub) * (gxj[c] - x0);
         const double vn = (inertia + cog) + soc;
-        x = x0 + vn;
+        x[c] = x0 + vn;
         a.ws.v[o] = vn;
-        a.ws.x[o] = x;
+        a.ws.x[o] = x[c];
       }
-      xs[j] = x;
+      xs[jj] = x[c];
     }
     wave_sync();
     if (live) {
-      const double f = group_value<OBJ, G, double>(L, d, xs);
+      const double f = group_value_slots<OBJ, G, CPL, double>(L, d, xs);
       bool improved = true;
       double pf = f;
       if (t > 0) {
         const double old = a.ws.pf[i];
         improved = rank_key(f) < rank_key(old);  // personal best, strict
         pf = improved ? f : old;
-        if (improved && own) a.ws.px[i * d + j] = x;
+        if (improved)
+#pragma unroll
+          for (int c = 0; c < CPL; ++c)
+            if (j + G * c < d) a.ws.px[i * d + j + G * c] = x[c];
       }
       if (j == 0) {
         if (improved) a.ws.pf[i] = pf;
@@ -234,10 +244,10 @@ __global__ void ws_init_kernel(BatchDev *hdr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) hdr->queue = 0ull;
 }
 
-template <int OBJ, int G>
+template <int OBJ, int G, int CPL = 1>
 hipError_t launch_g(const Group &g, int t) {
-  hipLaunchKernelGGL((pso_kernel<OBJ, G>), dim3(g.pso_grid), dim3(kPsoBlock), 0, g.stream, g.reqs,
-                     g.nreq, t);
+  hipLaunchKernelGGL((pso_kernel<OBJ, G, CPL>), dim3(g.pso_grid), dim3(kPsoBlock), 0, g.stream,
+                     g.reqs, g.nreq, t);
   return hipGetLastError();
 }
 
@@ -250,6 +260,8 @@ hipError_t launch_obj(const Group &g, int t) {
     case 16: return launch_g<OBJ, 16>(g, t);
     case 32: return launch_g<OBJ, 32>(g, t);
     case 64: return launch_g<OBJ, 64>(g, t);
+    case 128: return launch_g<OBJ, 64, 2>(g, t);
+    case 256: return launch_g<OBJ, 64, 4>(g, t);
     default: return hipErrorInvalidValue;
   }
 }
@@ -263,7 +275,8 @@ int pso_group_lanes(int dim) {
 }
 
 int pso_blocks(int64_t n, int dim) {
-  const int64_t per_block = kPsoBlock / pso_group_lanes(dim);
+  const int lanes = pso_group_lanes(dim) < 64 ? pso_group_lanes(dim) : 64;
+  const int64_t per_block = kPsoBlock / lanes;
   const int64_t want = (n + per_block - 1) / per_block;
   return (int)(want < kPsoMaxBlocks ? want : kPsoMaxBlocks);
 }

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libzeus.so")
+# ZEUS_LIB names another build of the same library (e.g. to compare builds).
+LIB_PATH = os.environ.get("ZEUS_LIB") or os.path.join(HERE, "libzeus.so")
 
 ABI_VERSION = 1
 OK, NOT_READY, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ECANCELLED, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6

@@ -92,7 +92,7 @@ def test_validation_abi_and_reserved(Z):
     assert Z.lib.zeus_validate(None) == Z.EINVAL
 
 
-@pytest.mark.parametrize("unsup", [dict(dim=65), dict(required_converged=5)])
+@pytest.mark.parametrize("unsup", [dict(dim=257), dict(required_converged=5)])
 def test_validation_unsupported(Z, unsup):
     assert Z.zeus_validate(Z.make_problem(_p(**unsup))) == Z.EUNSUPPORTED
 
@@ -106,6 +106,17 @@ def test_workspace_bytes(Z):
     assert 3 * 8 * n * d + 8 * n <= b <= 3 * 8 * n * d + 8 * n + 2 * 512 * (d + 3) * 8 + 64 * 1024
     with pytest.raises(Z.ZeusError):
         Z.zeus_workspace_bytes(Z.make_problem(_p(dim=0)))
+
+
+@pytest.mark.parametrize("n,d", [(100, 65), (5000, 200), (3000, 256)])
+def test_workspace_bytes_wide(Z, n, d):
+    """Above 64 dimensions the workspace also holds one inverse-Hessian slot per
+    resident block (at most 2048), d columns of the dimension rounded up to 64."""
+    b = Z.zeus_workspace_bytes(Z.make_problem(_p(n=n, dim=d)))
+    slots = min(n, 2048)
+    hs = 8 * slots * d * ((d + 63) // 64 * 64)
+    swarm = 3 * 8 * n * d + 8 * n
+    assert swarm + hs <= b <= swarm + hs + 2 * 512 * (d + 3) * 8 + 64 * 1024
 
 
 def test_context_without_device_is_a_clean_error(Z):

@@ -58,6 +58,18 @@ def test_batch_equals_alone(Z, ctx):
         assert a["summary"] == b["summary"], r
 
 
+def test_batch_with_wide_requests_equals_alone(Z, ctx):
+    """Requests up to 200 dimensions: narrow and wide launch groups together."""
+    reqs = _mix(10, 13, dmax=200, nmin=16, nspan=4.0)
+    print(f"\n[batch] wide mix d {sorted(r['dim'] for r in reqs)}", flush=True)
+    outs = Z.zeus_minimize_batch(ctx, reqs, pso_state=True)
+    for r, (p, b) in enumerate(zip(reqs, outs)):
+        a = Z.zeus_minimize(ctx, p, pso_state=True)
+        for k in KEYS:
+            assert np.array_equal(a[k], b[k], equal_nan=True), (r, k)
+        assert a["summary"] == b["summary"], r
+
+
 def test_batch_fp64_matches_oracle(Z, ctx, oracle_mod):
     reqs = [p for p in _mix(16, 5, dmax=24, nmin=32, nspan=4.0) if p["precision"] == "fp64"]
     outs = Z.zeus_minimize_batch(ctx, reqs, pso_state=True)

@@ -40,6 +40,11 @@ CASES = [
     (dict(W.scaled(W.RASTRIGIN_D10, 4000), grad_tol=1e-4), 0.6),
     (W.problem(name="rosenbrock_d20", objective="rosenbrock", dim=20, n=500, lower=-2.0,
                upper=2.0, iter_pso=3, iter_bfgs=2000, grad_tol=1e-4, seed=8), 0.8),
+    # above 64 dimensions (one block of 256 lanes per start)
+    (W.problem(name="styblinski_d96", objective="styblinski_tang", dim=96, n=200, lower=-5.0,
+               upper=5.0, iter_pso=2, iter_bfgs=500, grad_tol=1e-4, seed=5), 0.6),
+    (W.problem(name="rosenbrock_d72", objective="rosenbrock", dim=72, n=300, lower=-2.0,
+               upper=2.0, iter_pso=2, iter_bfgs=4000, grad_tol=1e-4, seed=9), 0.7),
 ]
 
 

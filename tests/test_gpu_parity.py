@@ -141,6 +141,13 @@ CASES = [
                iter_pso=2, iter_bfgs=200, seed=9), False),
     (W.problem(name="sphere_d64", objective="sphere", dim=64, n=129, lower=-3.0, upper=3.0,
                iter_pso=3, iter_bfgs=50, seed=4), False),
+    # one wavefront per start (33..64 dimensions) for every objective
+    (W.problem(name="ackley_d50", objective="ackley", dim=50, n=96, lower=-5.0, upper=5.0,
+               iter_pso=5, iter_bfgs=600, seed=2), True),
+    (W.problem(name="rastrigin_d40", objective="rastrigin", dim=40, n=80, lower=-5.12,
+               upper=5.12, iter_pso=4, iter_bfgs=500, seed=11), True),
+    (W.problem(name="styblinski_d57", objective="styblinski_tang", dim=57, n=70, lower=-5.0,
+               upper=5.0, iter_pso=3, iter_bfgs=400, seed=13), False),
 ]
 
 
@@ -158,6 +165,43 @@ def test_rosenbrock_d64_max_dim(Z, ctx, oracle_mod):
     g, sw, o = _run_both(Z, ctx, oracle_mod, p)
     _check_pso(g, sw, False)
     _check_bfgs(g, o, p)
+
+
+# Above 64 dimensions a start runs on a block of 256 lanes with its inverse
+# Hessian in device memory: just over the narrow limit, unaligned and aligned
+# sizes, and the largest dimension of the build.
+WIDE_CASES = [
+    W.problem(name="rosenbrock_d65", objective="rosenbrock", dim=65, n=70, lower=-2.0, upper=2.0,
+              iter_pso=2, iter_bfgs=300, seed=12),
+    W.problem(name="rastrigin_d100", objective="rastrigin", dim=100, n=40, lower=-5.12,
+              upper=5.12, iter_pso=3, iter_bfgs=300, seed=1, request_id=3),
+    W.problem(name="styblinski_d128", objective="styblinski_tang", dim=128, n=33, lower=-5.0,
+              upper=5.0, iter_pso=2, iter_bfgs=200, seed=3),
+    W.problem(name="ackley_d200", objective="ackley", dim=200, n=20, lower=-5.0, upper=5.0,
+              iter_pso=2, iter_bfgs=200, seed=2),
+    W.problem(name="sphere_d256", objective="sphere", dim=256, n=9, lower=-3.0, upper=3.0,
+              iter_pso=1, iter_bfgs=30, seed=4),
+]
+
+
+@pytest.mark.parametrize("p", WIDE_CASES, ids=[c["name"] for c in WIDE_CASES])
+def test_parity_wide(Z, ctx, oracle_mod, p):
+    g, sw, o = _run_both(Z, ctx, oracle_mod, p)
+    _check_pso(g, sw)
+    _check_bfgs(g, o, p)
+    _check_summary(g)
+
+
+def test_wide_more_starts_than_slots(Z, ctx, oracle_mod):
+    """2300 starts on at most 2048 resident blocks: the later starts come from
+    the work counter and reuse H slots of finished starts (sampled)."""
+    p = W.problem(name="rosenbrock_d70_n2300", objective="rosenbrock", dim=70, n=2300, lower=-2.0,
+                  upper=2.0, iter_pso=1, iter_bfgs=60, seed=21)
+    idx = np.concatenate([np.arange(0, 40), np.arange(2048, 2300, 7)])
+    g, sw, o = _run_both(Z, ctx, oracle_mod, p, idx=idx)
+    _check_pso(g, sw)
+    _check_bfgs(g, o, p, idx=idx)
+    _check_summary(g)
 
 
 def test_single_start_and_dim_one(Z, ctx, oracle_mod):
@@ -228,7 +272,7 @@ def test_async_matches_blocking(Z, ctx):
 
 
 def test_errors_through_the_abi(Z, ctx):
-    bad = Z.make_problem(W.problem(objective="rastrigin", dim=65, n=10, lower=-1.0, upper=1.0))
+    bad = Z.make_problem(W.problem(objective="rastrigin", dim=257, n=10, lower=-1.0, upper=1.0))
     with pytest.raises(Z.ZeusError) as e:
         Z.zeus_minimize(ctx, bad)
     assert e.value.code == Z.EUNSUPPORTED
