@@ -200,6 +200,65 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem,
                              void *workspace, size_t workspace_bytes,
                              const zeus_result *out, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: a request loop with continuous batching.                        */
+/*                                                                          */
+/* The paper solves one problem per call (Alg. 7).  A server keeps a queue  */
+/* of such problems from any number of callers and runs them as batches    */
+/* (see zeus_minimize_batch) while further requests arrive:                 */
+/*  - zeus_server_create allocates the server's whole device-memory budget  */
+/*    once and starts one worker thread;                                    */
+/*  - requests wait in arrival order; whenever fewer than four batches are  */
+/*    running, the worker forms a new batch from the longest prefix of the  */
+/*    queue whose device footprint (results, swarm state, tables, H slots)  */
+/*    fits in the largest free piece of the budget, and launches it on its  */
+/*    own stream;                                                           */
+/*  - when a batch finishes, its results are in the callers' host arrays,   */
+/*    its memory returns to the budget and its tickets complete.            */
+/* Inside a batch every start retires on its own (the BFGS kernels take the */
+/* next start when one converges).  A request's results are bit-identical  */
+/* to solving it alone with zeus_minimize.                                  */
+/* All server calls are thread-safe.                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct zeus_server zeus_server;
+
+/* Host steady-clock times (nanoseconds, arbitrary origin) of one request. */
+typedef struct zeus_request_times {
+  uint64_t t_submit_ns;  /* zeus_server_submit accepted it                  */
+  uint64_t t_admit_ns;   /* its batch was launched                          */
+  uint64_t t_done_ns;    /* its results were in the host arrays             */
+} zeus_request_times;
+
+/* Creates a server on the device of ctx with hbm_budget_bytes of device
+ * memory (>= 1 MiB).  The context must outlive the server. */
+zeus_err zeus_server_create(zeus_context *ctx, size_t hbm_budget_bytes, zeus_server **out);
+
+/* Queues one problem.  host_out is as for zeus_minimize (host memory) and,
+ * with the problem it points to, must stay valid until the ticket has been
+ * waited for (the problem is copied at submission).  *ticket identifies the
+ * request.  ZEUS_EINVAL / ZEUS_EUNSUPPORTED as zeus_validate; ZEUS_ENOMEM if
+ * the request alone needs more device memory than the budget;
+ * ZEUS_ECANCELLED once the server is being destroyed. */
+zeus_err zeus_server_submit(zeus_server *srv, const zeus_problem *problem,
+                            const zeus_result *host_out, uint64_t *ticket);
+
+/* Waits for a ticket: timeout_ns < 0 waits without limit, 0 only polls.
+ * Returns ZEUS_OK (results written; times filled if not NULL),
+ * ZEUS_NOT_READY (poll, still queued or running), ZEUS_ETIMEOUT,
+ * ZEUS_ECANCELLED (cancelled before it ran), or the error that stopped its
+ * batch.  Every outcome but NOT_READY / ETIMEOUT releases the ticket;
+ * waiting on a released or unknown ticket is ZEUS_EINVAL. */
+zeus_err zeus_server_wait(zeus_server *srv, uint64_t ticket, int64_t timeout_ns,
+                          zeus_request_times *times);
+
+/* Cancels a queued request (its wait then returns ZEUS_ECANCELLED).  A
+ * request already launched cannot be stopped: ZEUS_NOT_READY, wait for it. */
+zeus_err zeus_server_cancel(zeus_server *srv, uint64_t ticket);
+
+/* Cancels every queued request, waits for the running batches, stops the
+ * worker and frees the budget. */
+zeus_err zeus_server_destroy(zeus_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,8 +10,14 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <map>
 #include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <new>
 #include <string>
 #include <vector>
@@ -297,7 +303,7 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
                                 sizeof(zeus::ReqDev) * host.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "request table upload");
   zeus_context::Pending pend{};
-  const bool prof = ctx->profiling;
+  const bool prof = ctx && ctx->profiling;
   if (prof)
     for (auto &ev : pend.ev)
       if (hipEventCreate(&ev) != hipSuccess) return fail(ZEUS_EHIP, "hipEventCreate failed");
@@ -421,7 +427,244 @@ GroupKey key_of(const zeus_problem &p) {
   return GroupKey{p.objective, p.precision, zeus::pso_group_lanes(p.dim), zeus::group_lanes(p.dim)};
 }
 
+// Device memory plan of a batch: result arrays of every request, then the
+// swarm workspaces, then per launch group its header, request table and H
+// slots.  Offsets are relative to two bases (results, workspace).
+struct BatchPlan {
+  std::map<GroupKey, std::vector<int32_t>> groups;
+  std::vector<GroupKey> order;  // groups in the order of their first request
+  std::vector<ResLayout> rl;
+  std::vector<size_t> res_off, ws_off, tab_off, h_off;
+  size_t res_total = 0, ws_total = 0;
+};
+
+BatchPlan plan_batch(const zeus_problem *problems, const zeus_result *outs, int32_t n) {
+  BatchPlan b;
+  for (int32_t r = 0; r < n; ++r) {
+    const GroupKey k = key_of(problems[r]);
+    auto it = b.groups.find(k);
+    if (it == b.groups.end()) b.order.push_back(k);
+    b.groups[k].push_back(r);
+  }
+  b.rl.resize(n);
+  b.res_off.resize(n);
+  b.ws_off.resize(n);
+  for (int32_t r = 0; r < n; ++r) {
+    b.rl[r] = res_layout(problems[r], outs[r]);
+    b.res_off[r] = b.res_total;
+    b.res_total += b.rl[r].total;
+    b.ws_off[r] = b.ws_total;
+    b.ws_total += zeus::workspace_bytes(problems[r].n_starts, problems[r].dim);
+  }
+  b.tab_off.resize(b.order.size());
+  b.h_off.resize(b.order.size());
+  for (size_t gi = 0; gi < b.order.size(); ++gi) {
+    const std::vector<int32_t> &members = b.groups[b.order[gi]];
+    b.tab_off[gi] = b.ws_total;
+    b.ws_total += kHdrBytes + table_bytes((int)members.size());
+    int64_t starts = 0;
+    int dmax = 0;
+    for (int32_t r : members) {
+      starts += problems[r].n_starts;
+      dmax = problems[r].dim > dmax ? problems[r].dim : dmax;
+    }
+    const size_t hb = hslot_bytes(b.order[gi].g_bfgs, starts, dmax);
+    b.h_off[gi] = hb ? b.ws_total : SIZE_MAX;
+    b.ws_total += hb;
+  }
+  return b;
+}
+
+// Enqueues every launch group of a planned batch (group gi on
+// streams[gi % streams.size()]) followed by the copies of its results into
+// the host arrays of outs.
+zeus_err enqueue_batch(zeus_context *ctx, const BatchPlan &b, const zeus_problem *problems,
+                       const zeus_result *outs, void *res_base, void *ws_base,
+                       const std::vector<hipStream_t> &streams) {
+  char *R = static_cast<char *>(res_base), *Wb = static_cast<char *>(ws_base);
+  zeus_err e;
+  for (size_t gi = 0; gi < b.order.size(); ++gi) {
+    hipStream_t s = streams[gi % streams.size()];
+    const std::vector<int32_t> &members = b.groups.at(b.order[gi]);
+    std::vector<Planned> plan(members.size());
+    for (size_t k = 0; k < members.size(); ++k) {
+      const int32_t r = members[k];
+      plan[k].pb = &problems[r];
+      plan[k].dev = carve_result(R + b.res_off[r], b.rl[r], outs[r]);
+      plan[k].ws = zeus::carve_workspace(Wb + b.ws_off[r], problems[r].n_starts, problems[r].dim);
+    }
+    void *hs = b.h_off[gi] == SIZE_MAX ? nullptr : Wb + b.h_off[gi];
+    if ((e = enqueue_group(ctx, plan, Wb + b.tab_off[gi], hs, s)) != ZEUS_OK) return e;
+    for (size_t k = 0; k < members.size(); ++k)
+      if ((e = copy_back(problems[members[k]], outs[members[k]], plan[k].dev, s)) != ZEUS_OK)
+        return e;
+  }
+  return ZEUS_OK;
+}
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// First-fit allocator over [0, size) of one device allocation.
+class Pool {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t *off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t largest() const {
+    size_t m = 0;
+    for (auto &kv : free_) m = kv.second > m ? kv.second : m;
+    return m;
+  }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> size
+};
+
+enum TicketState { kQueued, kRunning, kDone, kCancelled, kFailed };
+
+struct Ticket {
+  zeus_problem pb;
+  zeus_result out;
+  size_t bytes = 0;  // footprint of the request alone
+  TicketState state = kQueued;
+  zeus_err err = ZEUS_OK;
+  std::string msg;
+  zeus_request_times times{};
+};
+
+size_t footprint(const BatchPlan &b) { return align_up(b.res_total) + align_up(b.ws_total); }
+
 }  // namespace
+
+constexpr int kServerSlots = 4;       // batches in flight, one worker thread each
+constexpr int kServerMaxBatch = 512;  // requests per batch
+
+struct zeus_server {
+  zeus_context *ctx = nullptr;
+  int device = 0;
+  void *mem = nullptr;
+  size_t budget = 0;
+  Pool pool;
+  hipStream_t streams[kServerSlots] = {};
+  std::mutex mu;
+  std::condition_variable cv;        // workers: new requests or freed memory
+  std::condition_variable done_cv;   // waiters: a ticket changed state
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, Ticket> tickets;
+  uint64_t next_id = 1;
+  bool stopping = false;
+  std::vector<std::thread> workers;
+
+  // Takes the longest prefix of the queue whose batch fits in the largest
+  // free piece of the budget (lock held).  Returns false if the queue is
+  // empty or its head does not fit now.
+  bool take_batch(std::vector<uint64_t> &ids, std::vector<zeus_problem> &pbs,
+                  std::vector<zeus_result> &outs, BatchPlan &plan, size_t &off, size_t &need) {
+    const size_t room = pool.largest();
+    ids.clear();
+    pbs.clear();
+    outs.clear();
+    need = 0;
+    for (uint64_t id : queue) {
+      if ((int)ids.size() == kServerMaxBatch) break;
+      const Ticket &t = tickets.at(id);
+      pbs.push_back(t.pb);
+      outs.push_back(t.out);
+      BatchPlan trial = plan_batch(pbs.data(), outs.data(), (int32_t)pbs.size());
+      const size_t f = footprint(trial);
+      if (f > room) {
+        pbs.pop_back();
+        outs.pop_back();
+        break;
+      }
+      ids.push_back(id);
+      plan = std::move(trial);
+      need = f;
+    }
+    if (ids.empty()) return false;
+    for (size_t k = 0; k < ids.size(); ++k) queue.pop_front();
+    (void)pool.alloc(need, &off);
+    const uint64_t t0 = now_ns();
+    for (uint64_t id : ids) {
+      Ticket &t = tickets.at(id);
+      t.state = kRunning;
+      t.times.t_admit_ns = t0;
+    }
+    return true;
+  }
+
+  void work(int slot) {
+    (void)hipSetDevice(device);
+    std::vector<uint64_t> ids;
+    std::vector<zeus_problem> pbs;
+    std::vector<zeus_result> outs;
+    BatchPlan plan;
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      if (stopping && queue.empty()) break;
+      size_t off = 0, need = 0;
+      if (!take_batch(ids, pbs, outs, plan, off, need)) {
+        cv.wait(lk);
+        continue;
+      }
+      lk.unlock();
+      // enqueue the batch and its copies into the callers' arrays, then wait
+      char *base = static_cast<char *>(mem) + off;
+      std::vector<hipStream_t> st{streams[slot]};
+      zeus_err e = enqueue_batch(nullptr, plan, pbs.data(), outs.data(), base,
+                                 base + align_up(plan.res_total), st);
+      std::string msg = e != ZEUS_OK ? g_last_error : std::string();
+      hipError_t he = hipStreamSynchronize(streams[slot]);
+      if (e == ZEUS_OK && he != hipSuccess) {
+        e = ZEUS_EHIP;
+        msg = std::string("hipStreamSynchronize: ") + hipGetErrorString(he);
+      }
+      const uint64_t t1 = now_ns();
+      lk.lock();
+      for (uint64_t id : ids) {
+        Ticket &t = tickets.at(id);
+        t.state = e == ZEUS_OK ? kDone : kFailed;
+        t.err = e;
+        t.msg = msg;
+        t.times.t_done_ns = t1;
+      }
+      pool.release(off, need);
+      done_cv.notify_all();
+      cv.notify_all();  // freed memory may let a waiting head in
+    }
+  }
+};
 
 extern "C" {
 
@@ -558,84 +801,172 @@ zeus_err zeus_minimize_batch(zeus_context *ctx, const zeus_problem *problems, in
     if (e == ZEUS_OK) e = check_result(&outs[r], &problems[r]);
     if (e != ZEUS_OK) return fail(e, "request " + std::to_string(r) + ": " + g_last_error);
   }
-  // groups, in the order of their first request
-  std::map<GroupKey, std::vector<int32_t>> groups;
-  std::vector<GroupKey> order;
-  for (int32_t r = 0; r < n; ++r) {
-    const GroupKey k = key_of(problems[r]);
-    auto it = groups.find(k);
-    if (it == groups.end()) {
-      order.push_back(k);
-      groups[k].push_back(r);
-    } else {
-      it->second.push_back(r);
-    }
-  }
-  // one allocation for results, one for workspaces and tables
-  std::vector<ResLayout> rl(n);
-  std::vector<size_t> res_off(n), ws_off(n);
-  size_t res_total = 0, ws_total = 0;
-  for (int32_t r = 0; r < n; ++r) {
-    rl[r] = res_layout(problems[r], outs[r]);
-    res_off[r] = res_total;
-    res_total += rl[r].total;
-    ws_off[r] = ws_total;
-    ws_total += zeus::workspace_bytes(problems[r].n_starts, problems[r].dim);
-  }
-  std::vector<size_t> tab_off(order.size()), h_off(order.size());
-  for (size_t gi = 0; gi < order.size(); ++gi) {
-    const std::vector<int32_t> &members = groups[order[gi]];
-    tab_off[gi] = ws_total;
-    ws_total += kHdrBytes + table_bytes((int)members.size());
-    int64_t starts = 0;
-    int dmax = 0;
-    for (int32_t r : members) {
-      starts += problems[r].n_starts;
-      dmax = problems[r].dim > dmax ? problems[r].dim : dmax;
-    }
-    const size_t hb = hslot_bytes(order[gi].g_bfgs, starts, dmax);
-    h_off[gi] = hb ? ws_total : SIZE_MAX;
-    ws_total += hb;
-  }
+  const BatchPlan plan = plan_batch(problems, outs, n);
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   std::lock_guard<std::mutex> lk(ctx->mu);
   zeus_err e;
-  if ((e = ensure(&ctx->ws, &ctx->ws_cap, ws_total)) != ZEUS_OK) return e;
-  if ((e = ensure(&ctx->res, &ctx->res_cap, res_total)) != ZEUS_OK) return e;
+  if ((e = ensure(&ctx->ws, &ctx->ws_cap, plan.ws_total)) != ZEUS_OK) return e;
+  if ((e = ensure(&ctx->res, &ctx->res_cap, plan.res_total)) != ZEUS_OK) return e;
   // independent groups run on separate streams so that their kernels overlap
-  const size_t want_streams = order.size() < 4 ? order.size() : 4;
+  const size_t want_streams = plan.order.size() < 4 ? plan.order.size() : 4;
   while (ctx->aux.size() + 1 < want_streams) {
     hipStream_t s;
     hipError_t he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (he != hipSuccess) return hip_fail(he, "hipStreamCreate");
     ctx->aux.push_back(s);
   }
-  std::vector<zeus_result> dev(n);
-  for (int32_t r = 0; r < n; ++r)
-    dev[r] = carve_result(static_cast<char *>(ctx->res) + res_off[r], rl[r], outs[r]);
-  for (size_t gi = 0; gi < order.size(); ++gi) {
-    hipStream_t s = gi % want_streams == 0 ? ctx->stream : ctx->aux[gi % want_streams - 1];
-    const std::vector<int32_t> &members = groups[order[gi]];
-    std::vector<Planned> plan(members.size());
-    for (size_t k = 0; k < members.size(); ++k) {
-      const int32_t r = members[k];
-      plan[k].pb = &problems[r];
-      plan[k].dev = dev[r];
-      plan[k].ws = zeus::carve_workspace(static_cast<char *>(ctx->ws) + ws_off[r],
-                                         problems[r].n_starts, problems[r].dim);
-    }
-    void *hs = h_off[gi] == SIZE_MAX ? nullptr : static_cast<char *>(ctx->ws) + h_off[gi];
-    if ((e = enqueue_group(ctx, plan, static_cast<char *>(ctx->ws) + tab_off[gi], hs, s)) != ZEUS_OK)
-      return e;
-    for (int32_t r : members)
-      if ((e = copy_back(problems[r], outs[r], dev[r], s)) != ZEUS_OK) return e;
-  }
+  std::vector<hipStream_t> streams{ctx->stream};
+  for (size_t k = 0; k + 1 < want_streams; ++k) streams.push_back(ctx->aux[k]);
+  if ((e = enqueue_batch(ctx, plan, problems, outs, ctx->res, ctx->ws, streams)) != ZEUS_OK)
+    return e;
   hipError_t he;
-  if ((he = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
-  for (size_t k = 0; k + 1 < want_streams; ++k)
-    if ((he = hipStreamSynchronize(ctx->aux[k])) != hipSuccess)
-      return hip_fail(he, "hipStreamSynchronize");
+  for (hipStream_t st : streams)
+    if ((he = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
+  return ZEUS_OK;
+}
+
+
+zeus_err zeus_server_create(zeus_context *ctx, size_t hbm_budget_bytes, zeus_server **out) {
+  g_last_error.clear();
+  if (!ctx || !out) return fail(ZEUS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (hbm_budget_bytes < ((size_t)1 << 20)) return fail(ZEUS_EINVAL, "budget below 1 MiB");
+  auto *srv = new (std::nothrow) zeus_server;
+  if (!srv) return fail(ZEUS_ENOMEM, "server allocation failed");
+  srv->ctx = ctx;
+  srv->device = ctx->device;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) {
+    delete srv;
+    return hip_fail(g.err, "hipSetDevice");
+  }
+  srv->budget = hbm_budget_bytes / kAlign * kAlign;
+  hipError_t e = hipMalloc(&srv->mem, srv->budget);
+  if (e != hipSuccess) {
+    delete srv;
+    return fail(ZEUS_ENOMEM, std::string("hipMalloc of the budget: ") + hipGetErrorString(e));
+  }
+  srv->pool.reset(srv->budget);
+  for (auto &st : srv->streams) {
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) {
+      for (auto &s2 : srv->streams)
+        if (s2) (void)hipStreamDestroy(s2);
+      (void)hipFree(srv->mem);
+      delete srv;
+      return hip_fail(e, "hipStreamCreate");
+    }
+  }
+  for (int k = 0; k < kServerSlots; ++k) srv->workers.emplace_back([srv, k] { srv->work(k); });
+  *out = srv;
+  return ZEUS_OK;
+}
+
+zeus_err zeus_server_submit(zeus_server *srv, const zeus_problem *problem,
+                            const zeus_result *host_out, uint64_t *ticket) {
+  g_last_error.clear();
+  if (!srv || !ticket) return fail(ZEUS_EINVAL, "NULL argument");
+  zeus_err e = check_problem(problem);
+  if (e == ZEUS_OK) e = check_result(host_out, problem);
+  if (e != ZEUS_OK) return e;
+  Ticket t;
+  t.pb = *problem;
+  t.out = *host_out;
+  if (!t.out.trace || t.out.trace_len == 0) {
+    t.out.trace = nullptr;
+    t.out.trace_len = 0;
+  }
+  t.bytes = footprint(plan_batch(&t.pb, &t.out, 1));
+  if (t.bytes > srv->budget)
+    return fail(ZEUS_ENOMEM, "request needs " + std::to_string(t.bytes) +
+                                 " bytes of device memory, more than the server's budget");
+  t.times.t_submit_ns = now_ns();
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->stopping) return fail(ZEUS_ECANCELLED, "server is shutting down");
+  const uint64_t id = srv->next_id++;
+  srv->tickets.emplace(id, t);
+  srv->queue.push_back(id);
+  *ticket = id;
+  srv->cv.notify_one();
+  return ZEUS_OK;
+}
+
+zeus_err zeus_server_wait(zeus_server *srv, uint64_t ticket, int64_t timeout_ns,
+                          zeus_request_times *times) {
+  g_last_error.clear();
+  if (!srv) return fail(ZEUS_EINVAL, "srv is NULL");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns > 0 ? timeout_ns : 0);
+  for (;;) {
+    auto it = srv->tickets.find(ticket);
+    if (it == srv->tickets.end()) return fail(ZEUS_EINVAL, "unknown or released ticket");
+    Ticket &t = it->second;
+    if (t.state == kDone || t.state == kCancelled || t.state == kFailed) {
+      if (times) *times = t.times;
+      const TicketState st = t.state;
+      const zeus_err err = t.err;
+      const std::string msg = t.msg;
+      srv->tickets.erase(it);
+      if (st == kDone) return ZEUS_OK;
+      if (st == kCancelled) return fail(ZEUS_ECANCELLED, "request was cancelled");
+      return fail(err, msg);
+    }
+    if (timeout_ns == 0) return ZEUS_NOT_READY;
+    if (timeout_ns < 0) {
+      srv->done_cv.wait(lk);
+    } else if (srv->done_cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+      auto again = srv->tickets.find(ticket);
+      if (again != srv->tickets.end() && (again->second.state == kQueued || again->second.state == kRunning))
+        return fail(ZEUS_ETIMEOUT, "timed out");
+    }
+  }
+}
+
+zeus_err zeus_server_cancel(zeus_server *srv, uint64_t ticket) {
+  g_last_error.clear();
+  if (!srv) return fail(ZEUS_EINVAL, "srv is NULL");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->tickets.find(ticket);
+  if (it == srv->tickets.end()) return fail(ZEUS_EINVAL, "unknown or released ticket");
+  if (it->second.state != kQueued) {
+    if (it->second.state == kRunning) {
+      g_last_error = "request is running; wait for it";
+      return ZEUS_NOT_READY;
+    }
+    return ZEUS_OK;  // already finished
+  }
+  for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q)
+    if (*q == ticket) {
+      srv->queue.erase(q);
+      break;
+    }
+  it->second.state = kCancelled;
+  srv->done_cv.notify_all();
+  srv->cv.notify_one();
+  return ZEUS_OK;
+}
+
+zeus_err zeus_server_destroy(zeus_server *srv) {
+  g_last_error.clear();
+  if (!srv) return ZEUS_OK;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stopping = true;
+    for (uint64_t id : srv->queue) srv->tickets.at(id).state = kCancelled;
+    srv->queue.clear();
+    srv->cv.notify_all();
+    srv->done_cv.notify_all();
+  }
+  for (auto &w : srv->workers) w.join();
+  {
+    DeviceGuard g(srv->device);
+    for (auto &st : srv->streams) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+    (void)hipFree(srv->mem);
+  }
+  delete srv;
   return ZEUS_OK;
 }
 

@@ -27,7 +27,8 @@ ST_MAXITER, ST_CONVERGED, ST_STOPPED, ST_NONFINITE = 0, 1, 2, 3
 EXPORTS = ("zeus_abi_version", "zeus_version", "zeus_last_error", "zeus_validate",
            "zeus_workspace_bytes", "zeus_context_create", "zeus_context_destroy",
            "zeus_context_set_profiling", "zeus_context_get_profile", "zeus_minimize",
-           "zeus_minimize_batch", "zeus_minimize_async")
+           "zeus_minimize_batch", "zeus_minimize_async", "zeus_server_create",
+           "zeus_server_submit", "zeus_server_wait", "zeus_server_cancel", "zeus_server_destroy")
 
 
 class zeus_problem(C.Structure):
@@ -62,6 +63,10 @@ class zeus_profile(C.Structure):
                 ("reduce_launches", C.c_int64)]
 
 
+class zeus_request_times(C.Structure):
+    _fields_ = [("t_submit_ns", C.c_uint64), ("t_admit_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
+
+
 class ZeusError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"zeus error {code}: {msg}")
@@ -91,6 +96,11 @@ def _load():
     L.zeus_minimize_batch.argtypes = [C.c_void_p, P(zeus_problem), C.c_int32, P(zeus_result)]
     L.zeus_minimize_async.argtypes = [C.c_void_p, P(zeus_problem), C.c_void_p, C.c_size_t,
                                       P(zeus_result), C.c_void_p]
+    L.zeus_server_create.argtypes = [C.c_void_p, C.c_size_t, P(C.c_void_p)]
+    L.zeus_server_submit.argtypes = [C.c_void_p, P(zeus_problem), P(zeus_result), P(C.c_uint64)]
+    L.zeus_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, P(zeus_request_times)]
+    L.zeus_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
+    L.zeus_server_destroy.argtypes = [C.c_void_p]
     for name in EXPORTS:
         if name not in ("zeus_abi_version", "zeus_version", "zeus_last_error"):
             getattr(L, name).restype = C.c_int
@@ -227,6 +237,60 @@ def zeus_minimize_async(ctx, problem, workspace_ptr: int, workspace_bytes: int,
     _check(lib.zeus_minimize_async(ctx, C.byref(pb), C.c_void_p(workspace_ptr),
                                    C.c_size_t(workspace_bytes), C.byref(result),
                                    C.c_void_p(stream_ptr) if stream_ptr else None))
+
+
+class Server:
+    """A zeus_server: submit problems from any thread, wait for their results.
+
+    The host arrays of each submitted request are kept here until it is waited
+    for."""
+
+    def __init__(self, ctx, budget_bytes: int):
+        self.h = C.c_void_p()
+        _check(lib.zeus_server_create(ctx, C.c_size_t(int(budget_bytes)), C.byref(self.h)))
+        self._live = {}
+
+    def submit(self, problem, *, trace_len=0, pso_state=False, ls_trials=True) -> int:
+        pb = problem if isinstance(problem, zeus_problem) else make_problem(problem)
+        o, s, r = _host_outputs(pb, trace_len, pso_state, ls_trials)
+        t = C.c_uint64()
+        _check(lib.zeus_server_submit(self.h, C.byref(pb), C.byref(r), C.byref(t)))
+        self._live[t.value] = (pb, o, s, r)
+        return t.value
+
+    def wait(self, ticket: int, timeout_s=None):
+        """Results of a ticket (host arrays, summary and times in ns), or None
+        when a poll (timeout_s == 0) finds it unfinished."""
+        tm = zeus_request_times()
+        ns = -1 if timeout_s is None else int(timeout_s * 1e9)
+        code = lib.zeus_server_wait(self.h, C.c_uint64(ticket), C.c_int64(ns), C.byref(tm))
+        if code == NOT_READY:
+            return None
+        if code != OK:
+            self._live.pop(ticket, None)
+        _check(code)
+        _, o, s, _ = self._live.pop(ticket)
+        o["summary"] = _summary_dict(s)
+        o["times"] = {k: getattr(tm, k) for k, _ in zeus_request_times._fields_}
+        return o
+
+    def cancel(self, ticket: int) -> int:
+        code = lib.zeus_server_cancel(self.h, C.c_uint64(ticket))
+        if code not in (OK, NOT_READY):
+            _check(code)
+        return code
+
+    def close(self):
+        if self.h:
+            _check(lib.zeus_server_destroy(self.h))
+            self.h = C.c_void_p()
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class DeviceSolve:
