@@ -114,12 +114,142 @@ def cpu_baseline(p):
             "converged_starts_per_s": float(np.mean(r["status"] == 1)) / per_start}
 
 
+MULTI = ("uneven_batch", "served_mix")
+
+
+def _totals(outs, reqs):
+    iters = sum(o["summary"]["total_iters"] for o in outs)
+    conv = sum(o["summary"]["n_converged"] for o in outs)
+    starts = sum(int(p["n"]) for p in reqs)
+    succ = sum(int(np.sum(o["f"] - W.f_star(p["objective"], p["dim"]) < 1e-4))
+               for o, p in zip(outs, reqs))
+    return iters, conv, starts, succ / max(1, starts)
+
+
+def _mix_config(name, reqs, scale):
+    dims = [int(p["dim"]) for p in reqs]
+    return {"workload": name, "requests": len(reqs), "starts": sum(int(p["n"]) for p in reqs),
+            "dim_range": [min(dims), max(dims)], "n_scale": scale,
+            "iter_bfgs": int(reqs[0]["iter_bfgs"])}
+
+
+def run_uneven_batch(args, Z, ctx):
+    """The uneven batch (512 requests, d in [2,128], N log-uniform in
+    [256, 16384]) through one zeus_minimize_batch call, FP64 and mixed.  The
+    timed region includes copying every result to host memory."""
+    scale = args.n_scale if args.n_scale else 1.0
+    reqs = [W.scaled(p, max(1, int(p["n"] * scale))) for p in W.uneven_batch()]
+    Z.zeus_minimize_batch(ctx, reqs[:8])  # warm-up: first launches load the code objects
+    t0 = time.perf_counter()
+    outs = Z.zeus_minimize_batch(ctx, reqs)
+    t = time.perf_counter() - t0
+    print(f"[batch] fp64: {t:.2f} s", file=sys.stderr, flush=True)
+    iters, conv, starts, succ = _totals(outs, reqs)
+    mreqs = [dict(p, precision="mixed", grad_tol=1e-4) for p in reqs]
+    t0 = time.perf_counter()
+    mouts = Z.zeus_minimize_batch(ctx, mreqs)
+    tm = time.perf_counter() - t0
+    miters, mconv, _, msucc = _totals(mouts, mreqs)
+    return {
+        "metric": METRIC, "value": iters / t, "unit": "start-iters/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded Philox request stream)",
+        "config": _mix_config("uneven_batch", reqs, scale),
+        "converged_starts_per_s": conv / t, "start_iters": iters, "success_rate": succ,
+        "mixed": {"grad_tol": 1e-4, "ms": tm * 1e3, "start_iters_per_s": miters / tm,
+                  "converged_starts_per_s": mconv / tm, "success_rate": msucc,
+                  "speedup_vs_fp64": t / tm},
+        "roofline": None, "note": "multi-request workload; the roofline is reported on the "
+                                  "single-problem default workload"}
+
+
+def run_served_mix(args, Z, ctx):
+    """The served mix (d in [2,200], N log-uniform; mixed precision, Theta 1e-4)
+    at reduced size: plain FP64 one request at a time, then the server closed
+    loop (all submitted at once: saturation rate mu), then Poisson arrivals at
+    0.5, 0.7 and 0.9 mu with per-request latency t_done - t_submit."""
+    import torch
+    count = args.requests or 256
+    scale = args.n_scale if args.n_scale else 1.0 / 16
+    base = W.served_mix(count)
+    reqs = [W.scaled(p, max(1, int(p["n"] * scale))) for p in base]
+    fp64 = [dict(p, precision="fp64") for p in reqs]
+    Z.zeus_minimize(ctx, fp64[0])  # warm-up
+    t0 = time.perf_counter()
+    souts = [Z.zeus_minimize(ctx, p) for p in fp64]
+    t_seq = time.perf_counter() - t0
+    print(f"[served] fp64 one at a time: {t_seq:.2f} s", file=sys.stderr, flush=True)
+    s_iters, s_conv, starts, s_succ = _totals(souts, fp64)
+    free, _ = torch.cuda.mem_get_info()
+    budget = max(1 << 30, free - (8 << 30))
+    with Z.Server(ctx, budget) as srv:
+        t0 = time.perf_counter()
+        ts = [srv.submit(p) for p in reqs]
+        outs = [srv.wait(t) for t in ts]
+        t_closed = time.perf_counter() - t0
+        iters, conv, _, succ = _totals(outs, reqs)
+        mu = count / t_closed
+        print(f"[served] closed loop: {t_closed:.2f} s ({mu:.1f} req/s)", file=sys.stderr, flush=True)
+        rng = np.random.Generator(np.random.Philox(key=[4, int.from_bytes(b"ARR", "little")]))
+        open_loop = {}
+        for frac in (0.5, 0.7, 0.9):
+            lam = frac * mu
+            arrive = np.cumsum(rng.exponential(1.0 / lam, count))
+            tickets = [None] * count
+
+            def feeder():
+                start = time.perf_counter()
+                for k in range(count):
+                    delay = start + arrive[k] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                    tickets[k] = srv.submit(reqs[k])
+
+            import threading
+            th = threading.Thread(target=feeder)
+            t0 = time.perf_counter()
+            th.start()
+            res = []
+            for k in range(count):
+                while tickets[k] is None:
+                    time.sleep(1e-4)
+                res.append(srv.wait(tickets[k]))
+            th.join()
+            span = time.perf_counter() - t0
+            print(f"[served] open loop at {frac} mu: {span:.2f} s", file=sys.stderr, flush=True)
+            lat = np.array([(o["times"]["t_done_ns"] - o["times"]["t_submit_ns"]) / 1e6 for o in res])
+            oi, oc, _, osc = _totals(res, reqs)
+            open_loop[f"{frac:.1f}"] = {
+                "rate_req_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "start_iters_per_s": oi / span,
+                "converged_starts_per_s": oc / span, "success_rate": osc}
+    main_ol = open_loop["0.7"]
+    return {
+        "metric": METRIC, "value": iters / t_closed, "unit": "start-iters/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": t_closed * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (mixed)",
+        "data": "synthetic (seeded Philox request stream, Poisson arrivals)",
+        "config": _mix_config("served_mix", reqs, scale),
+        "converged_starts_per_s": conv / t_closed, "success_rate": succ,
+        "saturation_req_per_s": mu, "p50_solve_ms": main_ol["p50_ms"],
+        "p99_solve_ms": main_ol["p99_ms"], "open_loop": open_loop,
+        "fp64_one_at_a_time": {"ms": t_seq * 1e3, "start_iters_per_s": s_iters / t_seq,
+                               "converged_starts_per_s": s_conv / t_seq, "success_rate": s_succ},
+        "speedup_vs_fp64_one_at_a_time": t_seq / t_closed,
+        "roofline": None, "note": "multi-request workload; the roofline is reported on the "
+                                  "single-problem default workload"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rastrigin_d10_n65536", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rastrigin_d10_n65536",
+                    choices=sorted(WORKLOADS) + list(MULTI))
+    ap.add_argument("--n-scale", type=float, default=0.0,
+                    help="multi-request workloads: multiply every request's start count")
+    ap.add_argument("--requests", type=int, default=0, help="served_mix: number of requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run of the same workload")
@@ -144,6 +274,14 @@ def main():
 
     import torch
     from paper_2603_28770_amd import zeus as Z
+
+    if args.workload in MULTI:
+        ctx = Z.zeus_context_create(0)
+        run = run_uneven_batch if args.workload == "uneven_batch" else run_served_mix
+        line = run(args, Z, ctx)
+        Z.zeus_context_destroy(ctx)
+        print(json.dumps(line), flush=True)
+        return
 
     p = WORKLOADS[args.workload]
     ctx = Z.zeus_context_create(0)
