@@ -38,7 +38,9 @@ METRIC = "converged starts/s & start-iters/s vs plain FP64; p50/p99 solve latenc
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 
 WORKLOADS = {"rastrigin_d10_n65536": W.RASTRIGIN_D10, "rosenbrock_d2_n1024": W.ROSENBROCK_D2,
-             "ackley_d50_n131072": W.ACKLEY_D50, "rosenbrock_d50_n131072": W.ROSENBROCK_D50}
+             "ackley_d50_n131072": W.ACKLEY_D50, "rosenbrock_d50_n131072": W.ROSENBROCK_D50,
+             "styblinski_d128_n16384": W.STYBLINSKI_D128,
+             "rosenbrock_d128_n16384": W.ROSENBROCK_D128}
 
 
 # Per-evaluation flop counts of the objectives as the kernels evaluate them

@@ -305,17 +305,32 @@ __global__ __launch_bounds__(kSumBlock) void summary_kernel(const ReqDev *reqs) 
   double key = __builtin_huge_val();
   int64_t idx = INT64_MAX;
   int64_t nconv = 0, nnf = 0, it = 0, lt = 0;
-  for (int64_t i = threadIdx.x; i < n; i += kSumBlock) {
-    const double fi = f[i];
-    if (__builtin_isfinite(fi) && key_less(fi, i, key, idx)) {
-      key = fi;
-      idx = i;
+  // U elements per thread per trip, their loads issued together
+  constexpr int U = 8;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kSumBlock * U) {
+    double fv[U];
+    int32_t sv[U], iv[U], lv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * kSumBlock;
+      const bool in = i < n;
+      fv[u] = in ? f[i] : __builtin_huge_val();
+      sv[u] = in ? rq.out_status[i] : -1;
+      iv[u] = in ? rq.out_iters[i] : 0;
+      lv[u] = (in && rq.out_ls) ? rq.out_ls[i] : 0;
     }
-    const int32_t st = rq.out_status[i];
-    nconv += st == ZEUS_ST_CONVERGED;
-    nnf += st == ZEUS_ST_NONFINITE;
-    it += rq.out_iters[i];
-    if (rq.out_ls) lt += rq.out_ls[i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * kSumBlock;
+      if (__builtin_isfinite(fv[u]) && key_less(fv[u], i, key, idx)) {
+        key = fv[u];
+        idx = i;
+      }
+      nconv += sv[u] == ZEUS_ST_CONVERGED;
+      nnf += sv[u] == ZEUS_ST_NONFINITE;
+      it += iv[u];
+      lt += lv[u];
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {

@@ -20,6 +20,9 @@ constexpr int kWideLanes = 256;
 // Most H slots (resident wide blocks) a launch group uses.
 constexpr int kWideMaxSlots = 2048;
 constexpr int kPsoBlock = 256;
+// Threads per swarm block (256 for every particle width: larger blocks lower
+// the number of resident blocks per CU more than they add groups).
+constexpr int pso_threads(int) { return kPsoBlock; }
 constexpr int kBfgsBlock = 256;
 
 // Most blocks a swarm launch gives one request (the blocks stride over its

@@ -41,9 +41,10 @@ __device__ __forceinline__ int find_entry(const ReqDev *reqs, int nreq, int64_t 
 
 // Block-wide minimum of (key, idx) carrying two payloads; the result is left
 // in every thread.
+template <int NT>
 __device__ void block_argmin(double &key, int64_t &idx, double &val, int64_t &aux) {
-  __shared__ double sk[kPsoBlock / 64], sv[kPsoBlock / 64];
-  __shared__ int64_t si[kPsoBlock / 64], sa[kPsoBlock / 64];
+  __shared__ double sk[NT / 64], sv[NT / 64];
+  __shared__ int64_t si[NT / 64], sa[NT / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const double ok = __shfl_xor(key, off, 64);
@@ -69,7 +70,7 @@ __device__ void block_argmin(double &key, int64_t &idx, double &val, int64_t &au
   idx = si[0];
   val = sv[0];
   aux = sa[0];
-  for (int wv = 1; wv < kPsoBlock / 64; ++wv)
+  for (int wv = 1; wv < NT / 64; ++wv)
     if (key_less(sk[wv], si[wv], key, idx)) {
       key = sk[wv];
       idx = si[wv];
@@ -83,12 +84,13 @@ __device__ void block_argmin(double &key, int64_t &idx, double &val, int64_t &au
 // of that sweep and the global best after sweep done-1.  Leaves its position
 // in gx_sh[0..d) for every thread of the block.  When `publish`, the result is
 // also stored for later launches (and in final_best / final_gx if given).
+template <int NT>
 __device__ void global_best_after(const ReqDev &a, int done, double *gx_sh, bool publish,
                                   PsoBest *final_best, double *final_gx) {
   const int P = a.ws.pso_blocks, d = a.d, slot = done & 1;
   double key = __builtin_huge_val(), val = __builtin_nan("");
   int64_t idx = INT64_MAX, blk = 0;
-  for (int b = threadIdx.x; b < P; b += kPsoBlock) {
+  for (int b = threadIdx.x; b < P; b += NT) {
     const double kb = a.ws.part_key[slot * P + b];
     const int64_t ib = a.ws.part_idx[slot * P + b];
     if (key_less(kb, ib, key, idx)) {
@@ -98,14 +100,14 @@ __device__ void global_best_after(const ReqDev &a, int done, double *gx_sh, bool
       blk = b;
     }
   }
-  block_argmin(key, idx, val, blk);
+  block_argmin<NT>(key, idx, val, blk);
   bool take = true;
   PsoBest prev{0.0, 0};
   if (done > 0) {
     prev = a.ws.best_store[(done - 1) & 1];
     take = rank_key(val) < rank_key(prev.f);  // strict improvement
   }
-  for (int j = threadIdx.x; j < d; j += kPsoBlock)
+  for (int j = threadIdx.x; j < d; j += NT)
     gx_sh[j] = take ? a.ws.part_x[((size_t)slot * P + blk) * d + j]
                     : a.ws.gx_store[((done - 1) & 1) * d + j];
   __syncthreads();
@@ -115,7 +117,7 @@ __device__ void global_best_after(const ReqDev &a, int done, double *gx_sh, bool
       a.ws.best_store[slot] = nb;
       if (final_best) *final_best = nb;
     }
-    for (int j = threadIdx.x; j < d; j += kPsoBlock) {
+    for (int j = threadIdx.x; j < d; j += NT) {
       a.ws.gx_store[slot * d + j] = gx_sh[j];
       if (final_gx) final_gx[j] = gx_sh[j];
     }
@@ -124,8 +126,10 @@ __device__ void global_best_after(const ReqDev &a, int done, double *gx_sh, bool
 
 // G lanes per particle, each owning CPL coordinates j, j + G, ...
 template <int OBJ, int G, int CPL>
-__global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int nreq, int t) {
-  constexpr int kGroups = kPsoBlock / G;
+__global__ __launch_bounds__(pso_threads(G * CPL)) void pso_kernel(const ReqDev *reqs, int nreq,
+                                                                  int t) {
+  constexpr int NT = pso_threads(G * CPL);
+  constexpr int kGroups = NT / G;
   constexpr int kSlots = G * CPL;
   __shared__ double xs_all[kGroups][kSlots];
   __shared__ double uw_all[kGroups][2][kSlots + 4];  // the group's uniforms, two streams
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
   const int d = a.d, j = L.j, P = a.ws.pso_blocks;
   const int nb = (d + 3) >> 2;  // Philox blocks per stream
 
-  if (t > 0) global_best_after(a, t - 1, gx_sh, blk == 0, nullptr, nullptr);
+  if (t > 0) global_best_after<NT>(a, t - 1, gx_sh, blk == 0, nullptr, nullptr);
   double gxj[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) gxj[c] = (t > 0 && j + G * c < d) ? gx_sh[j + G * c] : 0.0;
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
     }
     wave_sync();  // the group's LDS is reused by its next particle
   }
-  block_argmin(key, idx, val, unused);
+  block_argmin<NT>(key, idx, val, unused);
   // stage (1): this block's result and its winner's personal-best position
   // (written by this block in this launch, so visible after the barrier)
   const int slot = t & 1;
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
     a.ws.part_f[slot * P + blk] = val;
   }
   if (idx != INT64_MAX)
-    for (int jj = threadIdx.x; jj < d; jj += kPsoBlock)
+    for (int jj = threadIdx.x; jj < d; jj += NT)
       a.ws.part_x[((size_t)slot * P + blk) * d + jj] = a.ws.px[idx * d + jj];
 }
 
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(kPsoBlock) void pso_kernel(const ReqDev *reqs, int 
 __global__ __launch_bounds__(kPsoBlock) void pso_finish_kernel(const ReqDev *reqs) {
   __shared__ double gx_sh[kMaxDim];
   const ReqDev &a = reqs[blockIdx.x];
-  global_best_after(a, a.iter_pso, gx_sh, true, a.ws.best, a.ws.gx);
+  global_best_after<kPsoBlock>(a, a.iter_pso, gx_sh, true, a.ws.best, a.ws.gx);
 }
 
 __global__ void ws_init_kernel(BatchDev *hdr) {
@@ -246,7 +250,7 @@ __global__ void ws_init_kernel(BatchDev *hdr) {
 
 template <int OBJ, int G, int CPL = 1>
 hipError_t launch_g(const Group &g, int t) {
-  hipLaunchKernelGGL((pso_kernel<OBJ, G, CPL>), dim3(g.pso_grid), dim3(kPsoBlock), 0, g.stream,
+  hipLaunchKernelGGL((pso_kernel<OBJ, G, CPL>), dim3(g.pso_grid), dim3(pso_threads(G * CPL)), 0, g.stream,
                      g.reqs, g.nreq, t);
   return hipGetLastError();
 }
@@ -275,8 +279,9 @@ int pso_group_lanes(int dim) {
 }
 
 int pso_blocks(int64_t n, int dim) {
-  const int lanes = pso_group_lanes(dim) < 64 ? pso_group_lanes(dim) : 64;
-  const int64_t per_block = kPsoBlock / lanes;
+  const int slots = pso_group_lanes(dim);
+  const int lanes = slots < 64 ? slots : 64;
+  const int64_t per_block = pso_threads(slots) / lanes;
   const int64_t want = (n + per_block - 1) / per_block;
   return (int)(want < kPsoMaxBlocks ? want : kPsoMaxBlocks);
 }

@@ -65,6 +65,13 @@ ACKLEY_D50 = problem(name="ackley_d50_n131072", objective="ackley", dim=50, n=13
 ROSENBROCK_D50 = problem(name="rosenbrock_d50_n131072", objective="rosenbrock", dim=50,
                          n=131072, lower=-5.0, upper=5.0, iter_pso=5, iter_bfgs=2000, seed=2)
 
+# Wide problems (one block per start): Styblinski-Tang and Rosenbrock,
+# d = 128, N = 16,384 in [-5,5]^128, seed 5; PSO 2, BFGS <= 1000.
+STYBLINSKI_D128 = problem(name="styblinski_d128_n16384", objective="styblinski_tang", dim=128,
+                          n=16384, lower=-5.0, upper=5.0, iter_pso=2, iter_bfgs=1000, seed=5)
+ROSENBROCK_D128 = problem(name="rosenbrock_d128_n16384", objective="rosenbrock", dim=128,
+                          n=16384, lower=-5.0, upper=5.0, iter_pso=2, iter_bfgs=1000, seed=5)
+
 BOXES = {"rosenbrock": (-5.0, 5.0), "ackley": (-5.0, 5.0), "styblinski_tang": (-5.0, 5.0),
          "rastrigin": (-5.12, 5.12)}
 MIX = ("rosenbrock", "rastrigin", "ackley", "styblinski_tang")
