@@ -313,6 +313,29 @@ def main():
 
     wall, prof, lat, out = timed(p)
     s = out["summary"]
+
+    # the same solve captured once into a HIP graph and replayed
+    plan = Z.DevicePlan(ctx, [p])
+    for _ in range(args.warmup):
+        plan.launch(sptr)
+    torch.cuda.synchronize()
+    gevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in gevs:
+        a.record(stream)
+        plan.launch(sptr)
+        b.record(stream)
+    torch.cuda.synchronize()
+    gwall = time.perf_counter() - t0
+    glat = np.array([a.elapsed_time(b) for a, b in gevs])
+    gout = plan.host()[0]
+    plan.close()
+    graph = {"ms_per_step": gwall * 1e3 / args.steps,
+             "p50_solve_ms": float(np.percentile(glat, 50)),
+             "p99_solve_ms": float(np.percentile(glat, 99)),
+             "same_results": bool(np.array_equal(gout["f"], out["f"], equal_nan=True)
+                                  and gout["summary"] == s)}
     mixed = None
     if not args.no_mixed and p.get("precision", "fp64") == "fp64":
         pm = dict(p, precision="mixed", grad_tol=max(p["grad_tol"], 1e-4))
@@ -357,6 +380,7 @@ def main():
                      "traffic": profiled_traffic(args.workload), "kernel": "bfgs_kernel",
                      "flops_per_launch": flops},
     }
+    line["graph"] = graph
     if mixed is not None:
         line["mixed"] = mixed
     if not args.no_cpu_baseline:

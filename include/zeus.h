@@ -201,6 +201,31 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem,
                              const zeus_result *out, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Plans: a batch captured once into a HIP graph and replayed.              */
+/*                                                                          */
+/* zeus_plan_create lays a batch out in a caller-owned device workspace      */
+/* (zeus_plan_workspace_bytes bytes, 256-byte aligned), uploads its request */
+/* tables, and captures the kernels of every launch group (counter reset,   */
+/* each PSO sweep, the swarm best, the persistent BFGS kernel and the       */
+/* best-of-N reduction) into one graph; launch groups become parallel       */
+/* branches.  zeus_plan_launch replays the whole solve with one graph       */
+/* launch on `stream` (a hipStream_t; NULL = the null stream).  Every       */
+/* replay recomputes the same results from the problems' seeds, written to  */
+/* the device arrays of outs.  The swarm-state outputs (seeds, pso_*) are   */
+/* not available in a plan (ZEUS_EINVAL).  The workspace and outputs must   */
+/* not be used by other work while a replay runs, and must outlive the     */
+/* plan; replays on one plan must not overlap.                              */
+/* ------------------------------------------------------------------------ */
+typedef struct zeus_plan zeus_plan;
+
+zeus_err zeus_plan_workspace_bytes(const zeus_problem *problems, int32_t n, size_t *bytes);
+zeus_err zeus_plan_create(zeus_context *ctx, const zeus_problem *problems, int32_t n,
+                          void *workspace, size_t workspace_bytes, const zeus_result *outs,
+                          zeus_plan **out);
+zeus_err zeus_plan_launch(zeus_plan *plan, void *stream);
+zeus_err zeus_plan_destroy(zeus_plan *plan);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: a request loop with continuous batching.                        */
 /*                                                                          */
 /* The paper solves one problem per call (Alg. 7).  A server keeps a queue  */

@@ -233,14 +233,20 @@ size_t hslot_bytes(int g_bfgs, int64_t total_starts, int dmax) {
   return g_bfgs == zeus::kWideLanes ? align_up(zeus::wide_hslot_bytes(total_starts, dmax)) : 0;
 }
 
-// Enqueues the whole method for a group of requests that share objective,
-// precision and lane counts: table upload, counter reset, swarm sweeps
-// 0..max iter_pso, swarm finish, one BFGS launch over all their starts, one
-// summary block per request, then the optional swarm-state copies.
-zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void *hdr_table,
-                       void *hslots, hipStream_t stream) {
-  const zeus_problem &p0 = *reqs[0].pb;
+// A launch group ready to run: the kernels' view (Group) and the host copy of
+// its request table.
+struct GroupRun {
   zeus::Group g;
+  std::vector<zeus::ReqDev> host;
+};
+
+// Builds the launch group of requests that share objective, precision and
+// lane counts (nothing is enqueued).
+zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hslots,
+                     hipStream_t stream, GroupRun *run) {
+  zeus::Group &g = run->g;
+  std::vector<zeus::ReqDev> &host = run->host;
+  const zeus_problem &p0 = *reqs[0].pb;
   g.objective = p0.objective;
   g.precision = p0.precision;
   g.g_pso = zeus::pso_group_lanes(p0.dim);
@@ -256,7 +262,7 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
   g.wide_slots = 0;
   g.wide_cs = 0;
   g.wide_slot_doubles = 0;
-  std::vector<zeus::ReqDev> host(reqs.size());
+  host.assign(reqs.size(), zeus::ReqDev{});
   for (size_t r = 0; r < reqs.size(); ++r) {
     const zeus_problem &p = *reqs[r].pb;
     zeus::ReqDev &q = host[r];
@@ -299,9 +305,25 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
     g.wide_slot_doubles = (int64_t)dmax * g.wide_cs;
     if (!hslots) return fail(ZEUS_EINVAL, "wide problem without H slots");
   }
-  hipError_t e = hipMemcpyAsync(const_cast<zeus::ReqDev *>(g.reqs), host.data(),
-                                sizeof(zeus::ReqDev) * host.size(), hipMemcpyHostToDevice, stream);
+  return ZEUS_OK;
+}
+
+zeus_err upload_group(const GroupRun &run, hipStream_t stream) {
+  hipError_t e = hipMemcpyAsync(const_cast<zeus::ReqDev *>(run.g.reqs), run.host.data(),
+                                sizeof(zeus::ReqDev) * run.host.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "request table upload");
+  return ZEUS_OK;
+}
+
+// Enqueues the kernels of a group on g.stream: counter reset, swarm sweeps
+// 0..max iter_pso, swarm finish, one BFGS launch over all its starts, one
+// summary block per request, then (with_copies) the optional swarm-state
+// copies.  The request table must already be on the device.
+zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<Planned> &reqs,
+                      bool with_copies) {
+  const zeus::Group &g = run.g;
+  hipStream_t stream = g.stream;
+  hipError_t e;
   zeus_context::Pending pend{};
   const bool prof = ctx && ctx->profiling;
   if (prof)
@@ -318,6 +340,7 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
   if ((e = zeus::launch_summary(g)) != hipSuccess) return hip_fail(e, "summary launch");
   if (prof) (void)hipEventRecord(pend.ev[3], stream);
   for (const Planned &q : reqs) {
+    if (!with_copies) break;
     const size_t nd = sizeof(double) * (size_t)q.pb->n_starts * q.pb->dim;
     const size_t n8 = sizeof(double) * (size_t)q.pb->n_starts;
     struct Copy {
@@ -337,6 +360,17 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
     ctx->prof.reduce_launches += 1;
   }
   return ZEUS_OK;
+}
+
+
+// Build, upload and launch one group on `stream`.
+zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void *hdr_table,
+                       void *hslots, hipStream_t stream) {
+  GroupRun run;
+  zeus_err e = build_group(reqs, hdr_table, hslots, stream, &run);
+  if (e == ZEUS_OK) e = upload_group(run, stream);
+  if (e == ZEUS_OK) e = launch_group(ctx, run, reqs, true);
+  return e;
 }
 
 // Device result layout of one request for the blocking entry points.
@@ -566,6 +600,14 @@ struct Ticket {
 size_t footprint(const BatchPlan &b) { return align_up(b.res_total) + align_up(b.ws_total); }
 
 }  // namespace
+
+// A captured solve: the kernels of every launch group of a batch in one HIP
+// graph, bound to a caller-owned workspace and device outputs.
+struct zeus_plan {
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 constexpr int kServerSlots = 4;       // batches in flight, one worker thread each
 constexpr int kServerMaxBatch = 512;  // requests per batch
@@ -967,6 +1009,139 @@ zeus_err zeus_server_destroy(zeus_server *srv) {
     (void)hipFree(srv->mem);
   }
   delete srv;
+  return ZEUS_OK;
+}
+
+
+zeus_err zeus_plan_workspace_bytes(const zeus_problem *problems, int32_t n, size_t *bytes) {
+  g_last_error.clear();
+  if (!problems || n < 1 || !bytes) return fail(ZEUS_EINVAL, "need n >= 1 problems and bytes");
+  std::vector<zeus_result> none(n);
+  for (int32_t r = 0; r < n; ++r) {
+    zeus_err e = check_problem(&problems[r]);
+    if (e != ZEUS_OK) return fail(e, "request " + std::to_string(r) + ": " + g_last_error);
+  }
+  *bytes = plan_batch(problems, none.data(), n).ws_total;
+  return ZEUS_OK;
+}
+
+zeus_err zeus_plan_create(zeus_context *ctx, const zeus_problem *problems, int32_t n,
+                          void *workspace, size_t workspace_bytes, const zeus_result *outs,
+                          zeus_plan **out) {
+  g_last_error.clear();
+  if (!ctx || !out) return fail(ZEUS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 1 || !problems || !outs) return fail(ZEUS_EINVAL, "need n >= 1 problems and results");
+  for (int32_t r = 0; r < n; ++r) {
+    zeus_err e = check_problem(&problems[r]);
+    if (e == ZEUS_OK) e = check_result(&outs[r], &problems[r]);
+    if (e == ZEUS_OK && (outs[r].seeds || outs[r].pso_v || outs[r].pso_px || outs[r].pso_pf ||
+                         outs[r].pso_best_x))
+      e = fail(ZEUS_EINVAL, "swarm-state outputs are not available in a plan");
+    if (e != ZEUS_OK) return fail(e, "request " + std::to_string(r) + ": " + g_last_error);
+  }
+  std::vector<zeus_result> res(outs, outs + n);
+  for (auto &r : res)
+    if (!r.trace || r.trace_len == 0) {
+      r.trace = nullptr;
+      r.trace_len = 0;
+    }
+  const BatchPlan b = plan_batch(problems, res.data(), n);
+  if (!workspace || workspace_bytes < b.ws_total)
+    return fail(ZEUS_EINVAL, "workspace missing or smaller than zeus_plan_workspace_bytes()");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(ZEUS_EINVAL, "workspace must be 256-byte aligned");
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  // build every group and upload its request table (outside the graph)
+  char *Wb = static_cast<char *>(workspace);
+  std::vector<std::vector<Planned>> members(b.order.size());
+  std::vector<GroupRun> runs(b.order.size());
+  zeus_err e;
+  for (size_t gi = 0; gi < b.order.size(); ++gi) {
+    const std::vector<int32_t> &idx = b.groups.at(b.order[gi]);
+    members[gi].resize(idx.size());
+    for (size_t k = 0; k < idx.size(); ++k) {
+      members[gi][k].pb = &problems[idx[k]];
+      members[gi][k].dev = res[idx[k]];
+      members[gi][k].ws =
+          zeus::carve_workspace(Wb + b.ws_off[idx[k]], problems[idx[k]].n_starts, problems[idx[k]].dim);
+    }
+    void *hs = b.h_off[gi] == SIZE_MAX ? nullptr : Wb + b.h_off[gi];
+    if ((e = build_group(members[gi], Wb + b.tab_off[gi], hs, ctx->stream, &runs[gi])) != ZEUS_OK)
+      return e;
+    if ((e = upload_group(runs[gi], ctx->stream)) != ZEUS_OK) return e;
+  }
+  hipError_t he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
+  // capture: groups fork from the context's stream onto up to four streams
+  const size_t nstreams = b.order.size() < 4 ? b.order.size() : 4;
+  while (ctx->aux.size() + 1 < nstreams) {
+    hipStream_t st;
+    if ((he = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(he, "hipStreamCreate");
+    ctx->aux.push_back(st);
+  }
+  std::vector<hipStream_t> streams{ctx->stream};
+  for (size_t k = 0; k + 1 < nstreams; ++k) streams.push_back(ctx->aux[k]);
+  std::vector<hipEvent_t> evs(nstreams + 1, nullptr);
+  for (auto &ev : evs)
+    if ((he = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+      for (auto &e2 : evs)
+        if (e2) (void)hipEventDestroy(e2);
+      return hip_fail(he, "hipEventCreate");
+    }
+  auto *plan = new (std::nothrow) zeus_plan;
+  if (!plan) return fail(ZEUS_ENOMEM, "plan allocation failed");
+  plan->device = ctx->device;
+  zeus_err err = ZEUS_OK;
+  he = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed);
+  if (he == hipSuccess) {
+    (void)hipEventRecord(evs[0], ctx->stream);
+    for (size_t k = 1; k < nstreams; ++k) (void)hipStreamWaitEvent(streams[k], evs[0], 0);
+    for (size_t gi = 0; gi < b.order.size() && err == ZEUS_OK; ++gi) {
+      runs[gi].g.stream = streams[gi % nstreams];
+      err = launch_group(nullptr, runs[gi], members[gi], false);
+    }
+    for (size_t k = 1; k < nstreams; ++k) {
+      (void)hipEventRecord(evs[k], streams[k]);
+      (void)hipStreamWaitEvent(ctx->stream, evs[k], 0);
+    }
+    hipError_t ce = hipStreamEndCapture(ctx->stream, &plan->graph);
+    if (err == ZEUS_OK && ce != hipSuccess) err = hip_fail(ce, "hipStreamEndCapture");
+  } else {
+    err = hip_fail(he, "hipStreamBeginCapture");
+  }
+  for (auto &ev : evs) (void)hipEventDestroy(ev);
+  if (err == ZEUS_OK && (he = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0)) != hipSuccess)
+    err = hip_fail(he, "hipGraphInstantiate");
+  if (err != ZEUS_OK) {
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return err;
+  }
+  *out = plan;
+  return ZEUS_OK;
+}
+
+zeus_err zeus_plan_launch(zeus_plan *plan, void *stream) {
+  g_last_error.clear();
+  if (!plan) return fail(ZEUS_EINVAL, "plan is NULL");
+  DeviceGuard dg(plan->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ZEUS_OK;
+}
+
+zeus_err zeus_plan_destroy(zeus_plan *plan) {
+  g_last_error.clear();
+  if (!plan) return ZEUS_OK;
+  DeviceGuard dg(plan->device);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  delete plan;
   return ZEUS_OK;
 }
 

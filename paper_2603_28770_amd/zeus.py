@@ -28,7 +28,8 @@ EXPORTS = ("zeus_abi_version", "zeus_version", "zeus_last_error", "zeus_validate
            "zeus_workspace_bytes", "zeus_context_create", "zeus_context_destroy",
            "zeus_context_set_profiling", "zeus_context_get_profile", "zeus_minimize",
            "zeus_minimize_batch", "zeus_minimize_async", "zeus_server_create",
-           "zeus_server_submit", "zeus_server_wait", "zeus_server_cancel", "zeus_server_destroy")
+           "zeus_server_submit", "zeus_server_wait", "zeus_server_cancel", "zeus_server_destroy",
+           "zeus_plan_workspace_bytes", "zeus_plan_create", "zeus_plan_launch", "zeus_plan_destroy")
 
 
 class zeus_problem(C.Structure):
@@ -101,6 +102,11 @@ def _load():
     L.zeus_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, P(zeus_request_times)]
     L.zeus_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
     L.zeus_server_destroy.argtypes = [C.c_void_p]
+    L.zeus_plan_workspace_bytes.argtypes = [P(zeus_problem), C.c_int32, P(C.c_size_t)]
+    L.zeus_plan_create.argtypes = [C.c_void_p, P(zeus_problem), C.c_int32, C.c_void_p, C.c_size_t,
+                                   P(zeus_result), P(C.c_void_p)]
+    L.zeus_plan_launch.argtypes = [C.c_void_p, C.c_void_p]
+    L.zeus_plan_destroy.argtypes = [C.c_void_p]
     for name in EXPORTS:
         if name not in ("zeus_abi_version", "zeus_version", "zeus_last_error"):
             getattr(L, name).restype = C.c_int
@@ -291,6 +297,61 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class DevicePlan:
+    """A batch captured into a HIP graph (zeus_plan_*), with torch-owned device
+    workspace and outputs; launch() replays the whole solve."""
+
+    def __init__(self, ctx, problems, device="cuda:0", trace_len=0):
+        import torch
+        self.pbs = (zeus_problem * len(problems))(
+            *[p if isinstance(p, zeus_problem) else make_problem(p) for p in problems])
+        n = len(problems)
+        wb = C.c_size_t()
+        _check(lib.zeus_plan_workspace_bytes(self.pbs, n, C.byref(wb)))
+        dev = torch.device(device)
+        self.ws = torch.empty(wb.value + 256, dtype=torch.uint8, device=dev)
+        ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        f64, i32 = torch.float64, torch.int32
+        self.t = []
+        res = (zeus_result * n)()
+        for k in range(n):
+            nn, d = self.pbs[k].n_starts, self.pbs[k].dim
+            t = {"f": torch.empty(nn, dtype=f64, device=dev),
+                 "x": torch.empty((nn, d), dtype=f64, device=dev),
+                 "iters": torch.empty(nn, dtype=i32, device=dev),
+                 "status": torch.empty(nn, dtype=i32, device=dev),
+                 "ls_trials": torch.empty(nn, dtype=i32, device=dev),
+                 "summary": torch.empty(C.sizeof(zeus_summary), dtype=torch.uint8, device=dev)}
+            if trace_len:
+                t["trace"] = torch.empty((nn, trace_len, d), dtype=f64, device=dev)
+            self.t.append(t)
+            pp = lambda key: t[key].data_ptr() if key in t else None
+            res[k] = zeus_result(f=pp("f"), x=pp("x"), iters=pp("iters"), status=pp("status"),
+                                 ls_trials=pp("ls_trials"), trace=pp("trace"),
+                                 trace_len=int(trace_len), reserved0=0, summary=pp("summary"))
+        self.res = res
+        self.h = C.c_void_p()
+        _check(lib.zeus_plan_create(ctx, self.pbs, n, C.c_void_p(ws_ptr), wb, self.res,
+                                    C.byref(self.h)))
+
+    def launch(self, stream_ptr: int = 0):
+        _check(lib.zeus_plan_launch(self.h, C.c_void_p(stream_ptr) if stream_ptr else None))
+
+    def host(self) -> list:
+        out = []
+        for t in self.t:
+            o = {k: v.cpu().numpy() for k, v in t.items() if k != "summary"}
+            s = zeus_summary.from_buffer_copy(bytes(t["summary"].cpu().numpy().tobytes()))
+            o["summary"] = _summary_dict(s)
+            out.append(o)
+        return out
+
+    def close(self):
+        if self.h:
+            _check(lib.zeus_plan_destroy(self.h))
+            self.h = C.c_void_p()
 
 
 class DeviceSolve:
