@@ -250,7 +250,7 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
   g.objective = p0.objective;
   g.precision = p0.precision;
   g.g_pso = zeus::pso_group_lanes(p0.dim);
-  g.g_bfgs = zeus::group_lanes(p0.dim);
+  g.g_bfgs = zeus::group_lanes(p0.objective, p0.precision, p0.dim);
   g.nreq = (int)reqs.size();
   g.max_iter_pso = 0;
   g.pso_grid = 0;
@@ -458,7 +458,8 @@ struct GroupKey {
 };
 
 GroupKey key_of(const zeus_problem &p) {
-  return GroupKey{p.objective, p.precision, zeus::pso_group_lanes(p.dim), zeus::group_lanes(p.dim)};
+  return GroupKey{p.objective, p.precision, zeus::pso_group_lanes(p.dim),
+                  zeus::group_lanes(p.objective, p.precision, p.dim)};
 }
 
 // Device memory plan of a batch: result arrays of every request, then the
@@ -727,7 +728,8 @@ zeus_err zeus_workspace_bytes(const zeus_problem *problem, size_t *bytes) {
   zeus_err e = check_problem(problem);
   if (e != ZEUS_OK) return e;
   *bytes = kHdrBytes + table_bytes(1) + zeus::workspace_bytes(problem->n_starts, problem->dim) +
-           hslot_bytes(zeus::group_lanes(problem->dim), problem->n_starts, problem->dim);
+           hslot_bytes(zeus::group_lanes(problem->objective, problem->precision, problem->dim),
+                       problem->n_starts, problem->dim);
   return ZEUS_OK;
 }
 
@@ -823,7 +825,7 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, voi
   }
   const size_t ws_bytes = zeus::workspace_bytes(pb.n_starts, pb.dim);
   one[0].ws = zeus::carve_workspace(base + kHdrBytes + table_bytes(1), pb.n_starts, pb.dim);
-  void *hslots = hslot_bytes(zeus::group_lanes(pb.dim), pb.n_starts, pb.dim)
+  void *hslots = hslot_bytes(zeus::group_lanes(pb.objective, pb.precision, pb.dim), pb.n_starts, pb.dim)
                      ? base + kHdrBytes + table_bytes(1) + ws_bytes
                      : nullptr;
   return enqueue_group(ctx, one, base, hslots, s);

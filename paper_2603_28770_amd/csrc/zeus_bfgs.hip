@@ -425,25 +425,37 @@ hipError_t launch_prec(const Group &g, int64_t want, int cus) {
 
 }  // namespace
 
-// Lanes per start: the smallest power of two >= dim, at least 4 (more lanes
-// per start than coordinates buy more line-search trials per round;
-// ZEUS_MIN_LANES overrides the floor for experiments).
-int group_lanes(int dim) {
+// Tiling: lanes per start (2..64, a power of two >= dim: one group per start,
+// H in registers) or kWideLanes (one block per start, H in device memory).
+// Every tiling computes the same pairwise trees, so results do not depend on
+// it; only speed does.  The rules come from the autotuner's table; a start
+// no rule covers gets the smallest power of two >= max(dim, 4), or the block
+// above 64 dimensions.  ZEUS_TILE_LANES forces a tiling (the autotuner uses
+// it to time the candidates).
+#include "zeus_tiling.inc"
+
+namespace {
+bool tiling_valid(int lanes, int dim) {
+  if (lanes == kWideLanes) return dim <= kMaxDim;
+  return lanes >= 2 && lanes <= kMaxNarrowDim && (lanes & (lanes - 1)) == 0 && lanes >= dim;
+}
+}  // namespace
+
+int group_lanes(int objective, int precision, int dim) {
+  if (const char *e = getenv("ZEUS_TILE_LANES")) {
+    const int v = atoi(e);
+    if (v > 0 && tiling_valid(v, dim)) return v;
+  }
   if (dim > kMaxNarrowDim) return kWideLanes;
-  static int floor_lanes = [] {
-    const char *e = getenv("ZEUS_MIN_LANES");
-    int v = e ? atoi(e) : 4;
-    int g = 2;
-    while (g < v && g < 64) g <<= 1;
-    return g;
-  }();
-  int g = floor_lanes;
+  for (const TileRule &r : kTileRules)
+    if (r.objective == objective && r.precision == precision && dim >= r.dmin && dim <= r.dmax &&
+        tiling_valid(r.lanes, dim))
+      return r.lanes;
+  int g = 4;
   while (g < dim) g <<= 1;
   return g;
 }
 
-// Line-search trials evaluated per round (a power of two <= G; default 4,
-// ZEUS_LS_TRIALS overrides it for experiments).
 hipError_t launch_bfgs(const Group &g) {
   int dev = 0;
   (void)hipGetDevice(&dev);

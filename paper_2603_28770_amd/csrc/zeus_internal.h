@@ -113,9 +113,15 @@ hipError_t launch_bfgs(const Group &g);
 hipError_t launch_bfgs_wide(const Group &g, int cus);
 hipError_t launch_summary(const Group &g);
 
-// Lanes per start of the BFGS kernel for a dimension (power of two >= dim, at
-// most 64; kWideLanes above kMaxNarrowDim).
-int group_lanes(int dim);
+// Lanes per start of the BFGS kernels for a problem (power of two >= dim, at
+// most 64, or kWideLanes for one block per start), from the tiling table.
+int group_lanes(int objective, int precision, int dim);
+
+// One rule of the tiling table: problems of this objective and precision
+// with dmin <= dim <= dmax run with `lanes` lanes per start.
+struct TileRule {
+  int objective, precision, dmin, dmax, lanes;
+};
 // Coordinate slots per particle of the swarm kernels (power of two >= dim;
 // lanes per particle are min(slots, 64)), and one request's grid size.
 int pso_group_lanes(int dim);
