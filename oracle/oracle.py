@@ -194,6 +194,31 @@ def bfgs(problem, x0, idx=None, trace_len=0, nthreads=None):
     return o
 
 
+ST_CONVERGED, ST_STOPPED = 1, 2
+
+
+def bfgs_required(problem, x0, required_c, nthreads=None):
+    """Alg. 10's early stop (required_c starts converged), read iteration-
+    synchronously: K* is the iteration at which the required_c-th start
+    converges (the required_c-th smallest iteration count among converged
+    starts).  Every start still running at K* ends there: its result is its
+    iterate after K* steps, status STOPPED.  Starts that ended at K* or before
+    keep their results.  With fewer than required_c convergences nothing
+    stops early.  Returns the per-start results and K* (None if no stop)."""
+    full = bfgs(problem, x0, nthreads=nthreads)
+    conv = np.sort(full["iters"][full["status"] == ST_CONVERGED])
+    if required_c <= 0 or conv.size < required_c:
+        return full, None
+    kstar = int(conv[required_c - 1])
+    late = np.flatnonzero(full["iters"] > kstar)
+    if late.size:
+        cut = bfgs(dict(problem, iter_bfgs=kstar), x0, idx=late, nthreads=nthreads)
+        for k in ("x", "f", "iters", "ls_trials"):
+            full[k][late] = cut[k]
+        full["status"][late] = ST_STOPPED
+    return full, kstar
+
+
 def best(fvals, status):
     fvals = np.ascontiguousarray(fvals, dtype=np.float64)
     status = np.ascontiguousarray(status, dtype=np.int32)

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <atomic>
@@ -69,8 +70,6 @@ zeus_err check_problem(const zeus_problem *p) {
   if (!(p->ls_shrink > 0.0 && p->ls_shrink < 1.0))
     return fail(ZEUS_EINVAL, "ls_shrink must be in (0,1)");
   if (p->required_converged < 0) return fail(ZEUS_EINVAL, "required_converged must be >= 0");
-  if (p->required_converged != 0)
-    return fail(ZEUS_EUNSUPPORTED, "early stopping (required_converged > 0) is not built");
   if (p->dim > zeus::kMaxDim) return fail(ZEUS_EUNSUPPORTED, "dim > 256 is not built");
   return ZEUS_OK;
 }
@@ -272,6 +271,7 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
     q.iter_pso = p.iter_pso;
     q.iter_bfgs = p.iter_bfgs;
     q.iter_ls = p.iter_ls;
+    q.stop_status = ZEUS_ST_MAXITER;
     q.trace_len = reqs[r].dev.trace ? reqs[r].dev.trace_len : 0;
     q.lo = p.lower;
     q.hi = p.upper;
@@ -319,28 +319,9 @@ zeus_err upload_group(const GroupRun &run, hipStream_t stream) {
 // 0..max iter_pso, swarm finish, one BFGS launch over all its starts, one
 // summary block per request, then (with_copies) the optional swarm-state
 // copies.  The request table must already be on the device.
-zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<Planned> &reqs,
-                      bool with_copies) {
-  const zeus::Group &g = run.g;
-  hipStream_t stream = g.stream;
+zeus_err enqueue_copies(const std::vector<Planned> &reqs, hipStream_t stream) {
   hipError_t e;
-  zeus_context::Pending pend{};
-  const bool prof = ctx && ctx->profiling;
-  if (prof)
-    for (auto &ev : pend.ev)
-      if (hipEventCreate(&ev) != hipSuccess) return fail(ZEUS_EHIP, "hipEventCreate failed");
-  if (prof) (void)hipEventRecord(pend.ev[0], stream);
-  if ((e = zeus::launch_ws_init(g)) != hipSuccess) return hip_fail(e, "counter reset launch");
-  for (int t = 0; t <= g.max_iter_pso; ++t)
-    if ((e = zeus::launch_pso(g, t)) != hipSuccess) return hip_fail(e, "swarm launch");
-  if ((e = zeus::launch_pso_finish(g)) != hipSuccess) return hip_fail(e, "swarm best launch");
-  if (prof) (void)hipEventRecord(pend.ev[1], stream);
-  if ((e = zeus::launch_bfgs(g)) != hipSuccess) return hip_fail(e, "BFGS launch");
-  if (prof) (void)hipEventRecord(pend.ev[2], stream);
-  if ((e = zeus::launch_summary(g)) != hipSuccess) return hip_fail(e, "summary launch");
-  if (prof) (void)hipEventRecord(pend.ev[3], stream);
   for (const Planned &q : reqs) {
-    if (!with_copies) break;
     const size_t nd = sizeof(double) * (size_t)q.pb->n_starts * q.pb->dim;
     const size_t n8 = sizeof(double) * (size_t)q.pb->n_starts;
     struct Copy {
@@ -353,15 +334,95 @@ zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<
       if (c.dst && (e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
   }
+  return ZEUS_OK;
+}
+
+// Enqueues the kernels of a group on g.stream: counter reset, (with_swarm)
+// swarm sweeps 0..max iter_pso and the swarm best, one BFGS launch over all
+// its starts, one summary block per request, then (with_copies) the optional
+// swarm-state copies.  The request table must already be on the device.
+zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<Planned> &reqs,
+                      bool with_copies, bool with_swarm = true) {
+  const zeus::Group &g = run.g;
+  hipStream_t stream = g.stream;
+  hipError_t e;
+  zeus_context::Pending pend{};
+  const bool prof = ctx && ctx->profiling;
+  if (prof)
+    for (auto &ev : pend.ev)
+      if (hipEventCreate(&ev) != hipSuccess) return fail(ZEUS_EHIP, "hipEventCreate failed");
+  if (prof) (void)hipEventRecord(pend.ev[0], stream);
+  if ((e = zeus::launch_ws_init(g)) != hipSuccess) return hip_fail(e, "counter reset launch");
+  if (with_swarm) {
+    for (int t = 0; t <= g.max_iter_pso; ++t)
+      if ((e = zeus::launch_pso(g, t)) != hipSuccess) return hip_fail(e, "swarm launch");
+    if ((e = zeus::launch_pso_finish(g)) != hipSuccess) return hip_fail(e, "swarm best launch");
+  }
+  if (prof) (void)hipEventRecord(pend.ev[1], stream);
+  if ((e = zeus::launch_bfgs(g)) != hipSuccess) return hip_fail(e, "BFGS launch");
+  if (prof) (void)hipEventRecord(pend.ev[2], stream);
+  if ((e = zeus::launch_summary(g)) != hipSuccess) return hip_fail(e, "summary launch");
+  if (prof) (void)hipEventRecord(pend.ev[3], stream);
+  if (with_copies) {
+    zeus_err ce = enqueue_copies(reqs, stream);
+    if (ce != ZEUS_OK) return ce;
+  }
   if (prof) {
     ctx->pending.push_back(pend);
-    ctx->prof.pso_launches += 3 + g.max_iter_pso;
+    ctx->prof.pso_launches += with_swarm ? 3 + g.max_iter_pso : 0;
     ctx->prof.bfgs_launches += 1;
     ctx->prof.reduce_launches += 1;
   }
   return ZEUS_OK;
 }
 
+// Alg. 10's early stop for one request (required_converged = c > 0), read
+// iteration-synchronously: K* is the iteration at which the c-th start
+// converges; every start still running at K* ends there with status STOPPED.
+// The swarm runs once; BFGS then runs from its seeds with an iteration cap
+// of 16, 64, ... (x4, at most iter_bfgs) until at least c starts have
+// converged, and a last time with the cap at K* when K* is below the cap.
+// Each pass is deterministic, so the result is the same as a run that stops
+// every start at K*.  Synchronises `stream` between passes.
+zeus_err run_required(zeus_context *ctx, const std::vector<Planned> &reqs, void *hdr_table,
+                      void *hslots, hipStream_t stream) {
+  const zeus_problem &p = *reqs[0].pb;
+  const int64_t c = p.required_converged, n = p.n_starts;
+  std::vector<int32_t> it((size_t)n), st((size_t)n);
+  int cap = p.iter_bfgs < 16 ? p.iter_bfgs : 16;
+  bool swarm = true, last = false;
+  zeus_err e;
+  for (;;) {
+    GroupRun run;
+    if ((e = build_group(reqs, hdr_table, hslots, stream, &run)) != ZEUS_OK) return e;
+    run.host[0].iter_bfgs = cap;
+    run.host[0].stop_status = cap < p.iter_bfgs ? ZEUS_ST_STOPPED : ZEUS_ST_MAXITER;
+    if ((e = upload_group(run, stream)) != ZEUS_OK) return e;
+    if ((e = launch_group(ctx, run, reqs, false, swarm)) != ZEUS_OK) return e;
+    swarm = false;
+    if (last) break;
+    hipError_t he = hipMemcpyAsync(it.data(), reqs[0].dev.iters, 4 * (size_t)n, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(st.data(), reqs[0].dev.status, 4 * (size_t)n, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(stream);
+    if (he != hipSuccess) return hip_fail(he, "early-stop pass");
+    std::vector<int32_t> conv;
+    for (int64_t i = 0; i < n; ++i)
+      if (st[(size_t)i] == ZEUS_ST_CONVERGED) conv.push_back(it[(size_t)i]);
+    if ((int64_t)conv.size() >= c) {
+      std::nth_element(conv.begin(), conv.begin() + (c - 1), conv.end());
+      const int kstar = conv[(size_t)(c - 1)];
+      if (kstar == cap) break;
+      cap = kstar;
+      last = true;
+    } else if (cap >= p.iter_bfgs) {
+      break;  // fewer than c starts converge within the budget: no early stop
+    } else {
+      cap = cap * 4 < p.iter_bfgs ? cap * 4 : p.iter_bfgs;
+    }
+  }
+  return enqueue_copies(reqs, stream);
+}
 
 // Build, upload and launch one group on `stream`.
 zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void *hdr_table,
@@ -449,7 +510,9 @@ zeus_err copy_back(const zeus_problem &pb, const zeus_result &out, const zeus_re
 // lane counts run in one group.
 struct GroupKey {
   int objective, precision, g_pso, g_bfgs;
+  int64_t solo;  // > 0: a request with early stop, in a group of its own
   bool operator<(const GroupKey &o) const {
+    if (solo != o.solo) return solo < o.solo;
     if (objective != o.objective) return objective < o.objective;
     if (precision != o.precision) return precision < o.precision;
     if (g_pso != o.g_pso) return g_pso < o.g_pso;
@@ -457,9 +520,10 @@ struct GroupKey {
   }
 };
 
-GroupKey key_of(const zeus_problem &p) {
+GroupKey key_of(const zeus_problem &p, int32_t index) {
   return GroupKey{p.objective, p.precision, zeus::pso_group_lanes(p.dim),
-                  zeus::group_lanes(p.objective, p.precision, p.dim)};
+                  zeus::group_lanes(p.objective, p.precision, p.dim),
+                  p.required_converged > 0 ? (int64_t)index + 1 : 0};
 }
 
 // Device memory plan of a batch: result arrays of every request, then the
@@ -476,7 +540,7 @@ struct BatchPlan {
 BatchPlan plan_batch(const zeus_problem *problems, const zeus_result *outs, int32_t n) {
   BatchPlan b;
   for (int32_t r = 0; r < n; ++r) {
-    const GroupKey k = key_of(problems[r]);
+    const GroupKey k = key_of(problems[r], r);
     auto it = b.groups.find(k);
     if (it == b.groups.end()) b.order.push_back(k);
     b.groups[k].push_back(r);
@@ -529,7 +593,11 @@ zeus_err enqueue_batch(zeus_context *ctx, const BatchPlan &b, const zeus_problem
       plan[k].ws = zeus::carve_workspace(Wb + b.ws_off[r], problems[r].n_starts, problems[r].dim);
     }
     void *hs = b.h_off[gi] == SIZE_MAX ? nullptr : Wb + b.h_off[gi];
-    if ((e = enqueue_group(ctx, plan, Wb + b.tab_off[gi], hs, s)) != ZEUS_OK) return e;
+    if (b.order[gi].solo > 0)
+      e = run_required(ctx, plan, Wb + b.tab_off[gi], hs, s);
+    else
+      e = enqueue_group(ctx, plan, Wb + b.tab_off[gi], hs, s);
+    if (e != ZEUS_OK) return e;
     for (size_t k = 0; k < members.size(); ++k)
       if ((e = copy_back(problems[members[k]], outs[members[k]], plan[k].dev, s)) != ZEUS_OK)
         return e;
@@ -804,6 +872,8 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, voi
   zeus_err e = check_problem(problem);
   if (e != ZEUS_OK) return e;
   if ((e = check_result(out, problem)) != ZEUS_OK) return e;
+  if (problem->required_converged > 0)
+    return fail(ZEUS_EUNSUPPORTED, "early stopping needs zeus_minimize, zeus_minimize_batch or a server");
   const zeus_problem pb = *problem;
   size_t need = 0;
   (void)zeus_workspace_bytes(&pb, &need);
@@ -1040,6 +1110,8 @@ zeus_err zeus_plan_create(zeus_context *ctx, const zeus_problem *problems, int32
     if (e == ZEUS_OK && (outs[r].seeds || outs[r].pso_v || outs[r].pso_px || outs[r].pso_pf ||
                          outs[r].pso_best_x))
       e = fail(ZEUS_EINVAL, "swarm-state outputs are not available in a plan");
+    if (e == ZEUS_OK && problems[r].required_converged > 0)
+      e = fail(ZEUS_EUNSUPPORTED, "early stopping is not available in a plan");
     if (e != ZEUS_OK) return fail(e, "request " + std::to_string(r) + ": " + g_last_error);
   }
   std::vector<zeus_result> res(outs, outs + n);

@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     else if (sqrt(gg) < q.tol)
       status = ZEUS_ST_CONVERGED;
     else if (k == q.iter_bfgs)
-      status = ZEUS_ST_MAXITER;
+      status = q.stop_status;  // MAXITER, or STOPPED at an early-stop cap
     if (status >= 0) {
       const ReqDev &rq = reqs[q.ri];
       const int tl = q.trace_len;

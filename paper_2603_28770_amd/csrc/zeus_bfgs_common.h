@@ -14,6 +14,7 @@ namespace zeus {
 struct ReqHot {
   int d, m;                  // dimension, number of terms
   int iter_bfgs, iter_ls, trace_len, ri;
+  int stop_status;           // status at the iteration budget
   double armijo_c, tol, shrink;
 };
 constexpr int kHotDoubles = (sizeof(ReqHot) + 7) / 8;
@@ -55,6 +56,7 @@ __device__ __forceinline__ void load_hot(ReqHot &w, const ReqDev &rq, int ri) {
   w.d = rq.d;
   w.m = Elem<OBJ>::terms(rq.d);
   w.iter_bfgs = rq.iter_bfgs;
+  w.stop_status = rq.stop_status;
   w.iter_ls = rq.iter_ls;
   w.trace_len = rq.trace ? rq.trace_len : 0;
   w.ri = ri;

@@ -61,7 +61,8 @@ Workspace carve_workspace(void *base, int64_t n, int dim);
 // A launch serves requests that share objective, precision and lane counts.
 struct ReqDev {
   int64_t n;                 // particles == starts
-  int d, iter_pso, iter_bfgs, iter_ls, trace_len, pad0;
+  int d, iter_pso, iter_bfgs, iter_ls, trace_len;
+  int stop_status;           // status of a start that reaches iter_bfgs
   double lo, hi, vh;         // box and velocity half-range
   double w, c1, c2;          // swarm coefficients
   double armijo_c, shrink, tol;

@@ -92,7 +92,7 @@ def test_validation_abi_and_reserved(Z):
     assert Z.lib.zeus_validate(None) == Z.EINVAL
 
 
-@pytest.mark.parametrize("unsup", [dict(dim=257), dict(required_converged=5)])
+@pytest.mark.parametrize("unsup", [dict(dim=257)])
 def test_validation_unsupported(Z, unsup):
     assert Z.zeus_validate(Z.make_problem(_p(**unsup))) == Z.EUNSUPPORTED
 
