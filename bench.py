@@ -252,6 +252,9 @@ def main():
     ap.add_argument("--n-scale", type=float, default=0.0,
                     help="multi-request workloads: multiply every request's start count")
     ap.add_argument("--requests", type=int, default=0, help="served_mix: number of requests")
+    ap.add_argument("--required-c", type=int, default=0, metavar="C",
+                    help="also time the solve with early stop at C converged starts (the "
+                         "paper's time-to-C-convergences metric; blocking entry point)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run of the same workload")
@@ -350,7 +353,6 @@ def main():
                  "p99_solve_ms": float(np.percentile(mlat, 99)),
                  "success_rate": float(np.mean(mout["f"] - fstar_m < 1e-4)),
                  "speedup_vs_fp64": (wall * 1e3 / args.steps) / mms}
-    Z.zeus_context_destroy(ctx)
 
     ms_per_step = wall * 1e3 / args.steps
     iters = s["total_iters"]
@@ -381,8 +383,28 @@ def main():
                      "flops_per_launch": flops},
     }
     line["graph"] = graph
+    if args.required_c > 0:
+        # time to required_c convergences against the full solve, both through
+        # the blocking entry point (results copied to the host)
+        Z.zeus_minimize(ctx, dict(p, required_converged=args.required_c))
+        reps = max(1, args.steps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            full = Z.zeus_minimize(ctx, p)
+        t_full = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            early = Z.zeus_minimize(ctx, dict(p, required_converged=args.required_c))
+        t_early = (time.perf_counter() - t0) / reps
+        line["time_to_c"] = {
+            "required_c": args.required_c, "ms": t_early * 1e3, "full_solve_ms": t_full * 1e3,
+            "speedup": t_full / t_early, "k_star": int(early["iters"].max()),
+            "converged": int(np.sum(early["status"] == 1)),
+            "stopped": int(np.sum(early["status"] == 2)),
+            "full_converged": int(np.sum(full["status"] == 1))}
     if mixed is not None:
         line["mixed"] = mixed
+    Z.zeus_context_destroy(ctx)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)

@@ -27,7 +27,7 @@ class _Problem(C.Structure):
                 ("iter_bfgs", C.c_int32), ("iter_ls", C.c_int32),
                 ("armijo_c", C.c_double), ("ls_shrink", C.c_double),
                 ("grad_tol", C.c_double), ("seed", C.c_uint64),
-                ("request_id", C.c_uint64)]
+                ("request_id", C.c_uint64), ("lbfgs_m", C.c_int32)]
 
 
 class _Swarm(C.Structure):
@@ -63,6 +63,8 @@ def lib():
         L.zo_grad.argtypes = [C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p]
         L.zo_bfgs_update.restype = C.c_int
         L.zo_bfgs_update.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.zo_lbfgs_direction.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                         C.c_int, C.c_void_p]
         L.zo_line_search.restype = C.c_double
         L.zo_line_search.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_double, C.c_void_p,
                                      C.c_double, C.c_void_p, C.POINTER(C.c_int32),
@@ -95,7 +97,8 @@ def make_problem(p: dict) -> _Problem:
         v_half=float(p.get("v_half", 0.0)), iter_bfgs=int(p.get("iter_bfgs", 100)),
         iter_ls=int(p.get("iter_ls", 20)), armijo_c=float(p.get("armijo_c", 0.3)),
         ls_shrink=float(p.get("ls_shrink", 0.5)), grad_tol=float(p.get("grad_tol", 1e-6)),
-        seed=int(p.get("seed", 0)), request_id=int(p.get("request_id", 0)))
+        seed=int(p.get("seed", 0)), request_id=int(p.get("request_id", 0)),
+        lbfgs_m=int(p.get("lbfgs_m", 0)))
 
 
 def philox(ctr, key):
@@ -121,6 +124,17 @@ def grad(objective, x):
     fv = C.c_double()
     lib().zo_grad(OBJECTIVES[objective], _ptr(x), x.size, C.byref(fv), _ptr(g))
     return fv.value, g
+
+
+def lbfgs_direction(S, Y, rho, g):
+    """Two-loop recursion p = -H g over the pairs in the rows of S, Y (oldest first)."""
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    p = np.empty_like(g)
+    lib().zo_lbfgs_direction(_ptr(S), _ptr(Y), _ptr(rho), int(rho.size), _ptr(g), g.size, _ptr(p))
+    return p
 
 
 def bfgs_update(H, s, y):

@@ -368,6 +368,7 @@ int zo_validate(const zo_problem *pb) {
   if (!isfinite(pb->grad_tol) || !(pb->grad_tol > 0.0)) return -1;
   if (!(pb->armijo_c > 0.0 && pb->armijo_c < 1.0)) return -1;
   if (!(pb->ls_shrink > 0.0 && pb->ls_shrink < 1.0)) return -1;
+  if (pb->lbfgs_m < 0) return -1;
   return 0;
 }
 
@@ -537,6 +538,32 @@ int zo_bfgs_update(double *H, const double *s, const double *y, int d) {
   return 1;
 }
 
+void zo_lbfgs_direction(const double *S, const double *Y, const double *rho, int count,
+                        const double *g, int d, double *p) {
+  double *q = (double *)malloc(sizeof(double) * (size_t)d);
+  double *alpha = (double *)malloc(sizeof(double) * (size_t)(count > 0 ? count : 1));
+  memcpy(q, g, sizeof(double) * (size_t)d);
+  /* first loop, newest pair first: alpha_i = rho_i s_i'q, q <- q - alpha_i y_i */
+  for (int i = count - 1; i >= 0; --i) {
+    alpha[i] = rho[i] * pw_dot(S + (size_t)i * d, q, d);
+    for (int j = 0; j < d; ++j) q[j] = fma(-alpha[i], Y[(size_t)i * d + j], q[j]);
+  }
+  /* r = H0 q with H0 = gamma I */
+  if (count > 0) {
+    const double *sn = S + (size_t)(count - 1) * d, *yn = Y + (size_t)(count - 1) * d;
+    double gamma = pw_dot(sn, yn, d) / pw_dot(yn, yn, d);
+    for (int j = 0; j < d; ++j) q[j] = gamma * q[j];
+  }
+  /* second loop, oldest pair first: beta = rho_i y_i'r, r <- r + (alpha_i - beta) s_i */
+  for (int i = 0; i < count; ++i) {
+    double beta = rho[i] * pw_dot(Y + (size_t)i * d, q, d);
+    for (int j = 0; j < d; ++j) q[j] = fma(alpha[i] - beta, S[(size_t)i * d + j], q[j]);
+  }
+  for (int j = 0; j < d; ++j) p[j] = -q[j];
+  free(alpha);
+  free(q);
+}
+
 /* Track the smallest decision margin and the first iteration at which a
  * margin fell below ZO_TIE_MARGIN (a near-tie: rounding differences of other
  * implementations may legitimately take the other branch there). */
@@ -562,6 +589,14 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
   int32_t tie_iter = -1;
   double *trace = out->trace ? out->trace + k_out * (int64_t)out->trace_len * d : NULL;
 
+  const int lm = pb->lbfgs_m;                    /* L-BFGS history (0: BFGS) */
+  double *LS = NULL, *LY = NULL, *lrho = NULL;
+  int lcount = 0;
+  if (lm > 0) {
+    LS = (double *)malloc(sizeof(double) * (size_t)lm * d);
+    LY = (double *)malloc(sizeof(double) * (size_t)lm * d);
+    lrho = (double *)malloc(sizeof(double) * (size_t)lm);
+  }
   memcpy(x, x0, sizeof(double) * (size_t)d);    /* x <- swarm[i]        */
   for (int i = 0; i < d; ++i)                    /* H <- I               */
     for (int j = 0; j < d; ++j) H[i * d + j] = (i == j) ? 1.0 : 0.0;
@@ -579,11 +614,16 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
     if (gnorm < pb->grad_tol) { status = ZO_CONVERGED; break; }
     if (k == pb->iter_bfgs) { status = ZO_MAXITER; break; }
 
-    /* search direction p = -H g (products accumulated by fused multiply-add) */
-    for (int i = 0; i < d; ++i) {
-      double acc = 0.0;
-      for (int j = 0; j < d; ++j) acc = fma(H[i * d + j], g[j], acc);
-      p[i] = -acc;
+    /* search direction p = -H g (products accumulated by fused multiply-add),
+     * or the L-BFGS two-loop recursion over the stored pairs */
+    if (lm > 0) {
+      zo_lbfgs_direction(LS, LY, lrho, lcount, g, d, p);
+    } else {
+      for (int i = 0; i < d; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < d; ++j) acc = fma(H[i * d + j], g[j], acc);
+        p[i] = -acc;
+      }
     }
     double ddir = pw_dot(g, p, d);
     {
@@ -593,6 +633,7 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
     if (!(ddir < 0.0)) {  /* not a descent direction: restart from H = I */
       for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) H[i * d + j] = (i == j) ? 1.0 : 0.0;
+      lcount = 0;         /* L-BFGS: forget the stored pairs */
       for (int i = 0; i < d; ++i) p[i] = -g[i];
       ddir = pw_dot(g, p, d);
       ++resets;
@@ -615,7 +656,26 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
       double m = fabs(sy) / (sqrt(pw_dot(s, s, d)) * sqrt(pw_dot(y, y, d)));
       if (!isnan(m)) note_margin(m, k, &min_margin, &tie_iter);
     }
-    if (!zo_bfgs_update(H, s, y, d)) ++skips;
+    if (lm > 0) {
+      /* L-BFGS: keep the pair when y's > 0, dropping the oldest beyond m */
+      double sy = pw_dot(y, s, d);
+      if (sy > 0.0) {
+        if (lcount == lm) {
+          memmove(LS, LS + d, sizeof(double) * (size_t)(lm - 1) * d);
+          memmove(LY, LY + d, sizeof(double) * (size_t)(lm - 1) * d);
+          memmove(lrho, lrho + 1, sizeof(double) * (size_t)(lm - 1));
+          --lcount;
+        }
+        memcpy(LS + (size_t)lcount * d, s, sizeof(double) * (size_t)d);
+        memcpy(LY + (size_t)lcount * d, y, sizeof(double) * (size_t)d);
+        lrho[lcount] = 1.0 / sy;
+        ++lcount;
+      } else {
+        ++skips;
+      }
+    } else if (!zo_bfgs_update(H, s, y, d)) {
+      ++skips;
+    }
 
     memcpy(x, xn, sizeof(double) * (size_t)d);
     memcpy(g, gn, sizeof(double) * (size_t)d);
@@ -623,6 +683,9 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
     ++k;
   }
 
+  free(LS);
+  free(LY);
+  free(lrho);
   if (trace)
     for (int kk = k + 1; kk < out->trace_len; ++kk)
       for (int j = 0; j < d; ++j) trace[(int64_t)kk * d + j] = NAN;

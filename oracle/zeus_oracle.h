@@ -61,6 +61,8 @@ typedef struct {
   double grad_tol;      /* Theta: converged when ||g||_2 < Theta               */
   uint64_t seed;        /* Philox key word 0                                  */
   uint64_t request_id;  /* Philox key word 1                                  */
+  int32_t lbfgs_m;      /* 0: BFGS with the full inverse Hessian; m > 0:
+                           L-BFGS keeping the m most recent (s, y) pairs       */
 } zo_problem;
 
 /* Swarm state after PSO.  Arrays are caller-owned, row-major [n][dim]. */
@@ -133,6 +135,14 @@ double zo_line_search(const zo_problem *pb, const double *x, double f0,
                       int32_t *trials, int32_t *accepted);
 
 /* ---- the method --------------------------------------------------------- */
+
+/* L-BFGS search direction p = -H g by the two-loop recursion (Nocedal and
+ * Wright, "Numerical Optimization", 2nd ed., Alg. 7.4): H is the inverse-
+ * Hessian approximation built from the `count` pairs in the rows of S and Y
+ * (oldest first, rho_i = 1 / y_i's_i) on H0 = gamma I, gamma = s'y / y'y of
+ * the newest pair (their eq. 7.20); with no pairs, p = -g. */
+void zo_lbfgs_direction(const double *S, const double *Y, const double *rho, int count,
+                        const double *g, int dim, double *p);
 
 /* 0 if the problem is acceptable, -1 otherwise. */
 int zo_validate(const zo_problem *pb);
