@@ -72,7 +72,7 @@ typedef enum zeus_precision { ZEUS_FP64 = 0, ZEUS_MIXED = 1 } zeus_precision;
 typedef enum zeus_start_status {
   ZEUS_ST_MAXITER = 0,
   ZEUS_ST_CONVERGED = 1,
-  ZEUS_ST_STOPPED = 2,   /* reserved for early stopping at required_converged */
+  ZEUS_ST_STOPPED = 2,   /* stopped early at required_converged                 */
   ZEUS_ST_NONFINITE = 3  /* f or a gradient component became inf/NaN          */
 } zeus_start_status;
 
@@ -82,7 +82,7 @@ typedef enum zeus_start_status {
 typedef struct zeus_problem {
   uint32_t abi_version;  /* must be ZEUS_ABI_VERSION                             */
   int32_t objective;     /* zeus_objective                                       */
-  int32_t dim;           /* 1 <= dim <= 64 in this build                          */
+  int32_t dim;           /* 1 <= dim <= 256 in this build                         */
   int32_t precision;     /* zeus_precision                                       */
   int64_t n_starts;      /* N particles == N BFGS starts, >= 1                    */
   double lower, upper;   /* sampling box, same on every axis (Alg. 2 'range');
@@ -90,14 +90,25 @@ typedef struct zeus_problem {
   int32_t iter_pso;      /* synchronous PSO updates, >= 0                          */
   int32_t iter_bfgs;     /* BFGS iteration budget per start, >= 0                  */
   int32_t iter_ls;       /* Armijo trials per line search, >= 1 (paper: 20)         */
-  int32_t reserved0;     /* must be 0                                              */
+  int32_t lbfgs_m;       /* 0: BFGS with the full inverse Hessian (Alg. 4).  1..8:
+                            limited-memory BFGS keeping the lbfgs_m newest (s, y)
+                            pairs with y's > 0, direction by the two-loop
+                            recursion on H0 = (s'y / y'y) I of the newest pair
+                            (Nocedal and Wright, Alg. 7.4 and eq. 7.20), the
+                            remedy Sec. VII names for the d^2 update; no d x d
+                            matrix is kept.  > 8: ZEUS_EUNSUPPORTED            */
   double w, c1, c2;      /* PSO inertia, cognitive, social (paper: 0.5, 1.2, 1.5)  */
   double v_half;         /* initial velocity in [-v_half, v_half]; <= 0 selects
                             upper - lower as in Alg. 2                             */
   double armijo_c;       /* sufficient-decrease constant in (0,1) (paper: 0.3)      */
   double ls_shrink;      /* backtracking factor in (0,1) (paper: 0.5)               */
   double grad_tol;       /* Theta > 0: a start converges when ||grad||_2 < Theta     */
-  int64_t required_converged; /* must be 0 (early stopping not built)              */
+  int64_t required_converged; /* 0: off.  c > 0: stop when c starts have converged
+                            (Alg. 10), read iteration-synchronously: K* is the
+                            iteration at which the c-th start converges, and
+                            every start still running at K* ends there with
+                            status ZEUS_ST_STOPPED.  Blocking and server entry
+                            points only (async and plans: ZEUS_EUNSUPPORTED)   */
   uint64_t seed;         /* Philox key word 0                                      */
   uint64_t request_id;   /* Philox key word 1                                      */
 } zeus_problem;
@@ -156,7 +167,7 @@ const char *zeus_version(void);
 const char *zeus_last_error(void);
 
 /* Checks a problem against the rules above.  ZEUS_OK, ZEUS_EINVAL (invalid) or
- * ZEUS_EUNSUPPORTED (valid but outside this build, e.g. dim > 64). */
+ * ZEUS_EUNSUPPORTED (valid but outside this build, e.g. dim > 256). */
 zeus_err zeus_validate(const zeus_problem *problem);
 
 /* Device workspace that zeus_minimize_async needs for this problem, in bytes.

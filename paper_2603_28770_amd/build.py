@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libzeus.so")
 ARCH = os.environ.get("ZEUS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["zeus_api.cpp", "zeus_pso.hip", "zeus_bfgs.hip", "zeus_bfgs_wide.hip"]
+SOURCES = ["zeus_api.cpp", "zeus_pso.hip", "zeus_bfgs.hip", "zeus_bfgs_wide.hip", "zeus_lbfgs.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -59,7 +59,9 @@ zeus_err check_problem(const zeus_problem *p) {
     return fail(ZEUS_EINVAL, "need finite lower < upper");
   if (p->iter_pso < 0 || p->iter_bfgs < 0 || p->iter_ls < 1)
     return fail(ZEUS_EINVAL, "need iter_pso >= 0, iter_bfgs >= 0, iter_ls >= 1");
-  if (p->reserved0 != 0) return fail(ZEUS_EINVAL, "reserved0 must be 0");
+  if (p->lbfgs_m < 0) return fail(ZEUS_EINVAL, "lbfgs_m must be >= 0");
+  if (p->lbfgs_m > zeus::kLbfgsMaxHistory)
+    return fail(ZEUS_EUNSUPPORTED, "lbfgs_m above 8 is not built");
   if (!std::isfinite(p->w) || !std::isfinite(p->c1) || !std::isfinite(p->c2) ||
       !std::isfinite(p->v_half))
     return fail(ZEUS_EINVAL, "PSO coefficients must be finite");
@@ -232,6 +234,14 @@ size_t hslot_bytes(int g_bfgs, int64_t total_starts, int dmax) {
   return g_bfgs == zeus::kWideLanes ? align_up(zeus::wide_hslot_bytes(total_starts, dmax)) : 0;
 }
 
+// Method (0 BFGS, 1 L-BFGS) and lanes / coordinate slots per start of a problem.
+int method_of(const zeus_problem &p) { return p.lbfgs_m > 0 ? 1 : 0; }
+int lanes_of(const zeus_problem &p) {
+  return method_of(p) ? zeus::lbfgs_slots(p.dim) : zeus::group_lanes(p.objective, p.precision, p.dim);
+}
+// Only BFGS above the narrow limit keeps H in device-memory slots.
+int hslot_lanes(const zeus_problem &p) { return method_of(p) ? 0 : lanes_of(p); }
+
 // A launch group ready to run: the kernels' view (Group) and the host copy of
 // its request table.
 struct GroupRun {
@@ -249,7 +259,8 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
   g.objective = p0.objective;
   g.precision = p0.precision;
   g.g_pso = zeus::pso_group_lanes(p0.dim);
-  g.g_bfgs = zeus::group_lanes(p0.objective, p0.precision, p0.dim);
+  g.method = method_of(p0);
+  g.g_bfgs = lanes_of(p0);
   g.nreq = (int)reqs.size();
   g.max_iter_pso = 0;
   g.pso_grid = 0;
@@ -272,6 +283,7 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
     q.iter_bfgs = p.iter_bfgs;
     q.iter_ls = p.iter_ls;
     q.stop_status = ZEUS_ST_MAXITER;
+    q.lbfgs_m = p.lbfgs_m;
     q.trace_len = reqs[r].dev.trace ? reqs[r].dev.trace_len : 0;
     q.lo = p.lower;
     q.hi = p.upper;
@@ -298,7 +310,7 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
     g.pso_grid += q.ws.pso_blocks;
     if (p.iter_pso > g.max_iter_pso) g.max_iter_pso = p.iter_pso;
   }
-  if (g.g_bfgs == zeus::kWideLanes) {
+  if (g.method == 0 && g.g_bfgs == zeus::kWideLanes) {
     const int dmax = max_dim(reqs);
     g.wide_slots = zeus::wide_slots(g.total_starts);
     g.wide_cs = zeus::wide_cs(dmax);
@@ -509,11 +521,12 @@ zeus_err copy_back(const zeus_problem &pb, const zeus_result &out, const zeus_re
 // Launch groups of a batch: requests that share objective, precision and
 // lane counts run in one group.
 struct GroupKey {
-  int objective, precision, g_pso, g_bfgs;
+  int objective, precision, method, g_pso, g_bfgs;
   int64_t solo;  // > 0: a request with early stop, in a group of its own
   bool operator<(const GroupKey &o) const {
     if (solo != o.solo) return solo < o.solo;
     if (objective != o.objective) return objective < o.objective;
+    if (method != o.method) return method < o.method;
     if (precision != o.precision) return precision < o.precision;
     if (g_pso != o.g_pso) return g_pso < o.g_pso;
     return g_bfgs < o.g_bfgs;
@@ -521,9 +534,8 @@ struct GroupKey {
 };
 
 GroupKey key_of(const zeus_problem &p, int32_t index) {
-  return GroupKey{p.objective, p.precision, zeus::pso_group_lanes(p.dim),
-                  zeus::group_lanes(p.objective, p.precision, p.dim),
-                  p.required_converged > 0 ? (int64_t)index + 1 : 0};
+  return GroupKey{p.objective, p.precision, method_of(p), zeus::pso_group_lanes(p.dim),
+                  lanes_of(p), p.required_converged > 0 ? (int64_t)index + 1 : 0};
 }
 
 // Device memory plan of a batch: result arrays of every request, then the
@@ -567,7 +579,7 @@ BatchPlan plan_batch(const zeus_problem *problems, const zeus_result *outs, int3
       starts += problems[r].n_starts;
       dmax = problems[r].dim > dmax ? problems[r].dim : dmax;
     }
-    const size_t hb = hslot_bytes(b.order[gi].g_bfgs, starts, dmax);
+    const size_t hb = hslot_bytes(b.order[gi].method ? 0 : b.order[gi].g_bfgs, starts, dmax);
     b.h_off[gi] = hb ? b.ws_total : SIZE_MAX;
     b.ws_total += hb;
   }
@@ -796,8 +808,7 @@ zeus_err zeus_workspace_bytes(const zeus_problem *problem, size_t *bytes) {
   zeus_err e = check_problem(problem);
   if (e != ZEUS_OK) return e;
   *bytes = kHdrBytes + table_bytes(1) + zeus::workspace_bytes(problem->n_starts, problem->dim) +
-           hslot_bytes(zeus::group_lanes(problem->objective, problem->precision, problem->dim),
-                       problem->n_starts, problem->dim);
+           hslot_bytes(hslot_lanes(*problem), problem->n_starts, problem->dim);
   return ZEUS_OK;
 }
 
@@ -895,7 +906,7 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, voi
   }
   const size_t ws_bytes = zeus::workspace_bytes(pb.n_starts, pb.dim);
   one[0].ws = zeus::carve_workspace(base + kHdrBytes + table_bytes(1), pb.n_starts, pb.dim);
-  void *hslots = hslot_bytes(zeus::group_lanes(pb.objective, pb.precision, pb.dim), pb.n_starts, pb.dim)
+  void *hslots = hslot_bytes(hslot_lanes(pb), pb.n_starts, pb.dim)
                      ? base + kHdrBytes + table_bytes(1) + ws_bytes
                      : nullptr;
   return enqueue_group(ctx, one, base, hslots, s);

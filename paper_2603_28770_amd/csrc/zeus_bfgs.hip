@@ -46,60 +46,6 @@ __device__ __host__ __forceinline__ constexpr int group_stride(int G) {
   return 5 * G + kTabTrials + kHotDoubles;
 }
 
-// Line-search trials per round: R trials of G / R lanes each.
-template <int G>
-constexpr int kRound = G < 4 ? G : 4;
-
-// One Armijo search (Alg. 6) with the objective evaluated in number type U.
-// A round evaluates R consecutive trials of the sequence at once, each spread
-// over TP = G / R lanes: lane c of a trial evaluates the term slots
-// cR .. cR + R - 1 (zero past the last term) and adds them pairwise, and the
-// trial's lanes finish the pairwise sum across lanes.  The first trial that
-// passes is the step Alg. 6 returns.  Returns its index, or -1 when none of
-// the iter_ls trials passes.
-template <int OBJ, int G, class U>
-__device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const GroupShm &sh, double f,
-                                             double ddir) {
-  using E = Elem<OBJ>;
-  constexpr int R = kRound<G>, TP = G / R;
-  constexpr uint64_t leaders = [] {  // bit r * TP for every trial r of a round
-    uint64_t b = 0;
-    for (int r = 0; r < R; ++r) b |= 1ull << (r * TP);
-    return b;
-  }();
-  const int trial_slot = L.j / TP, c = L.j % TP;
-  const ReqHot &q = *sh.q;
-  const int d = q.d, m = q.m;
-  for (int base = 0; base < q.iter_ls; base += R) {
-    const int t = base + trial_slot;
-    const double alpha = step_length(sh.al, q.shrink, t);
-    U tv[E::K][R];
-#pragma unroll
-    for (int b = 0; b < R; ++b) {
-      const int i = c * R + b;
-      U out[E::K];
-#pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) out[kk] = U(0);
-      if (i < m) {
-        U w[E::W];
-#pragma unroll
-        for (int e = 0; e < E::W; ++e) w[e] = (U)(sh.xs[i + e] + alpha * sh.ps[i + e]);
-        E::template term<U>(w, out);
-      }
-#pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = out[kk];
-    }
-    U sums[E::K];
-#pragma unroll
-    for (int kk = 0; kk < E::K; ++kk) sums[kk] = lane_tree_sum<TP, U>(reg_tree_sum<R, U>(tv[kk]));
-    const double ft = (double)E::template outer<U>(d, sums);
-    const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
-    const uint64_t hit = L.ballot(ok) & leaders;
-    if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1) / TP;
-  }
-  return -1;
-}
-
 // T = double: every step in FP64.
 // T = float (mixed precision): a start evaluates the objective, its dual
 // numbers and the term sums in FP32 at the FP32-rounded point, while x, p, H,
@@ -268,9 +214,9 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     // -- Armijo backtracking (Alg. 6) ---------------------------------------
     int taken;
     if (hi) {
-      taken = armijo_search<OBJ, G, double>(L, sh, f, ddir);
+      taken = armijo_search<OBJ, G, G, double>(L, sh.xs, sh.ps, sh.al, *sh.q, f, ddir);
     } else {
-      taken = armijo_search<OBJ, G, T>(L, sh, f, ddir);
+      taken = armijo_search<OBJ, G, G, T>(L, sh.xs, sh.ps, sh.al, *sh.q, f, ddir);
       if (taken < 0) {
         ls_trials += q.iter_ls;
         hi = true;  // escalate: FP32 cannot resolve this decrease
@@ -462,6 +408,7 @@ hipError_t launch_bfgs(const Group &g) {
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
+  if (g.method == 1) return launch_lbfgs(g, cus);
   if (g.g_bfgs == kWideLanes) return launch_bfgs_wide(g, cus);
   if (g.g_bfgs > kMaxNarrowDim) return hipErrorInvalidValue;
   const int64_t starts_per_block = (int64_t)(kBfgsBlock / g.g_bfgs);

@@ -15,6 +15,7 @@ struct ReqHot {
   int d, m;                  // dimension, number of terms
   int iter_bfgs, iter_ls, trace_len, ri;
   int stop_status;           // status at the iteration budget
+  int m_hist;                // L-BFGS pairs kept
   double armijo_c, tol, shrink;
 };
 constexpr int kHotDoubles = (sizeof(ReqHot) + 7) / 8;
@@ -57,6 +58,7 @@ __device__ __forceinline__ void load_hot(ReqHot &w, const ReqDev &rq, int ri) {
   w.m = Elem<OBJ>::terms(rq.d);
   w.iter_bfgs = rq.iter_bfgs;
   w.stop_status = rq.stop_status;
+  w.m_hist = rq.lbfgs_m;
   w.iter_ls = rq.iter_ls;
   w.trace_len = rq.trace ? rq.trace_len : 0;
   w.ri = ri;
@@ -65,4 +67,62 @@ __device__ __forceinline__ void load_hot(ReqHot &w, const ReqDev &rq, int ri) {
   w.shrink = rq.shrink;
 }
 
+
+// Line-search trials per round: R trials of G / R lanes each.
+template <int G>
+constexpr int kRound = G < 4 ? G : 4;
+
+// One Armijo search (Alg. 6) with the objective evaluated in number type U,
+// by a group of G lanes covering SLOTS term slots (SLOTS a multiple of G; the
+// point is xs + alpha ps, both in LDS and zero past the dimension).  A round
+// evaluates R consecutive trials of the sequence at once, each spread over
+// TP = G / R lanes holding B = SLOTS / TP consecutive term slots (zero past
+// the last term): a lane adds its slots pairwise and the trial's lanes finish
+// the pairwise sum with a butterfly.  The first trial that passes is the step
+// Alg. 6 returns.  Returns its index, or -1 when none of the iter_ls trials
+// passes.
+template <int OBJ, int G, int SLOTS, class U>
+__device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const double *xs,
+                                             const double *ps, const double *al, const ReqHot &q,
+                                             double f, double ddir) {
+  using E = Elem<OBJ>;
+  constexpr int R = kRound<G>, TP = G / R, B = SLOTS / TP;
+  constexpr uint64_t leaders = [] {  // bit r * TP for every trial r of a round
+    uint64_t b = 0;
+    for (int r = 0; r < R; ++r) b |= 1ull << (r * TP);
+    return b;
+  }();
+  const int trial_slot = L.j / TP, c = L.j % TP;
+  const int d = q.d, m = q.m;
+  for (int base = 0; base < q.iter_ls; base += R) {
+    const int t = base + trial_slot;
+    const double alpha = step_length(al, q.shrink, t);
+    U tv[E::K][B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int i = c * B + b;
+      U out[E::K];
+#pragma unroll
+      for (int kk = 0; kk < E::K; ++kk) out[kk] = U(0);
+      if (i < m) {
+        U w[E::W];
+#pragma unroll
+        for (int e = 0; e < E::W; ++e) w[e] = (U)(xs[i + e] + alpha * ps[i + e]);
+        E::template term<U>(w, out);
+      }
+#pragma unroll
+      for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = out[kk];
+    }
+    U sums[E::K];
+#pragma unroll
+    for (int kk = 0; kk < E::K; ++kk) sums[kk] = lane_tree_sum<TP, U>(reg_tree_sum<B, U>(tv[kk]));
+    const double ft = (double)E::template outer<U>(d, sums);
+    const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
+    const uint64_t hit = L.ballot(ok) & leaders;
+    if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1) / TP;
+  }
+  return -1;
+}
+
 }  // namespace zeus
+

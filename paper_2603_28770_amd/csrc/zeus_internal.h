@@ -19,6 +19,8 @@ constexpr int kMaxNarrowDim = 64;
 constexpr int kWideLanes = 256;
 // Most H slots (resident wide blocks) a launch group uses.
 constexpr int kWideMaxSlots = 2048;
+// Most (s, y) pairs an L-BFGS start keeps (in registers).
+constexpr int kLbfgsMaxHistory = 8;
 constexpr int kPsoBlock = 256;
 // Threads per swarm block (256 for every particle width: larger blocks lower
 // the number of resident blocks per CU more than they add groups).
@@ -63,6 +65,8 @@ struct ReqDev {
   int64_t n;                 // particles == starts
   int d, iter_pso, iter_bfgs, iter_ls, trace_len;
   int stop_status;           // status of a start that reaches iter_bfgs
+  int lbfgs_m;               // L-BFGS pairs kept (0: BFGS)
+  int pad0;
   double lo, hi, vh;         // box and velocity half-range
   double w, c1, c2;          // swarm coefficients
   double armijo_c, shrink, tol;
@@ -86,6 +90,7 @@ struct BatchDev {
 struct Group {
   int objective;
   int precision;
+  int method;                // 0: BFGS, 1: L-BFGS
   int g_pso, g_bfgs;         // lanes per particle / per start
   int nreq;
   int max_iter_pso;
@@ -112,6 +117,10 @@ hipError_t launch_pso(const Group &g, int t);
 hipError_t launch_pso_finish(const Group &g);
 hipError_t launch_bfgs(const Group &g);
 hipError_t launch_bfgs_wide(const Group &g, int cus);
+hipError_t launch_lbfgs(const Group &g, int cus);
+// Coordinate slots per L-BFGS start (power of two >= max(dim, 4); one
+// wavefront covers up to 256).
+int lbfgs_slots(int dim);
 hipError_t launch_summary(const Group &g);
 
 // Lanes per start of the BFGS kernels for a problem (power of two >= dim, at

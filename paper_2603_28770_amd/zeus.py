@@ -36,7 +36,7 @@ class zeus_problem(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("objective", C.c_int32), ("dim", C.c_int32),
                 ("precision", C.c_int32), ("n_starts", C.c_int64), ("lower", C.c_double),
                 ("upper", C.c_double), ("iter_pso", C.c_int32), ("iter_bfgs", C.c_int32),
-                ("iter_ls", C.c_int32), ("reserved0", C.c_int32), ("w", C.c_double),
+                ("iter_ls", C.c_int32), ("lbfgs_m", C.c_int32), ("w", C.c_double),
                 ("c1", C.c_double), ("c2", C.c_double), ("v_half", C.c_double),
                 ("armijo_c", C.c_double), ("ls_shrink", C.c_double), ("grad_tol", C.c_double),
                 ("required_converged", C.c_int64), ("seed", C.c_uint64),
@@ -128,7 +128,7 @@ def make_problem(p: dict) -> zeus_problem:
         abi_version=ABI_VERSION, objective=OBJECTIVES[p["objective"]], dim=int(p["dim"]),
         precision=PRECISIONS[p.get("precision", "fp64")], n_starts=int(p["n"]),
         lower=float(p["lower"]), upper=float(p["upper"]), iter_pso=int(p.get("iter_pso", 0)),
-        iter_bfgs=int(p.get("iter_bfgs", 100)), iter_ls=int(p.get("iter_ls", 20)), reserved0=0,
+        iter_bfgs=int(p.get("iter_bfgs", 100)), iter_ls=int(p.get("iter_ls", 20)), lbfgs_m=int(p.get("lbfgs_m", 0)),
         w=float(p.get("w", 0.5)), c1=float(p.get("c1", 1.2)), c2=float(p.get("c2", 1.5)),
         v_half=float(p.get("v_half", 0.0)), armijo_c=float(p.get("armijo_c", 0.3)),
         ls_shrink=float(p.get("ls_shrink", 0.5)), grad_tol=float(p.get("grad_tol", 1e-6)),

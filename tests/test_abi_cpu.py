@@ -79,13 +79,14 @@ def test_validation_rejects(Z, bad):
     assert Z.zeus_last_error() != ""
 
 
-def test_validation_abi_and_reserved(Z):
+def test_validation_abi_and_history(Z):
     pb = Z.make_problem(_p())
     pb.abi_version = 2
     assert Z.zeus_validate(pb) == Z.EINVAL
-    pb = Z.make_problem(_p())
-    pb.reserved0 = 1
-    assert Z.zeus_validate(pb) == Z.EINVAL
+    for m, code in ((-1, Z.EINVAL), (0, Z.OK), (1, Z.OK), (8, Z.OK), (9, Z.EUNSUPPORTED)):
+        pb = Z.make_problem(_p())
+        pb.lbfgs_m = m
+        assert Z.zeus_validate(pb) == code, m
     pb = Z.make_problem(_p())
     pb.objective = 99
     assert Z.zeus_validate(pb) == Z.EINVAL
