@@ -40,7 +40,8 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4
 WORKLOADS = {"rastrigin_d10_n65536": W.RASTRIGIN_D10, "rosenbrock_d2_n1024": W.ROSENBROCK_D2,
              "ackley_d50_n131072": W.ACKLEY_D50, "rosenbrock_d50_n131072": W.ROSENBROCK_D50,
              "styblinski_d128_n16384": W.STYBLINSKI_D128,
-             "rosenbrock_d128_n16384": W.ROSENBROCK_D128}
+             "rosenbrock_d128_n16384": W.ROSENBROCK_D128,
+             "rosenbrock_d200_n8192": W.ROSENBROCK_D200}
 
 
 # Per-evaluation flop counts of the objectives as the kernels evaluate them
@@ -67,7 +68,7 @@ def _counts(obj, d):
     raise KeyError(obj)
 
 
-def algorithmic_flops(obj, d, n_starts, total_iters, total_ls_trials):
+def algorithmic_flops(obj, d, n_starts, total_iters, total_ls_trials, lbfgs_m=0):
     """Flops the method needs for a whole BFGS phase:
       per start:            one forward-mode gradient (primal + shared + d tangents)
                             and the norm test (2d);
@@ -75,10 +76,14 @@ def algorithmic_flops(obj, d, n_starts, total_iters, total_ls_trials):
                             product, rank-2 update with u = H g_new + p),
                             one gradient, vector work 14 d (g'p, y's, y'u,
                             ||g||^2, x + alpha p, s, y);
-      per line-search trial: one primal evaluation and x + alpha p (2d)."""
+      per line-search trial: one primal evaluation and x + alpha p (2d).
+    With L-BFGS (m pairs) the inverse-Hessian work is the two-loop recursion,
+    2m dot products and 2m vector updates of 2d flops each plus the scaling
+    (3d): 8 m d + 3d."""
     fp, fs, ft = _counts(obj, d)
     grad = fp + fs + d * ft
-    per_iter = 6 * d * d + grad + 14 * d
+    h_work = 8 * lbfgs_m * d + 3 * d if lbfgs_m else 6 * d * d
+    per_iter = h_work + grad + 14 * d
     return n_starts * (grad + 2 * d) + total_iters * per_iter + total_ls_trials * (fp + 2 * d)
 
 
@@ -252,6 +257,8 @@ def main():
     ap.add_argument("--n-scale", type=float, default=0.0,
                     help="multi-request workloads: multiply every request's start count")
     ap.add_argument("--requests", type=int, default=0, help="served_mix: number of requests")
+    ap.add_argument("--lbfgs-m", type=int, default=0, metavar="M",
+                    help="solve the workload with L-BFGS keeping M pairs (default: BFGS)")
     ap.add_argument("--required-c", type=int, default=0, metavar="C",
                     help="also time the solve with early stop at C converged starts (the "
                          "paper's time-to-C-convergences metric; blocking entry point)")
@@ -289,6 +296,8 @@ def main():
         return
 
     p = WORKLOADS[args.workload]
+    if args.lbfgs_m:
+        p = dict(p, lbfgs_m=args.lbfgs_m)
     ctx = Z.zeus_context_create(0)
     stream = torch.cuda.Stream()   # the library's kernels and torch's events share it
     sptr = stream.cuda_stream
@@ -359,7 +368,8 @@ def main():
     value = iters / (ms_per_step / 1e3)
     conv_per_s = s["n_converged"] / (ms_per_step / 1e3)
     bfgs_ms = prof["bfgs_ms"] / max(1, prof["bfgs_launches"])
-    flops = algorithmic_flops(p["objective"], p["dim"], p["n"], iters, s["total_ls_trials"])
+    flops = algorithmic_flops(p["objective"], p["dim"], p["n"], iters, s["total_ls_trials"],
+                              p.get("lbfgs_m", 0))
     achieved = flops / (bfgs_ms * 1e-3) / 1e12
     fstar = W.f_star(p["objective"], p["dim"])
     line = {
@@ -369,7 +379,8 @@ def main():
         "data": "synthetic (seeded Philox starts in the box; analytic objective)",
         "config": {"workload": args.workload, "objective": p["objective"], "dim": p["dim"],
                    "n_starts": p["n"], "iter_pso": p["iter_pso"], "iter_bfgs": p["iter_bfgs"],
-                   "grad_tol": p["grad_tol"], "precision": p.get("precision", "fp64")},
+                   "grad_tol": p["grad_tol"], "precision": p.get("precision", "fp64"),
+                   "method": f"lbfgs_m{args.lbfgs_m}" if args.lbfgs_m else "bfgs"},
         "converged_starts_per_s": conv_per_s,
         "p50_solve_ms": float(np.percentile(lat, 50)), "p99_solve_ms": float(np.percentile(lat, 99)),
         "start_iters_per_step": iters, "ls_trials_per_iter": s["total_ls_trials"] / max(1, iters),

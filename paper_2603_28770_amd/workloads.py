@@ -72,6 +72,9 @@ STYBLINSKI_D128 = problem(name="styblinski_d128_n16384", objective="styblinski_t
 ROSENBROCK_D128 = problem(name="rosenbrock_d128_n16384", objective="rosenbrock", dim=128,
                           n=16384, lower=-5.0, upper=5.0, iter_pso=2, iter_bfgs=1000, seed=5)
 
+ROSENBROCK_D200 = problem(name="rosenbrock_d200_n8192", objective="rosenbrock", dim=200, n=8192,
+                          lower=-5.0, upper=5.0, iter_pso=2, iter_bfgs=2000, seed=5)
+
 BOXES = {"rosenbrock": (-5.0, 5.0), "ackley": (-5.0, 5.0), "styblinski_tang": (-5.0, 5.0),
          "rastrigin": (-5.12, 5.12)}
 MIX = ("rosenbrock", "rastrigin", "ackley", "styblinski_tang")
