@@ -61,6 +61,8 @@ def lib():
         L.zo_f.restype = C.c_double
         L.zo_f.argtypes = [C.c_int, C.c_void_p, C.c_int]
         L.zo_grad.argtypes = [C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p]
+        L.zo_hrow_dot.restype = C.c_double
+        L.zo_hrow_dot.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
         L.zo_bfgs_update.restype = C.c_int
         L.zo_bfgs_update.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.zo_lbfgs_direction.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
@@ -135,6 +137,14 @@ def lbfgs_direction(S, Y, rho, g):
     p = np.empty_like(g)
     lib().zo_lbfgs_direction(_ptr(S), _ptr(Y), _ptr(rho), int(rho.size), _ptr(g), g.size, _ptr(p))
     return p
+
+
+def hrow_dot(hrow, v):
+    """Row of H times v in the order of the BFGS matvecs (16-column fused
+    multiply-add chains, block sums added pairwise)."""
+    hrow = np.ascontiguousarray(hrow, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return float(lib().zo_hrow_dot(_ptr(hrow), _ptr(v), hrow.size))
 
 
 def bfgs_update(H, s, y):

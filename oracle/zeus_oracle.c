@@ -217,6 +217,31 @@ static double pw_dot(const double *a, const double *b, int n) {
   return pw_dot(a, b, h) + pw_dot(a + h, b + h, n - h);
 }
 
+/* Products of a row of the inverse Hessian with a vector (u = H y in the
+ * update, p = -H g for the direction; Alg. 4).  The paper fixes no order for
+ * these sums either.  The one chosen: the columns fall into blocks of
+ * ZO_HBLOCK consecutive columns (the last block may be shorter); each block's
+ * products are accumulated left to right by fused multiply-adds, starting
+ * from zero, and the block sums are added pairwise as above.  For
+ * dim <= ZO_HBLOCK this is one fused multiply-add chain over the row. */
+#define ZO_HBLOCK 16
+
+static double hrow_blocks(const double *h, const double *v, int d, int b0, int nb) {
+  if (nb == 1) {
+    int c1 = (b0 + 1) * ZO_HBLOCK < d ? (b0 + 1) * ZO_HBLOCK : d;
+    double acc = 0.0;
+    for (int c = b0 * ZO_HBLOCK; c < c1; ++c) acc = fma(h[c], v[c], acc);
+    return acc;
+  }
+  int hb = pw_split(nb);
+  return hrow_blocks(h, v, d, b0, hb) + hrow_blocks(h, v, d, b0 + hb, nb - hb);
+}
+
+double zo_hrow_dot(const double *hrow, const double *v, int d) {
+  if (d <= 0) return 0.0;
+  return hrow_blocks(hrow, v, d, 0, (d + ZO_HBLOCK - 1) / ZO_HBLOCK);
+}
+
 /* sum of the terms lo .. lo+n-1 of an objective, each term a dual number */
 typedef dual (*term_fn)(const dual *x, int i);
 static dual pw_terms(term_fn term, const dual *x, int lo, int n) {
@@ -520,11 +545,7 @@ int zo_bfgs_update(double *H, const double *s, const double *y, int d) {
   if (!(sy > 0.0)) return 0;
   double rho = 1.0 / sy;
   double *u = (double *)calloc((size_t)d, sizeof(double));
-  for (int i = 0; i < d; ++i) {
-    double acc = 0.0;
-    for (int j = 0; j < d; ++j) acc = fma(H[i * d + j], y[j], acc);
-    u[i] = acc;
-  }
+  for (int i = 0; i < d; ++i) u[i] = zo_hrow_dot(H + (size_t)i * d, y, d);
   double yu = pw_dot(y, u, d);
   double beta = (rho * rho) * yu + rho;
   /* row i: H_ij + a_i u_j + e_i s_j with a_i = -rho s_i and
@@ -614,16 +635,12 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
     if (gnorm < pb->grad_tol) { status = ZO_CONVERGED; break; }
     if (k == pb->iter_bfgs) { status = ZO_MAXITER; break; }
 
-    /* search direction p = -H g (products accumulated by fused multiply-add),
-     * or the L-BFGS two-loop recursion over the stored pairs */
+    /* search direction p = -H g (the row products of zo_hrow_dot), or the
+     * L-BFGS two-loop recursion over the stored pairs */
     if (lm > 0) {
       zo_lbfgs_direction(LS, LY, lrho, lcount, g, d, p);
     } else {
-      for (int i = 0; i < d; ++i) {
-        double acc = 0.0;
-        for (int j = 0; j < d; ++j) acc = fma(H[i * d + j], g[j], acc);
-        p[i] = -acc;
-      }
+      for (int i = 0; i < d; ++i) p[i] = -zo_hrow_dot(H + (size_t)i * d, g, d);
     }
     double ddir = pw_dot(g, p, d);
     {

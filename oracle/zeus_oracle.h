@@ -124,6 +124,11 @@ double zo_f(int objective, const double *x, int dim);
  * of the last pass (all passes have the same value part). */
 void zo_grad(int objective, const double *x, int dim, double *f, double *g);
 
+/* Row of the inverse Hessian times a vector, sum_c hrow[c] v[c] over
+ * c < dim: fused multiply-add chains over blocks of 16 consecutive columns,
+ * the block sums added pairwise (the order used for u = H y and p = -H g). */
+double zo_hrow_dot(const double *hrow, const double *v, int dim);
+
 /* One rank-2 inverse-Hessian update (Alg. 4), in place on H [dim][dim].
  * Returns 1 if applied, 0 if skipped because y's <= 0 (or NaN). */
 int zo_bfgs_update(double *H, const double *s, const double *y, int dim);
