@@ -34,16 +34,16 @@ namespace {
 struct GroupShm {
   double *xs;  // [G] iterate under evaluation (x, then x_new)
   double *ps;  // [G] search direction
-  double *vs;  // [G] operand of the next matrix-vector product (y, then g)
-  double *ss;  // [G] s = x_new - x
-  double *us;  // [G] u = H y
+  double *vs;  // operand of the next matrix-vector product (y, then g)
+  double *ss;  // s = x_new - x
+  double *us;  // u = H y  (vs, ss, us: tile_vec_len(G) doubles, padded layout)
   double *al;  // [kTabTrials] step lengths of the start's request
   ReqHot *q;   // the start's request
 };
 
 // Doubles per group slice.
 __device__ __host__ __forceinline__ constexpr int group_stride(int G) {
-  return 5 * G + kTabTrials + kHotDoubles;
+  return 2 * G + 3 * tile_vec_len(G) + kTabTrials + kHotDoubles;
 }
 
 // T = double: every step in FP64.
@@ -73,15 +73,16 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     double *base = smem + (size_t)((threadIdx.x >> 6) * S + L.grp) * group_stride(G);
     sh.xs = base;
     sh.ps = base + G;
+    constexpr int VL = tile_vec_len(G);
     sh.vs = base + 2 * G;
-    sh.ss = base + 3 * G;
-    sh.us = base + 4 * G;
-    sh.al = base + 5 * G;
+    sh.ss = sh.vs + VL;
+    sh.us = sh.ss + VL;
+    sh.al = sh.us + VL;
     sh.q = reinterpret_cast<ReqHot *>(sh.al + kTabTrials);
   }
 
   bool own = false;
-  double h[G];  // row j of H; h[c] = 0 for c >= d except h[j] = 1 when j >= d
+  Tile<G> H;  // this lane's tile of the inverse Hessian (identity in the padding)
   double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
   int64_t idx = -1;
   int k = 0, ls_trials = 0;
@@ -112,8 +113,7 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
       fill_step_lengths(sh.al, rq.shrink, j, G);
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
       sh.xs[j] = xj;
-#pragma unroll
-      for (int c = 0; c < G; ++c) h[c] = (c == j) ? 1.0 : 0.0;  // H <- I
+      H.identity(j);  // H <- I
       k = 0;
       ls_trials = 0;
       fresh = true;
@@ -136,25 +136,18 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
       const double sy = lane_tree_sum<G, double>(yj * sj);
       if (sy > 0.0) {  // curvature condition; skip the update otherwise
         const double rho = 1.0 / sy;
-        sh.vs[j] = yj;
+        sh.vs[vpos<G>(j)] = yj;
         wave_sync();
-        double uj = row_dot<G>(h, sh.vs);
+        double uj = H.matvec(sh.vs, j);  // every lane: the tile sums cross lanes
         uj = own ? uj : 0.0;
         const double yu = lane_tree_sum<G, double>(yj * uj);
-        sh.us[j] = uj;
-        sh.ss[j] = sj;
+        sh.us[vpos<G>(j)] = uj;
+        sh.ss[vpos<G>(j)] = sj;
         wave_sync();
         const double beta = (rho * rho) * yu + rho;
-        // H+ = H - rho (s u' + u s') + beta s s'   (row j, u = H y)
-        const double au = -rho * sj;
-        const double as = beta * sj - rho * uj;
-        row_rank2<G>(h, au, sh.us, as, sh.ss);
-        if (!__builtin_isfinite(au) || !__builtin_isfinite(as)) {
-          // inf * 0 would have reached the padding: restore it
-#pragma unroll
-          for (int c = 0; c < G; ++c)
-            if (c >= d) h[c] = (c == j) ? 1.0 : 0.0;
-        }
+        // H+ = H - rho (s u' + u s') + beta s s'   (u = H y); inf * 0 would
+        // have reached the padding when a coefficient is not finite
+        if (!H.rank2(rho, beta, sh.us, sh.ss, j, sj, uj)) H.restore_padding(j, d);
       }
       ++k;
     }
@@ -198,13 +191,13 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     }
 
     // -- search direction p = -H g (reset to -g if not a descent direction) -
-    sh.vs[j] = gj;
+    sh.vs[vpos<G>(j)] = gj;
     wave_sync();
-    pj = own ? -row_dot<G>(h, sh.vs) : 0.0;
+    const double hg = H.matvec(sh.vs, j);  // every lane: the tile sums cross lanes
+    pj = own ? -hg : 0.0;
     double ddir = lane_tree_sum<G, double>(gj * pj);
     if (!(ddir < 0.0)) {
-#pragma unroll
-      for (int c = 0; c < G; ++c) h[c] = (c == j) ? 1.0 : 0.0;
+      H.identity(j);
       pj = own ? -gj : 0.0;
       ddir = lane_tree_sum<G, double>(gj * pj);
     }

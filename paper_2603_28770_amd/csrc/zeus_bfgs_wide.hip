@@ -11,6 +11,9 @@
 //  * per iteration H is read once by u = H y and once more by the rank-2
 //    update, which writes the new rows and forms p = -H_new g_new from them in
 //    the same pass (the search direction needs no third pass);
+//  * a row's product with a vector is a fused multiply-add chain over each
+//    block of 16 consecutive columns, the block sums added pairwise (the
+//    order of the tile layout of the narrow kernel);
 //  * sums over coordinates and terms are the pairwise trees used everywhere:
 //    a butterfly inside each wavefront, then the four wavefront sums added
 //    pairwise through LDS;
@@ -168,6 +171,24 @@ __device__ __forceinline__ int wide_armijo(WideShm &sh, double f, double ddir, i
 // See the narrow kernel for the mixed-precision rules (T = float): FP32
 // evaluation with escalation to FP64 near the minimum, on a non-finite value
 // or on a failed FP32 line search; H, s, y, p, g'p and Armijo stay FP64.
+//
+// Row products: blocks of kHBlock columns, block sums over a zero-padded tree.
+constexpr int kHBlock = 16;
+constexpr int kHBlocks = kMaxDim / kHBlock;
+
+// sum_c H(j, c) v[c] for the column-major row starting at hc
+__device__ __forceinline__ double slot_row_dot(const double *hc, int64_t cs, const double *v, int d) {
+  double part[kHBlocks];
+#pragma unroll
+  for (int b = 0; b < kHBlocks; ++b) {
+    double acc = 0.0;
+    const int c1 = min(d, (b + 1) * kHBlock);
+#pragma unroll 8
+    for (int c = b * kHBlock; c < c1; ++c) acc = __builtin_fma(hc[(int64_t)c * cs], v[c], acc);
+    part[b] = acc;
+  }
+  return reg_tree_sum<kHBlocks, double>(part);
+}
 template <int OBJ, class T>
 __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, int nreq,
                                                           BatchDev *hdr, int64_t total,
@@ -231,12 +252,7 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
         sh.vs[j] = yj;
         sh.gs[j] = gn;
         __syncthreads();
-        double uj = 0.0;
-        if (own) {
-          const double *hc = H + j;
-#pragma unroll 8
-          for (int c = 0; c < d; ++c) uj = __builtin_fma(hc[(int64_t)c * cs], sh.vs[c], uj);
-        }
+        const double uj = own ? slot_row_dot(H + j, cs, sh.vs, d) : 0.0;
         const double yu = block_tree_sum(yj * uj, sh, phase);
         sh.us[j] = uj;
         sh.ss[j] = sj;
@@ -245,17 +261,26 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
         const double au = -rho * sj;
         const double as = beta * sj - rho * uj;
         // H+ = H - rho (s u' + u s') + beta s s'   (row j), then p_j = -(H+ g)_j
-        double acc = 0.0;
+        double part[kHBlocks];
+#pragma unroll
+        for (int b = 0; b < kHBlocks; ++b) part[b] = 0.0;
         if (own) {
           double *hc = H + j;
+#pragma unroll
+          for (int b = 0; b < kHBlocks; ++b) {
+            double acc = 0.0;
+            const int c1 = min(d, (b + 1) * kHBlock);
 #pragma unroll 8
-          for (int c = 0; c < d; ++c) {
-            const double hn = __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], hc[(int64_t)c * cs]));
-            hc[(int64_t)c * cs] = hn;
-            acc = __builtin_fma(hn, sh.gs[c], acc);
+            for (int c = b * kHBlock; c < c1; ++c) {
+              const double hn =
+                  __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], hc[(int64_t)c * cs]));
+              hc[(int64_t)c * cs] = hn;
+              acc = __builtin_fma(hn, sh.gs[c], acc);
+            }
+            part[b] = acc;
           }
         }
-        pj = own ? -acc : 0.0;
+        pj = own ? -reg_tree_sum<kHBlocks, double>(part) : 0.0;
         have_p = true;
       }
       ++k;
@@ -302,13 +327,7 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
     if (!have_p) {
       sh.gs[j] = gj;
       __syncthreads();
-      double acc = 0.0;
-      if (own) {
-        const double *hc = H + j;
-#pragma unroll 8
-        for (int c = 0; c < d; ++c) acc = __builtin_fma(hc[(int64_t)c * cs], sh.gs[c], acc);
-      }
-      pj = own ? -acc : 0.0;
+      pj = own ? -slot_row_dot(H + j, cs, sh.gs, d) : 0.0;
     }
     double ddir = block_tree_sum(gj * pj, sh, phase);
     if (!(ddir < 0.0)) {  // not a descent direction: H <- I, p = -g

@@ -45,8 +45,9 @@ struct GroupLanes {
 // addition is commutative, so both partners get the same bits and after
 // log2(N) levels every lane of an aligned N-lane block holds the block's sum.
 // The first four levels use DPP lane permutations (quad_perm, row_half_mirror,
-// row_mirror) that stay inside rows of 16 lanes; the last two go through
-// ds_bpermute.  Callers must have every lane of the block active.
+// row_mirror) that stay inside rows of 16 lanes; the last two use the gfx950
+// lane swaps between the halves of 32- and 64-lane blocks (no LDS round
+// trip).  Callers must have every lane of the block active.
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v) {
@@ -67,6 +68,41 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm(2,3,0,1)
 constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within 8
 constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within 16
 
+// Sum across the two halves of every aligned block of 2 * HALF lanes
+// (HALF = 16 or 32), from two values per lane: a lane in a lower half returns
+// its own a plus the a of the lane HALF above it, a lane in an upper half the
+// b of the lane HALF below it plus its own b.  v_permlane{16,32}_swap moves
+// the upper half of its first operand into the lower half of its second and
+// back, so the two results of a swap of (a, b) hold exactly those operands.
+template <int HALF>
+__device__ __forceinline__ void lane_swap(uint32_t &x, uint32_t &y) {
+  static_assert(HALF == 16 || HALF == 32, "HALF must be 16 or 32");
+  if constexpr (HALF == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  }
+}
+template <int HALF>
+__device__ __forceinline__ float half_pair_sum(float a, float b) {
+  uint32_t x = __builtin_bit_cast(uint32_t, a), y = __builtin_bit_cast(uint32_t, b);
+  lane_swap<HALF>(x, y);
+  return __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
+}
+template <int HALF>
+__device__ __forceinline__ double half_pair_sum(double a, double b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  uint32_t xl = (uint32_t)ua, yl = (uint32_t)ub, xh = (uint32_t)(ua >> 32), yh = (uint32_t)(ub >> 32);
+  lane_swap<HALF>(xl, yl);
+  lane_swap<HALF>(xh, yh);
+  return __builtin_bit_cast(double, ((uint64_t)xh << 32) | xl) +
+         __builtin_bit_cast(double, ((uint64_t)yh << 32) | yl);
+}
+
 template <int N, class T>
 __device__ __forceinline__ T lane_tree_sum(T v) {
   static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two <= 64");
@@ -74,8 +110,8 @@ __device__ __forceinline__ T lane_tree_sum(T v) {
   if constexpr (N >= 4) v = v + dpp_move<kDppXor2>(v);
   if constexpr (N >= 8) v = v + dpp_move<kDppHalfMirror>(v);
   if constexpr (N >= 16) v = v + dpp_move<kDppMirror>(v);
-  if constexpr (N >= 32) v = v + __shfl_xor(v, 16, 64);
-  if constexpr (N >= 64) v = v + __shfl_xor(v, 32, 64);
+  if constexpr (N >= 32) v = half_pair_sum<16>(v, v);
+  if constexpr (N >= 64) v = half_pair_sum<32>(v, v);
   return v;
 }
 
@@ -90,56 +126,141 @@ __device__ __forceinline__ T reg_tree_sum(const T *v) {
 }
 
 // ---------------------------------------------------------------------------
-// Row j of H against vectors that every lane reads from the group's LDS.  The
-// vectors are read in chunks, the next chunk's loads written before the
-// current chunk's arithmetic, so that the scheduler issues them early and a
-// wave waits for LDS about once per chunk instead of once per pair of
-// elements.
+// The inverse Hessian of a start, G x G (zero-padded past the dimension, with
+// ones on the padded diagonal), spread over the G lanes of its group in
+// tiles: with C = min(G, 16) columns and R = G / C rows per tile, lane j
+// holds rows (j mod C) + C t, t < R, at columns C * (j / C) + k, k < C.  For
+// G <= 16 that is row j whole.
+//
+// A row's product with a vector is a fused multiply-add chain over each block
+// of 16 consecutive columns, the block sums added pairwise.  In the tile
+// layout a lane forms one chain for each of its R rows, and the R = 2 or 4
+// blocks of a row meet in one or two lane-swap levels (16 lanes apart, then
+// 32): level one adds blocks (0, 1) and (2, 3), level two their sums, which
+// is the pairwise tree; each level also halves the rows a lane carries, so
+// that lane j ends with row j.
+//
+// The vectors the tiles read (y or g, u, s) sit in the group's LDS with two
+// doubles of padding after every 16, so that the four column blocks read by
+// one instruction fall in different banks.
 // ---------------------------------------------------------------------------
-template <int G>
-constexpr int kRowChunk = G < 16 ? G : 16;
-
+// LDS operands are read in chunks, the next chunk's loads written before the
+// current chunk's arithmetic, so that the scheduler issues them early and a
+// wave waits for LDS about once per chunk.
 template <int N>
 __device__ __forceinline__ void lds_load(double (&b)[N], const double *v) {
 #pragma unroll
   for (int c = 0; c < N; ++c) b[c] = v[c];
 }
 
-// sum_c h[c] v[c] as one fused multiply-add chain in column order.
 template <int G>
-__device__ __forceinline__ double row_dot(const double (&h)[G], const double *v) {
-  constexpr int CH = kRowChunk<G>, NC = G / CH;
-  double buf[2][CH];
-  lds_load(buf[0], v);
-  double acc = 0.0;
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    if (k + 1 < NC) lds_load(buf[(k + 1) & 1], v + (k + 1) * CH);
-#pragma unroll
-    for (int c = 0; c < CH; ++c) acc = __builtin_fma(h[k * CH + c], buf[k & 1][c], acc);
-  }
-  return acc;
+constexpr int kTileCols = G < 16 ? G : 16;
+template <int G>
+constexpr int kTileRows = G / kTileCols<G>;
+// doubles of a padded tile operand vector
+__host__ __device__ constexpr int tile_vec_len(int G) { return G <= 16 ? G : G + 2 * (G / 16); }
+
+// LDS position of coordinate c in a tile operand vector
+template <int G>
+__device__ __forceinline__ int vpos(int c) {
+  return G <= 16 ? c : c + 2 * (c >> 4);
 }
 
-// h[c] <- fma(as, s[c], fma(au, u[c], h[c])) for every column c.
 template <int G>
-__device__ __forceinline__ void row_rank2(double (&h)[G], double au, const double *u, double as,
-                                          const double *s) {
-  constexpr int CH = kRowChunk<G> / 2 > 0 ? kRowChunk<G> / 2 : 1, NC = G / CH;
-  double bu[2][CH], bs[2][CH];
-  lds_load(bu[0], u);
-  lds_load(bs[0], s);
+struct Tile {
+  double h[kTileRows<G> * kTileCols<G>];  // h[t * C + k] = H(row(t), col(k))
+  static constexpr int C = kTileCols<G>, R = kTileRows<G>;
+  __device__ __forceinline__ static int row(int j, int t) { return (j % C) + C * t; }
+  __device__ __forceinline__ static int col(int j, int k) { return C * (j / C) + k; }
+
+  __device__ __forceinline__ void identity(int j) {
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    if (k + 1 < NC) {
-      lds_load(bu[(k + 1) & 1], u + (k + 1) * CH);
-      lds_load(bs[(k + 1) & 1], s + (k + 1) * CH);
-    }
+    for (int t = 0; t < R; ++t)
 #pragma unroll
-    for (int c = 0; c < CH; ++c)
-      h[k * CH + c] = __builtin_fma(as, bs[k & 1][c], __builtin_fma(au, bu[k & 1][c], h[k * CH + c]));
+      for (int k = 0; k < C; ++k) h[t * C + k] = row(j, t) == col(j, k) ? 1.0 : 0.0;
   }
-}
+
+  // Puts the padding (row or column >= d) back to the identity's.
+  __device__ __forceinline__ void restore_padding(int j, int d) {
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+#pragma unroll
+      for (int k = 0; k < C; ++k)
+        if (row(j, t) >= d || col(j, k) >= d) h[t * C + k] = row(j, t) == col(j, k) ? 1.0 : 0.0;
+  }
+
+  // (H v)_j for lane j; v in the padded layout (vpos).  For G > 16 the rows
+  // are finished across lanes, so every lane of the group must call it (not
+  // under a condition that differs between the group's lanes).
+  __device__ __forceinline__ double matvec(const double *v, int j) const {
+    constexpr int CH = R == 1 ? C : 8, NC = C / CH;
+    const double *vb = v + vpos<G>(col(j, 0));
+    double buf[2][CH];
+    double part[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) part[t] = 0.0;
+    lds_load(buf[0], vb);
+#pragma unroll
+    for (int kc = 0; kc < NC; ++kc) {
+      if (kc + 1 < NC) lds_load(buf[(kc + 1) & 1], vb + (kc + 1) * CH);
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+          part[t] = __builtin_fma(h[t * C + kc * CH + c], buf[kc & 1][c], part[t]);
+    }
+    if constexpr (R == 1) {
+      return part[0];
+    } else if constexpr (R == 2) {
+      return half_pair_sum<16>(part[0], part[1]);
+    } else {
+      static_assert(R == 4, "tiles have 1, 2 or 4 rows");
+      const double q0 = half_pair_sum<16>(part[0], part[1]);
+      const double q1 = half_pair_sum<16>(part[2], part[3]);
+      return half_pair_sum<32>(q0, q1);
+    }
+  }
+
+  // H <- H - rho (s u' + u s') + beta s s', element (r, c) by
+  // fma(e_r, s_c, fma(a_r, u_c, H_rc)) with a_r = -rho s_r and
+  // e_r = beta s_r - rho u_r; u and s in the padded layout, sj and uj this
+  // lane's own entries.  Returns false when some a_r or e_r is not finite
+  // (then the padding must be restored).
+  __device__ __forceinline__ bool rank2(double rho, double beta, const double *us, const double *ss,
+                                        int j, double sj, double uj) {
+    double a[R], e[R];
+    bool fin = true;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const double sr = R == 1 ? sj : ss[vpos<G>(row(j, t))];
+      const double ur = R == 1 ? uj : us[vpos<G>(row(j, t))];
+      a[t] = -rho * sr;
+      e[t] = beta * sr - rho * ur;
+      fin = fin && __builtin_isfinite(a[t]) && __builtin_isfinite(e[t]);
+    }
+    constexpr int CH = R == 1 ? (C > 1 ? C / 2 : 1) : 4, NC = C / CH;
+    const double *ub = us + vpos<G>(col(j, 0));
+    const double *sb = ss + vpos<G>(col(j, 0));
+    double bu[2][CH], bs[2][CH];
+    lds_load(bu[0], ub);
+    lds_load(bs[0], sb);
+#pragma unroll
+    for (int kc = 0; kc < NC; ++kc) {
+      if (kc + 1 < NC) {
+        lds_load(bu[(kc + 1) & 1], ub + (kc + 1) * CH);
+        lds_load(bs[(kc + 1) & 1], sb + (kc + 1) * CH);
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          double &x = h[t * C + kc * CH + c];
+          x = __builtin_fma(e[t], bs[kc & 1][c], __builtin_fma(a[t], bu[kc & 1][c], x));
+        }
+    }
+    return fin;
+  }
+};
 
 // Value of the objective at the point whose coordinates are xs[0..d-1] in the
 // group's LDS, evaluated in number type T.  The group covers G * CPL term
