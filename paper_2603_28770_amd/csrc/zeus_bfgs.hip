@@ -130,10 +130,14 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     else
       fn = group_value_grad<OBJ, G, T>(L, d, sh.xs, &gn);
 
+    // y's and g'g are formed together (independent butterflies overlap);
+    // right after a claim or an escalation y's is not used
+    const double yj = gn - gj;  // zero beyond the dimension
+    const double sy = lane_tree_sum<G, double>(yj * sj);
+    const double gg = lane_tree_sum<G, double>(gn * gn);
+
     // -- after a step: y and the rank-2 inverse-Hessian update --------------
     if (!fresh) {
-      const double yj = gn - gj;  // zero beyond the dimension
-      const double sy = lane_tree_sum<G, double>(yj * sj);
       if (sy > 0.0) {  // curvature condition; skip the update otherwise
         const double rho = 1.0 / sy;
         sh.vs[vpos<G>(j)] = yj;
@@ -159,7 +163,6 @@ __global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, in
     // -- termination: non-finite, ||g|| < Theta, budget ---------------------
     const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
     const bool any_bad = L.ballot(bad) != 0ull;
-    const double gg = lane_tree_sum<G, double>(gj * gj);
     if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * q.tol)) {
       hi = true;  // escalate: re-evaluate this point in FP64
       fresh = true;

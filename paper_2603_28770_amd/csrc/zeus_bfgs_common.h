@@ -97,21 +97,22 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const doubl
   for (int base = 0; base < q.iter_ls; base += R) {
     const int t = base + trial_slot;
     const double alpha = step_length(al, q.shrink, t);
+    // every slot is evaluated (indices clamped into the vectors) and the
+    // slots past the last term are replaced by zero afterwards: no branch
+    // per slot, so the loads of all slots are in flight together
     U tv[E::K][B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int i = c * B + b;
-      U out[E::K];
+      U w[E::W], out[E::K];
 #pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) out[kk] = U(0);
-      if (i < m) {
-        U w[E::W];
-#pragma unroll
-        for (int e = 0; e < E::W; ++e) w[e] = (U)(xs[i + e] + alpha * ps[i + e]);
-        E::template term<U>(w, out);
+      for (int e = 0; e < E::W; ++e) {
+        const int ie = i + e < SLOTS ? i + e : SLOTS - 1;
+        w[e] = (U)(xs[ie] + alpha * ps[ie]);
       }
+      E::template term<U>(w, out);
 #pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = out[kk];
+      for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = i < m ? out[kk] : U(0);
     }
     U sums[E::K];
 #pragma unroll

@@ -277,17 +277,13 @@ __device__ __forceinline__ double group_value_slots(const GroupLanes<G> &L, int 
 #pragma unroll
   for (int r = 0; r < CPL; ++r) {
     const int i = L.j + G * r;
-    T out[E::K];
+    // evaluated on every slot (index clamped), zero past the last term
+    T w[E::W], out[E::K];
 #pragma unroll
-    for (int k = 0; k < E::K; ++k) out[k] = T(0);
-    if (i < m) {
-      T w[E::W];
+    for (int q = 0; q < E::W; ++q) w[q] = (T)xs[i + q < G * CPL ? i + q : G * CPL - 1];
+    E::template term<T>(w, out);
 #pragma unroll
-      for (int q = 0; q < E::W; ++q) w[q] = (T)xs[i + q];
-      E::template term<T>(w, out);
-    }
-#pragma unroll
-    for (int k = 0; k < E::K; ++k) blk[k][r] = lane_tree_sum<G, T>(out[k]);
+    for (int k = 0; k < E::K; ++k) blk[k][r] = lane_tree_sum<G, T>(i < m ? out[k] : T(0));
   }
   T s[E::K];
 #pragma unroll
@@ -320,22 +316,26 @@ __device__ __forceinline__ double group_value_grad(const GroupLanes<G> &L, int d
     tan[k] = T(0);
     val[k] = T(0);
   }
-  if (j < d) {
+  // Both window positions are evaluated on every lane (indices clamped into
+  // the vector) and a term that does not exist contributes an exact zero
+  // afterwards, so the loads are not behind branches.
 #pragma unroll
-    for (int back = E::W - 1; back >= 0; --back) {
-      const int i = j - back;  // term i holds x_j at window slot `back`
-      if (i >= 0 && i < m) {
-        dual<T> w[E::W], out[E::K];
+  for (int back = E::W - 1; back >= 0; --back) {
+    const int i = j - back;  // term i holds x_j at window slot `back`
+    const bool valid = j < d && i >= 0 && i < m;
+    dual<T> w[E::W], out[E::K];
 #pragma unroll
-        for (int q = 0; q < E::W; ++q) w[q] = dual<T>{(T)xs[i + q], q == back ? T(1) : T(0)};
-        E::template term<dual<T>>(w, out);
-#pragma unroll
-        for (int k = 0; k < E::K; ++k) tan[k] = tan[k] + out[k].t;
-        if (back == 0)
-#pragma unroll
-          for (int k = 0; k < E::K; ++k) val[k] = out[k].v;
-      }
+    for (int q = 0; q < E::W; ++q) {
+      int iq = i + q < 0 ? 0 : i + q;
+      iq = iq < G ? iq : G - 1;
+      w[q] = dual<T>{(T)xs[iq], q == back ? T(1) : T(0)};
     }
+    E::template term<dual<T>>(w, out);
+#pragma unroll
+    for (int k = 0; k < E::K; ++k) tan[k] = tan[k] + (valid ? out[k].t : T(0));
+    if (back == 0)
+#pragma unroll
+      for (int k = 0; k < E::K; ++k) val[k] = valid ? out[k].v : T(0);
   }
   dual<T> sd[E::K];
 #pragma unroll

@@ -53,22 +53,25 @@ __device__ __forceinline__ double value_grad_slots(const GroupLanes<G> &L, int d
       tan[k][c] = T(0);
       val[k][c] = T(0);
     }
-    if (jj < d) {
+    // evaluated on every lane (indices clamped), a missing term contributing
+    // an exact zero, so the loads are not behind branches
 #pragma unroll
-      for (int back = E::W - 1; back >= 0; --back) {
-        const int i = jj - back;
-        if (i >= 0 && i < m) {
-          dual<T> w[E::W], out[E::K];
+    for (int back = E::W - 1; back >= 0; --back) {
+      const int i = jj - back;
+      const bool valid = jj < d && i >= 0 && i < m;
+      dual<T> w[E::W], out[E::K];
 #pragma unroll
-          for (int q = 0; q < E::W; ++q) w[q] = dual<T>{(T)xs[i + q], q == back ? T(1) : T(0)};
-          E::template term<dual<T>>(w, out);
-#pragma unroll
-          for (int k = 0; k < E::K; ++k) tan[k][c] = tan[k][c] + out[k].t;
-          if (back == 0)
-#pragma unroll
-            for (int k = 0; k < E::K; ++k) val[k][c] = out[k].v;
-        }
+      for (int q = 0; q < E::W; ++q) {
+        int iq = i + q < 0 ? 0 : i + q;
+        iq = iq < G * CPL ? iq : G * CPL - 1;
+        w[q] = dual<T>{(T)xs[iq], q == back ? T(1) : T(0)};
       }
+      E::template term<dual<T>>(w, out);
+#pragma unroll
+      for (int k = 0; k < E::K; ++k) tan[k][c] = tan[k][c] + (valid ? out[k].t : T(0));
+      if (back == 0)
+#pragma unroll
+        for (int k = 0; k < E::K; ++k) val[k][c] = valid ? out[k].v : T(0);
     }
   }
   T sv[E::K];
