@@ -173,7 +173,17 @@ struct Tile {
   __device__ __forceinline__ static int row(int j, int t) { return (j % C) + C * t; }
   __device__ __forceinline__ static int col(int j, int k) { return C * (j / C) + k; }
 
+  // The identity pattern depends on the lane only; an opaque copy of the
+  // lane index keeps the compiler from hoisting the G comparisons out of the
+  // start loop and holding them in registers for the whole kernel (they are
+  // needed once per start).
+  __device__ __forceinline__ static int opaque(int j) {
+    asm volatile("" : "+v"(j));
+    return j;
+  }
+
   __device__ __forceinline__ void identity(int j) {
+    j = opaque(j);
 #pragma unroll
     for (int t = 0; t < R; ++t)
 #pragma unroll
@@ -182,6 +192,7 @@ struct Tile {
 
   // Puts the padding (row or column >= d) back to the identity's.
   __device__ __forceinline__ void restore_padding(int j, int d) {
+    j = opaque(j);
 #pragma unroll
     for (int t = 0; t < R; ++t)
 #pragma unroll
