@@ -84,22 +84,47 @@ __device__ void block_argmin(double &key, int64_t &idx, double &val, int64_t &au
 // of that sweep and the global best after sweep done-1.  Leaves its position
 // in gx_sh[0..d) for every thread of the block.  When `publish`, the result is
 // also stored for later launches (and in final_best / final_gx if given).
+//
+// It is split in two so that a caller can issue the loads of the block
+// results (stage_two_load) and do unrelated work while they are in flight.
 template <int NT>
-__device__ void global_best_after(const ReqDev &a, int done, double *gx_sh, bool publish,
-                                  PsoBest *final_best, double *final_gx) {
-  const int P = a.ws.pso_blocks, d = a.d, slot = done & 1;
-  double key = __builtin_huge_val(), val = __builtin_nan("");
-  int64_t idx = INT64_MAX, blk = 0;
-  for (int b = threadIdx.x; b < P; b += NT) {
-    const double kb = a.ws.part_key[slot * P + b];
-    const int64_t ib = a.ws.part_idx[slot * P + b];
-    if (key_less(kb, ib, key, idx)) {
-      key = kb;
-      idx = ib;
-      val = a.ws.part_f[slot * P + b];
-      blk = b;
+struct StageTwo {
+  static constexpr int kPer = (kPsoMaxBlocks + NT - 1) / NT;  // block results per thread
+  double kb[kPer], fb[kPer];
+  int64_t ib[kPer];
+};
+
+template <int NT>
+__device__ __forceinline__ void stage_two_load(const ReqDev &a, int done, StageTwo<NT> &s) {
+  const int P = a.ws.pso_blocks, slot = done & 1;
+#pragma unroll
+  for (int r = 0; r < StageTwo<NT>::kPer; ++r) {
+    const int b = threadIdx.x + r * NT;
+    s.kb[r] = __builtin_huge_val();
+    s.ib[r] = INT64_MAX;
+    s.fb[r] = __builtin_nan("");
+    if (b < P) {
+      s.kb[r] = a.ws.part_key[slot * P + b];
+      s.ib[r] = a.ws.part_idx[slot * P + b];
+      s.fb[r] = a.ws.part_f[slot * P + b];
     }
   }
+}
+
+template <int NT>
+__device__ void global_best_after(const ReqDev &a, int done, double *gx_sh, bool publish,
+                                  PsoBest *final_best, double *final_gx, const StageTwo<NT> &s) {
+  const int d = a.d, slot = done & 1, P = a.ws.pso_blocks;
+  double key = __builtin_huge_val(), val = __builtin_nan("");
+  int64_t idx = INT64_MAX, blk = 0;
+#pragma unroll
+  for (int r = 0; r < StageTwo<NT>::kPer; ++r)
+    if (key_less(s.kb[r], s.ib[r], key, idx)) {
+      key = s.kb[r];
+      idx = s.ib[r];
+      val = s.fb[r];
+      blk = threadIdx.x + r * NT;
+    }
   block_argmin<NT>(key, idx, val, blk);
   bool take = true;
   PsoBest prev{0.0, 0};
@@ -148,24 +173,15 @@ __global__ __launch_bounds__(pso_threads(G * CPL)) void pso_kernel(const ReqDev 
   const int d = a.d, j = L.j, P = a.ws.pso_blocks;
   const int nb = (d + 3) >> 2;  // Philox blocks per stream
 
-  if (t > 0) global_best_after<NT>(a, t - 1, gx_sh, blk == 0, nullptr, nullptr);
-  double gxj[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) gxj[c] = (t > 0 && j + G * c < d) ? gx_sh[j + G * c] : 0.0;
-
-  // this block's best particle of the sweep, tracked by each group's lane 0
-  double key = __builtin_huge_val(), val = __builtin_nan("");
-  int64_t idx = INT64_MAX, unused = 0;
   const uint64_t tag_a = t == 0 ? kTagX0 : kTagR1, tag_b = t == 0 ? kTagV0 : kTagR2;
   const int64_t stride = (int64_t)P * kGroups;
   const int64_t first = (int64_t)blk * kGroups + gib;
   // particles per batch: as many as fit their Philox blocks into G lanes
   const int pb = kBatch == 1 ? 1 : (G / (2 * nb) < 1 ? 1 : (G / (2 * nb) > kBatch ? kBatch : G / (2 * nb)));
-  for (int64_t k0 = 0;; k0 += pb) {
-    if (__ballot(first + k0 * stride < a.n) == 0ull) break;  // the whole wave is past the end
-    // Philox blocks b = j, j + G, ... below pb 2 nb: particle b / (2 nb) of
-    // the batch, block (b mod 2 nb) mod nb of stream a (first nb) or b
-    wave_sync();  // the previous batch's uniforms have been read
+  // Philox blocks b = j, j + G, ... below pb 2 nb of the batch starting at
+  // particle k0: particle b / (2 nb) of the batch, block (b mod 2 nb) mod nb
+  // of stream a (the first nb) or stream b
+  auto draw = [&](int64_t k0) {
     for (int b = j; b < pb * 2 * nb; b += G) {
       const int pp = b / (2 * nb), bb = b - pp * 2 * nb;
       const int64_t ip = first + (k0 + pp) * stride;
@@ -175,6 +191,26 @@ __global__ __launch_bounds__(pso_threads(G * CPL)) void pso_kernel(const ReqDev 
                                      a.k0, a.k1);
 #pragma unroll
       for (int q = 0; q < 4; ++q) uw_all[gib][pp][sb][jb * 4 + q] = u01(rw.w[q]);
+    }
+  };
+
+  // stage (2), its loads in flight while the first batch is drawn
+  StageTwo<NT> s2;
+  if (t > 0) stage_two_load<NT>(a, t - 1, s2);
+  draw(0);
+  if (t > 0) global_best_after<NT>(a, t - 1, gx_sh, blk == 0, nullptr, nullptr, s2);
+  double gxj[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) gxj[c] = (t > 0 && j + G * c < d) ? gx_sh[j + G * c] : 0.0;
+
+  // this block's best particle of the sweep, tracked by each group's lane 0
+  double key = __builtin_huge_val(), val = __builtin_nan("");
+  int64_t idx = INT64_MAX, unused = 0;
+  for (int64_t k0 = 0;; k0 += pb) {
+    if (__ballot(first + k0 * stride < a.n) == 0ull) break;  // the whole wave is past the end
+    if (k0 > 0) {
+      wave_sync();  // the previous batch's uniforms have been read
+      draw(k0);
     }
     wave_sync();
     for (int pp = 0; pp < pb; ++pp) {
@@ -256,7 +292,9 @@ __global__ __launch_bounds__(pso_threads(G * CPL)) void pso_kernel(const ReqDev 
 __global__ __launch_bounds__(kPsoBlock) void pso_finish_kernel(const ReqDev *reqs) {
   __shared__ double gx_sh[kMaxDim];
   const ReqDev &a = reqs[blockIdx.x];
-  global_best_after<kPsoBlock>(a, a.iter_pso, gx_sh, true, a.ws.best, a.ws.gx);
+  StageTwo<kPsoBlock> s2;
+  stage_two_load<kPsoBlock>(a, a.iter_pso, s2);
+  global_best_after<kPsoBlock>(a, a.iter_pso, gx_sh, true, a.ws.best, a.ws.gx, s2);
 }
 
 __global__ void ws_init_kernel(BatchDev *hdr) {
