@@ -59,8 +59,18 @@ __device__ __host__ __forceinline__ constexpr int group_stride(int G) {
 //
 // Every reduction below runs with all lanes of the group active: the control
 // flow splits only on values the whole group shares.
+// Waves per SIMD the register allocation must allow.  Left to itself the
+// compiler keeps the 64-lane kernels of the transcendental objectives at one
+// wave (256 VGPRs plus AGPRs); asking for two costs a few dozen spilled
+// registers but hides far more latency (Ackley d = 50: 1.5x faster), and
+// three waves help Rastrigin's 16-lane kernel the same way.  Other kernels
+// reach their occupancy without the request.
+template <int OBJ, int G>
+constexpr int kBfgsWaves = G == 64 ? 2 : (G == 16 && OBJ == kRastrigin) ? 3 : 1;
+
 template <int OBJ, int G, class T>
-__global__ __launch_bounds__(kBfgsBlock) void bfgs_kernel(const ReqDev *reqs, int nreq,
+__global__ __launch_bounds__(kBfgsBlock) __attribute__((amdgpu_waves_per_eu(kBfgsWaves<OBJ, G>)))
+void bfgs_kernel(const ReqDev *reqs, int nreq,
                                                           BatchDev *hdr, int64_t total) {
   using E = Elem<OBJ>;
   constexpr bool kMixed = sizeof(T) != sizeof(double);
