@@ -30,7 +30,7 @@ constexpr int kBfgsBlock = 256;
 // Most blocks a swarm launch gives one request (the blocks stride over its
 // particles; each re-reduces the previous launch's block results, so this
 // stays small).
-constexpr int kPsoMaxBlocks = 512;
+constexpr int kPsoMaxBlocks = 1024;
 
 // A swarm best, kept on the device.
 struct PsoBest {

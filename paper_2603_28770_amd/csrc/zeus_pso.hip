@@ -5,7 +5,7 @@
 // coordinate j (consecutive lanes touch consecutive addresses), the group
 // evaluates the objective term-parallel and keeps the personal best.
 // A launch serves a table of requests (one request, or a bucket of a batch);
-// each request owns P = min(#particle groups, 512) consecutive blocks that
+// each request owns P = min(#particle groups, 1024) consecutive blocks that
 // stride over its particles.
 //
 // Global best.  The paper's kernels take it with an atomicMin on the value and

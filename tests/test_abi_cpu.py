@@ -103,8 +103,8 @@ def test_workspace_bytes(Z):
     b = Z.zeus_workspace_bytes(pb)
     n, d = 65536, 10
     # swarm state x, v, px, pf plus the double-buffered block results of at
-    # most 512 blocks (value, key, index and a position each)
-    assert 3 * 8 * n * d + 8 * n <= b <= 3 * 8 * n * d + 8 * n + 2 * 512 * (d + 3) * 8 + 64 * 1024
+    # most 1024 blocks (value, key, index and a position each)
+    assert 3 * 8 * n * d + 8 * n <= b <= 3 * 8 * n * d + 8 * n + 2 * 1024 * (d + 3) * 8 + 64 * 1024
     with pytest.raises(Z.ZeusError):
         Z.zeus_workspace_bytes(Z.make_problem(_p(dim=0)))
 
@@ -117,7 +117,7 @@ def test_workspace_bytes_wide(Z, n, d):
     slots = min(n, 2048)
     hs = 8 * slots * d * ((d + 63) // 64 * 64)
     swarm = 3 * 8 * n * d + 8 * n
-    assert swarm + hs <= b <= swarm + hs + 2 * 512 * (d + 3) * 8 + 64 * 1024
+    assert swarm + hs <= b <= swarm + hs + 2 * 1024 * (d + 3) * 8 + 64 * 1024
 
 
 def test_context_without_device_is_a_clean_error(Z):
