@@ -97,26 +97,39 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const doubl
   for (int base = 0; base < q.iter_ls; base += R) {
     const int t = base + trial_slot;
     const double alpha = step_length(al, q.shrink, t);
-    // every slot is evaluated (indices clamped into the vectors) and the
+    // Every slot is evaluated (indices clamped into the vectors) and the
     // slots past the last term are replaced by zero afterwards: no branch
-    // per slot, so the loads of all slots are in flight together
-    U tv[E::K][B];
+    // per slot, so the loads of a chunk of CB slots are in flight together.
+    // A lane's B slots are taken CB at a time (a memory clobber between
+    // chunks keeps the next chunk's loads from being hoisted, which bounds
+    // the live registers); the pairwise tree over B is the tree over the
+    // chunk sums.
+    constexpr int CB = B < 4 ? B : 4;
+    U csum[E::K][B / CB];
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int i = c * B + b;
-      U w[E::W], out[E::K];
+    for (int cb = 0; cb < B / CB; ++cb) {
+      if (cb > 0) asm volatile("" ::: "memory");
+      U tv[E::K][CB];
 #pragma unroll
-      for (int e = 0; e < E::W; ++e) {
-        const int ie = i + e < SLOTS ? i + e : SLOTS - 1;
-        w[e] = (U)(xs[ie] + alpha * ps[ie]);
+      for (int b = 0; b < CB; ++b) {
+        const int i = c * B + cb * CB + b;
+        U w[E::W], out[E::K];
+#pragma unroll
+        for (int e = 0; e < E::W; ++e) {
+          const int ie = i + e < SLOTS ? i + e : SLOTS - 1;
+          w[e] = (U)(xs[ie] + alpha * ps[ie]);
+        }
+        E::template term<U>(w, out);
+#pragma unroll
+        for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = i < m ? out[kk] : U(0);
       }
-      E::template term<U>(w, out);
 #pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = i < m ? out[kk] : U(0);
+      for (int kk = 0; kk < E::K; ++kk) csum[kk][cb] = reg_tree_sum<CB, U>(tv[kk]);
     }
     U sums[E::K];
 #pragma unroll
-    for (int kk = 0; kk < E::K; ++kk) sums[kk] = lane_tree_sum<TP, U>(reg_tree_sum<B, U>(tv[kk]));
+    for (int kk = 0; kk < E::K; ++kk)
+      sums[kk] = lane_tree_sum<TP, U>(reg_tree_sum<B / CB, U>(csum[kk]));
     const double ft = (double)E::template outer<U>(d, sums);
     const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
     const uint64_t hit = L.ballot(ok) & leaders;

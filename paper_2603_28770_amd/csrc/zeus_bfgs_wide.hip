@@ -172,22 +172,43 @@ __device__ __forceinline__ int wide_armijo(WideShm &sh, double f, double ddir, i
 // evaluation with escalation to FP64 near the minimum, on a non-finite value
 // or on a failed FP32 line search; H, s, y, p, g'p and Armijo stay FP64.
 //
-// Row products: blocks of kHBlock columns, block sums over a zero-padded tree.
+// Row products: blocks of kHBlock columns, the block sums added over the
+// zero-padded pairwise tree of kHBlocks leaves.  The tree is folded as the
+// blocks complete, like a binary counter: s[l] holds the finished subtree of
+// 2^l blocks waiting for its right sibling.  The block index is the same on
+// every lane, so the branches are uniform and the column loops stay short.
 constexpr int kHBlock = 16;
 constexpr int kHBlocks = kMaxDim / kHBlock;
+static_assert(kHBlocks == 16, "the fold below has four levels");
+
+__device__ __forceinline__ void fold_block(double x, int b, double (&s)[4], double &total) {
+  if (!(b & 1)) { s[0] = x; return; }
+  x = s[0] + x;
+  if (!(b & 2)) { s[1] = x; return; }
+  x = s[1] + x;
+  if (!(b & 4)) { s[2] = x; return; }
+  x = s[2] + x;
+  if (!(b & 8)) { s[3] = x; return; }
+  total = s[3] + x;
+}
 
 // sum_c H(j, c) v[c] for the column-major row starting at hc
 __device__ __forceinline__ double slot_row_dot(const double *hc, int64_t cs, const double *v, int d) {
-  double part[kHBlocks];
-#pragma unroll
-  for (int b = 0; b < kHBlocks; ++b) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0}, total = 0.0;
+  int b = 0;
+  for (; b * kHBlock < d; ++b) {
+    const int c0 = b * kHBlock;
     double acc = 0.0;
-    const int c1 = min(d, (b + 1) * kHBlock);
-#pragma unroll 8
-    for (int c = b * kHBlock; c < c1; ++c) acc = __builtin_fma(hc[(int64_t)c * cs], v[c], acc);
-    part[b] = acc;
+    if (c0 + kHBlock <= d) {
+#pragma unroll
+      for (int k = 0; k < kHBlock; ++k) acc = __builtin_fma(hc[(int64_t)(c0 + k) * cs], v[c0 + k], acc);
+    } else {
+      for (int c = c0; c < d; ++c) acc = __builtin_fma(hc[(int64_t)c * cs], v[c], acc);
+    }
+    fold_block(acc, b, s, total);
   }
-  return reg_tree_sum<kHBlocks, double>(part);
+  for (; b < kHBlocks; ++b) fold_block(0.0, b, s, total);
+  return total;
 }
 template <int OBJ, class T>
 __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, int nreq,
@@ -261,26 +282,31 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
         const double au = -rho * sj;
         const double as = beta * sj - rho * uj;
         // H+ = H - rho (s u' + u s') + beta s s'   (row j), then p_j = -(H+ g)_j
-        double part[kHBlocks];
-#pragma unroll
-        for (int b = 0; b < kHBlocks; ++b) part[b] = 0.0;
+        double total = 0.0;
         if (own) {
           double *hc = H + j;
-#pragma unroll
-          for (int b = 0; b < kHBlocks; ++b) {
+          double s[4] = {0.0, 0.0, 0.0, 0.0};
+          auto upd = [&](int c, double acc) {
+            const double hn =
+                __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], hc[(int64_t)c * cs]));
+            hc[(int64_t)c * cs] = hn;
+            return __builtin_fma(hn, sh.gs[c], acc);
+          };
+          int b = 0;
+          for (; b * kHBlock < d; ++b) {
+            const int c0 = b * kHBlock;
             double acc = 0.0;
-            const int c1 = min(d, (b + 1) * kHBlock);
-#pragma unroll 8
-            for (int c = b * kHBlock; c < c1; ++c) {
-              const double hn =
-                  __builtin_fma(as, sh.ss[c], __builtin_fma(au, sh.us[c], hc[(int64_t)c * cs]));
-              hc[(int64_t)c * cs] = hn;
-              acc = __builtin_fma(hn, sh.gs[c], acc);
+            if (c0 + kHBlock <= d) {
+#pragma unroll
+              for (int k = 0; k < kHBlock; ++k) acc = upd(c0 + k, acc);
+            } else {
+              for (int c = c0; c < d; ++c) acc = upd(c, acc);
             }
-            part[b] = acc;
+            fold_block(acc, b, s, total);
           }
+          for (; b < kHBlocks; ++b) fold_block(0.0, b, s, total);
         }
-        pj = own ? -reg_tree_sum<kHBlocks, double>(part) : 0.0;
+        pj = own ? -total : 0.0;
         have_p = true;
       }
       ++k;

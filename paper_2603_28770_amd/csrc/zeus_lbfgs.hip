@@ -100,9 +100,15 @@ __device__ __forceinline__ double value_slots(const GroupLanes<G> &L, int d, con
   return group_value_slots<OBJ, G, CPL, T>(L, d, xs);
 }
 
+// Two waves per SIMD for the 4-coordinate kernels of the polynomial
+// objectives, which then fit 256 registers without spilling (the
+// transcendental ones would spill over a hundred and stay at one wave).
+template <int OBJ, int CPL>
+constexpr int kLbfgsWaves = CPL == 4 && OBJ != kRastrigin && OBJ != kAckley ? 2 : 1;
+
 template <int OBJ, int G, int CPL, class T>
-__global__ __launch_bounds__(kBfgsBlock) void lbfgs_kernel(const ReqDev *reqs, int nreq,
-                                                           BatchDev *hdr, int64_t total) {
+__global__ __launch_bounds__(kBfgsBlock) __attribute__((amdgpu_waves_per_eu(kLbfgsWaves<OBJ, CPL>)))
+void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
   constexpr bool kMixed = sizeof(T) != sizeof(double);
   constexpr int S = 64 / G;  // groups per wave
   constexpr int SLOTS = G * CPL;
