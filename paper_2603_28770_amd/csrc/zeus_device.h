@@ -5,9 +5,10 @@
 //
 // All code here is compiled with -ffp-contract=off: every multiply and add
 // rounds separately unless a kernel asks for a fused multiply-add explicitly
-// with __builtin_fma.  The evaluation order of each objective is fixed (left
-// to right sums) so that the swarm phase reproduces a plain sequential
-// evaluation bit for bit.
+// with __builtin_fma.  Each objective is split into per-term values and an
+// outer function of their sums; the kernels add the terms by the balanced
+// pairwise tree, so an evaluation rounds exactly as a plain sequential
+// evaluation with pairwise sums does.
 #pragma once
 
 #include <hip/hip_runtime.h>
