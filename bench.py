@@ -265,6 +265,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run of the same workload")
+    ap.add_argument("--study", choices=("ncorrect_vs_d", "pso_iters"), default=None,
+                    help="effectiveness study instead of the throughput line: N_correct per "
+                         "Rastrigin dimension (10^5 particles, 5 sweeps, stop at 100 "
+                         "convergences), or N_correct and time to 100 convergences per number "
+                         "of swarm sweeps (d = 5 Rastrigin and Rosenbrock)")
+    ap.add_argument("--runs", type=int, default=100, help="--study: runs per configuration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 3 times (a plain copy kernel "
                          "of known size for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -286,6 +292,25 @@ def main():
 
     import torch
     from paper_2603_28770_amd import zeus as Z
+
+    if args.study:
+        from paper_2603_28770_amd import studies as S
+        ctx = Z.zeus_context_create(0)
+        log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
+        if args.study == "ncorrect_vs_d":
+            rows = S.sweep(Z, ctx, "rastrigin", [(d, 5) for d in range(1, 11)], args.runs,
+                           100000, 100, 1000, log)
+        else:
+            sweeps = [0, 1, 2, 5, 10, 20, 50]
+            rows = []
+            for obj in ("rastrigin", "rosenbrock"):
+                rows += S.sweep(Z, ctx, obj, [(5, k) for k in sweeps], args.runs, 100000, 100,
+                                2000, log)
+        Z.zeus_context_destroy(ctx)
+        print(json.dumps({"study": args.study, "data": "synthetic (seeded Philox starts)",
+                          "criterion": "Euclidean distance to the global minimiser < 0.5",
+                          "rows": rows}), flush=True)
+        return
 
     if args.workload in MULTI:
         ctx = Z.zeus_context_create(0)
