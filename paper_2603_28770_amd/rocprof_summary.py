@@ -28,9 +28,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # Sources that define each kernel's code.
 KERNEL_SOURCES = {
-    "bfgs_kernel": ["csrc/zeus_bfgs.hip", "csrc/zeus_group.h", "csrc/zeus_device.h",
-                    "csrc/zeus_internal.h"],
-    "pso_kernel": ["csrc/zeus_pso.hip", "csrc/zeus_group.h", "csrc/zeus_device.h",
+    "bfgs_kernel": ["csrc/zeus_bfgs_kernels.h", "csrc/zeus_bfgs_common.h", "csrc/zeus_group.h",
+                    "csrc/zeus_device.h", "csrc/zeus_internal.h"],
+    "pso_kernel": ["csrc/zeus_pso_kernels.h", "csrc/zeus_group.h", "csrc/zeus_device.h",
                    "csrc/zeus_internal.h"],
 }
 
