@@ -59,7 +59,8 @@ typedef enum zeus_objective {
   ZEUS_STYBLINSKI_TANG = 3,
   ZEUS_GOLDSTEIN_PRICE = 4, /* dim == 2 */
   ZEUS_SPHERE = 5,
-  ZEUS_QUARTIC = 6
+  ZEUS_QUARTIC = 6,
+  ZEUS_USER = 7             /* user code, see zeus_objective_compile */
 } zeus_objective;
 
 /* ZEUS_FP64: everything in IEEE double.
@@ -294,6 +295,47 @@ zeus_err zeus_server_cancel(zeus_server *srv, uint64_t ticket);
 /* Cancels every queued request, waits for the running batches, stops the
  * worker and frees the budget. */
 zeus_err zeus_server_destroy(zeus_server *srv);
+
+/* ------------------------------------------------------------------------ */
+/* User-defined objectives.                                                 */
+/*                                                                          */
+/* The paper's f is user code: a function of the point written once over a */
+/* number type, so that it gives values and, on dual numbers, directional   */
+/* derivatives (Sec. III-C, Alg. 5).  Here it is C++ source compiled at run */
+/* time (hipRTC) together with the library's kernel templates.  The source  */
+/* defines                                                                  */
+/*     template <class T, class X> ZEUS_FN T objective(const X &x, int d);  */
+/* where x[i], i < d, is the point's coordinate i as a T; T is double or    */
+/* zeus::Dual; +, -, *, / work between Ts and doubles, and zsin, zcos,      */
+/* zexp, zlog and zsqrt are provided for both; helpers are ZEUS_FN too and  */
+/* data may sit in namespace-scope constexpr arrays.  Without a term        */
+/* structure the kernels evaluate the whole function: a value is one call,  */
+/* lane j of a start computes df/dx_j by one call on dual numbers seeded    */
+/* with e_j (Alg. 5 as written), and a line-search round tries one step     */
+/* length per lane.  Built for dim <= 64, FP64, BFGS.                       */
+/* ------------------------------------------------------------------------ */
+typedef struct zeus_user_objective zeus_user_objective;
+
+/* Compiles `source` (NUL-terminated) for the context's device and loads its
+ * kernels.  *out receives the handle (owned by the caller, released with
+ * zeus_objective_destroy; valid while the context lives).  ZEUS_EINVAL with
+ * the compiler's messages in zeus_last_error() when the source does not
+ * compile; ZEUS_EHIP when loading fails. */
+zeus_err zeus_objective_compile(zeus_context *ctx, const char *source, zeus_user_objective **out);
+
+/* Compiles `source` for gfx950 without loading it (no device needed): the
+ * same checks as zeus_objective_compile, for validating a source. */
+zeus_err zeus_objective_check(const char *source);
+
+zeus_err zeus_objective_destroy(zeus_user_objective *obj);
+
+/* Blocking solve of n >= 1 problems of the user objective `obj`, as
+ * zeus_minimize_batch: every problem has objective ZEUS_USER (else
+ * ZEUS_EINVAL), precision ZEUS_FP64, lbfgs_m 0 and dim <= 64 (else
+ * ZEUS_EUNSUPPORTED); required_converged works as for zeus_minimize.  The
+ * other entry points refuse ZEUS_USER. */
+zeus_err zeus_minimize_user(zeus_context *ctx, const zeus_user_objective *obj,
+                            const zeus_problem *problems, int32_t n, const zeus_result *outs);
 
 #ifdef __cplusplus
 }

@@ -42,11 +42,19 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Argument checks shared by every entry point taking a problem.
-zeus_err check_problem(const zeus_problem *p) {
+zeus_err check_problem(const zeus_problem *p, bool user = false) {
   if (!p) return fail(ZEUS_EINVAL, "problem is NULL");
   if (p->abi_version != ZEUS_ABI_VERSION) return fail(ZEUS_EINVAL, "abi_version mismatch");
-  if (p->objective < ZEUS_ROSENBROCK || p->objective > ZEUS_QUARTIC)
+  if (user) {
+    if (p->objective != ZEUS_USER) return fail(ZEUS_EINVAL, "objective must be ZEUS_USER");
+    if (p->precision != ZEUS_FP64) return fail(ZEUS_EUNSUPPORTED, "user objectives run in FP64");
+    if (p->lbfgs_m != 0) return fail(ZEUS_EUNSUPPORTED, "user objectives run with BFGS");
+    if (p->dim > zeus::kMaxNarrowDim) return fail(ZEUS_EUNSUPPORTED, "user objectives need dim <= 64");
+  } else if (p->objective == ZEUS_USER) {
+    return fail(ZEUS_EINVAL, "ZEUS_USER problems run through zeus_minimize_user");
+  } else if (p->objective < ZEUS_ROSENBROCK || p->objective > ZEUS_QUARTIC) {
     return fail(ZEUS_EINVAL, "unknown objective");
+  }
   if (p->dim < 1) return fail(ZEUS_EINVAL, "dim must be >= 1");
   if (p->objective == ZEUS_ROSENBROCK && p->dim < 2)
     return fail(ZEUS_EINVAL, "Rosenbrock needs dim >= 2");
@@ -175,7 +183,19 @@ struct zeus_context {
   };
   std::vector<Pending> pending;
   zeus_profile prof{};
+  // the user objective of the call in progress (set under mu)
+  const zeus::UserKernels *active_user = nullptr;
 };
+
+struct zeus_user_objective {
+  int device = 0;
+  zeus::UserKernels k{};
+};
+
+namespace zeus {
+int user_compile(const char *arch, const char *source, UserKernels *out, std::string *log);
+void user_release(UserKernels *k);
+}  // namespace zeus
 
 namespace {
 
@@ -272,6 +292,7 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
   g.wide_slots = 0;
   g.wide_cs = 0;
   g.wide_slot_doubles = 0;
+  g.user = nullptr;
   host.assign(reqs.size(), zeus::ReqDev{});
   for (size_t r = 0; r < reqs.size(); ++r) {
     const zeus_problem &p = *reqs[r].pb;
@@ -355,7 +376,11 @@ zeus_err enqueue_copies(const std::vector<Planned> &reqs, hipStream_t stream) {
 // swarm-state copies.  The request table must already be on the device.
 zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<Planned> &reqs,
                       bool with_copies, bool with_swarm = true) {
-  const zeus::Group &g = run.g;
+  zeus::Group g = run.g;
+  if (g.objective == ZEUS_USER) {
+    g.user = ctx ? ctx->active_user : nullptr;
+    if (!g.user) return fail(ZEUS_EINVAL, "ZEUS_USER problem without a compiled objective");
+  }
   hipStream_t stream = g.stream;
   hipError_t e;
   zeus_context::Pending pend{};
@@ -916,13 +941,17 @@ zeus_err zeus_minimize(zeus_context *ctx, const zeus_problem *problem, const zeu
   return zeus_minimize_batch(ctx, problem, 1, out);
 }
 
-zeus_err zeus_minimize_batch(zeus_context *ctx, const zeus_problem *problems, int32_t n,
-                             const zeus_result *outs) {
+namespace {
+// zeus_minimize_batch, and zeus_minimize_user with `user` set.
+zeus_err minimize_batch(zeus_context *ctx, const zeus_problem *problems, int32_t n,
+                        const zeus_result *outs, const zeus_user_objective *user) {
   g_last_error.clear();
   if (!ctx) return fail(ZEUS_EINVAL, "ctx is NULL");
   if (n < 1 || !problems || !outs) return fail(ZEUS_EINVAL, "need n >= 1 problems and results");
+  if (user && user->device != ctx->device)
+    return fail(ZEUS_EINVAL, "the objective was compiled for another device");
   for (int32_t r = 0; r < n; ++r) {
-    zeus_err e = check_problem(&problems[r]);
+    zeus_err e = check_problem(&problems[r], user != nullptr);
     if (e == ZEUS_OK) e = check_result(&outs[r], &problems[r]);
     if (e != ZEUS_OK) return fail(e, "request " + std::to_string(r) + ": " + g_last_error);
   }
@@ -943,11 +972,75 @@ zeus_err zeus_minimize_batch(zeus_context *ctx, const zeus_problem *problems, in
   }
   std::vector<hipStream_t> streams{ctx->stream};
   for (size_t k = 0; k + 1 < want_streams; ++k) streams.push_back(ctx->aux[k]);
-  if ((e = enqueue_batch(ctx, plan, problems, outs, ctx->res, ctx->ws, streams)) != ZEUS_OK)
-    return e;
+  ctx->active_user = user ? &user->k : nullptr;
+  e = enqueue_batch(ctx, plan, problems, outs, ctx->res, ctx->ws, streams);
+  ctx->active_user = nullptr;
+  if (e != ZEUS_OK) return e;
   hipError_t he;
   for (hipStream_t st : streams)
     if ((he = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
+  return ZEUS_OK;
+}
+}  // namespace
+
+zeus_err zeus_minimize_batch(zeus_context *ctx, const zeus_problem *problems, int32_t n,
+                             const zeus_result *outs) {
+  return minimize_batch(ctx, problems, n, outs, nullptr);
+}
+
+zeus_err zeus_minimize_user(zeus_context *ctx, const zeus_user_objective *obj,
+                            const zeus_problem *problems, int32_t n, const zeus_result *outs) {
+  if (!obj) {
+    g_last_error.clear();
+    return fail(ZEUS_EINVAL, "objective is NULL");
+  }
+  return minimize_batch(ctx, problems, n, outs, obj);
+}
+
+zeus_err zeus_objective_check(const char *source) {
+  g_last_error.clear();
+  if (!source) return fail(ZEUS_EINVAL, "source is NULL");
+  std::string log;
+  const int r = zeus::user_compile("gfx950", source, nullptr, &log);
+  if (r == 1) return fail(ZEUS_EINVAL, "objective does not compile:\n" + log);
+  if (r != 0) return fail(ZEUS_EHIP, log);
+  return ZEUS_OK;
+}
+
+zeus_err zeus_objective_compile(zeus_context *ctx, const char *source, zeus_user_objective **out) {
+  g_last_error.clear();
+  if (!ctx || !source || !out) return fail(ZEUS_EINVAL, "NULL argument");
+  *out = nullptr;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  hipDeviceProp_t prop;
+  hipError_t he = hipGetDeviceProperties(&prop, ctx->device);
+  if (he != hipSuccess) return hip_fail(he, "hipGetDeviceProperties");
+  std::string arch(prop.gcnArchName);
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  auto *obj = new (std::nothrow) zeus_user_objective;
+  if (!obj) return fail(ZEUS_ENOMEM, "allocation failed");
+  obj->device = ctx->device;
+  std::string log;
+  const int r = zeus::user_compile(arch.c_str(), source, &obj->k, &log);
+  if (r != 0) {
+    delete obj;
+    return fail(r == 1 ? ZEUS_EINVAL : ZEUS_EHIP,
+                r == 1 ? "objective does not compile:\n" + log : log);
+  }
+  *out = obj;
+  return ZEUS_OK;
+}
+
+zeus_err zeus_objective_destroy(zeus_user_objective *obj) {
+  g_last_error.clear();
+  if (!obj) return ZEUS_OK;
+  {
+    DeviceGuard dg(obj->device);
+    zeus::user_release(&obj->k);
+  }
+  delete obj;
   return ZEUS_OK;
 }
 

@@ -173,6 +173,10 @@ int group_lanes(int objective, int precision, int dim) {
   return g;
 }
 
+size_t bfgs_lds_bytes(int lanes) {
+  return sizeof(double) * (size_t)group_stride(lanes) * (kBfgsBlock / lanes);
+}
+
 hipError_t launch_bfgs(const Group &g) {
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -184,6 +188,7 @@ hipError_t launch_bfgs(const Group &g) {
   if (g.g_bfgs > kMaxNarrowDim) return hipErrorInvalidValue;
   const int64_t starts_per_block = (int64_t)(kBfgsBlock / g.g_bfgs);
   const int64_t want = (g.total_starts + starts_per_block - 1) / starts_per_block;
+  if (g.objective == kUser) return launch_user_bfgs(g, want, cus);
   if (g.precision == ZEUS_MIXED) return launch_prec<float>(g, want, cus);
   return launch_prec<double>(g, want, cus);
 }

@@ -92,6 +92,18 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const doubl
     for (int r = 0; r < R; ++r) b |= 1ull << (r * TP);
     return b;
   }();
+  if constexpr (whole_form<E>::value) {
+    // one trial per lane: trials base .. base + G - 1 in a round
+    for (int base = 0; base < q.iter_ls; base += G) {
+      const int t = base + L.j;
+      const double alpha = step_length(al, q.shrink, t);
+      const double ft = E::trial(xs, ps, alpha, q.d);
+      const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
+      const uint64_t hit = L.ballot(ok);
+      if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1);
+    }
+    return -1;
+  } else {
   const int trial_slot = L.j / TP, c = L.j % TP;
   const int d = q.d, m = q.m;
   for (int base = 0; base < q.iter_ls; base += R) {
@@ -136,6 +148,7 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const doubl
     if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1) / TP;
   }
   return -1;
+  }
 }
 
 }  // namespace zeus

@@ -273,11 +273,24 @@ enum Objective : int {
   kStyblinskiTang = 3,
   kGoldsteinPrice = 4,
   kSphere = 5,
-  kQuartic = 6
+  kQuartic = 6,
+  kUser = 7  // a user objective compiled at run time (zeus_user.h)
 };
 
 template <int OBJ>
 struct Elem;
+
+// An objective in "whole" form (user code, no term structure) declares
+// kWhole = true and provides value / value_grad / trial evaluations; the
+// kernels then evaluate it as one function instead of term by term.
+template <class E, class = void>
+struct whole_form {
+  static constexpr bool value = false;
+};
+template <class E>
+struct whole_form<E, decltype(void(E::kWhole))> {
+  static constexpr bool value = E::kWhole;
+};
 
 // sum_{i<d-1} (1 - x_i)^2 + 100 (x_{i+1} - x_i^2)^2
 template <>

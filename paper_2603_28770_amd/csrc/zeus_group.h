@@ -283,6 +283,9 @@ template <int OBJ, int G, int CPL, class T>
 __device__ __forceinline__ double group_value_slots(const GroupLanes<G> &L, int d,
                                                     const double *xs) {
   using E = Elem<OBJ>;
+  if constexpr (whole_form<E>::value) {
+    return E::value(xs, d);
+  } else {
   const int m = E::terms(d);
   T blk[E::K][CPL];
 #pragma unroll
@@ -300,6 +303,7 @@ __device__ __forceinline__ double group_value_slots(const GroupLanes<G> &L, int 
 #pragma unroll
   for (int k = 0; k < E::K; ++k) s[k] = reg_tree_sum<CPL, T>(blk[k]);
   return (double)E::template outer<T>(d, s);
+  }
 }
 
 template <int OBJ, int G, class T>
@@ -318,9 +322,16 @@ template <int OBJ, int G, class T>
 __device__ __forceinline__ double group_value_grad(const GroupLanes<G> &L, int d,
                                                    const double *xs, double *gj) {
   using E = Elem<OBJ>;
+  const int j = L.j;
+  if constexpr (whole_form<E>::value) {
+    // Alg. 5 as written: one evaluation on dual numbers seeded with e_j
+    double g;
+    const double f = E::value_grad(xs, d, j < d ? j : -1, &g);
+    *gj = j < d ? g : 0.0;
+    return f;
+  } else {
   static_assert(E::W <= 2, "the tangent sum assumes at most two terms per coordinate");
   const int m = E::terms(d);
-  const int j = L.j;
   T tan[E::K], val[E::K];
 #pragma unroll
   for (int k = 0; k < E::K; ++k) {
@@ -354,6 +365,7 @@ __device__ __forceinline__ double group_value_grad(const GroupLanes<G> &L, int d
   const dual<T> r = E::template outer<dual<T>>(d, sd);
   *gj = (j < d) ? (double)r.t : 0.0;
   return (double)r.v;
+  }
 }
 
 }  // namespace zeus

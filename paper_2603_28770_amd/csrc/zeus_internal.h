@@ -86,6 +86,15 @@ struct BatchDev {
   uint64_t queue;            // next unclaimed BFGS start over all requests
 };
 
+// Kernels of a user objective, compiled at run time (zeus_user.cpp): the
+// module and its swarm and BFGS kernels by log2 of the lanes per particle /
+// per start (hipModule_t and hipFunction_t handles).
+struct UserKernels {
+  void *module;
+  void *pso[7];
+  void *bfgs[7];
+};
+
 // A launch group: device table of nreq requests plus its counters.
 struct Group {
   int objective;
@@ -104,6 +113,7 @@ struct Group {
   int wide_slots;
   int wide_cs;               // column stride of a slot (max dim rounded up to 64)
   int64_t wide_slot_doubles; // max dim * wide_cs
+  const UserKernels *user;   // objective == kUser: its compiled kernels
 };
 
 // H slots of a wide launch group whose largest dimension is dmax.
@@ -122,6 +132,11 @@ hipError_t launch_lbfgs(const Group &g, int cus);
 // wavefront covers up to 256).
 int lbfgs_slots(int dim);
 hipError_t launch_summary(const Group &g);
+// User objectives: swarm sweep and (d <= 64) BFGS launches of the compiled
+// kernels, and the dynamic LDS of a BFGS block with `lanes` lanes per start.
+hipError_t launch_user_pso(const Group &g, int t);
+hipError_t launch_user_bfgs(const Group &g, int64_t want, int cus);
+size_t bfgs_lds_bytes(int lanes);
 
 // Lanes per start of the BFGS kernels for a problem (power of two >= dim, at
 // most 64, or kWideLanes for one block per start), from the tiling table.

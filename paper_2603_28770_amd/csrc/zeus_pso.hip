@@ -72,6 +72,7 @@ hipError_t launch_pso(const Group &g, int t) {
     case kGoldsteinPrice: return launch_g<kGoldsteinPrice, 2>(g, t);
     case kSphere: return launch_obj<kSphere>(g, t);
     case kQuartic: return launch_obj<kQuartic>(g, t);
+    case kUser: return launch_user_pso(g, t);
     default: return hipErrorInvalidValue;
   }
 }

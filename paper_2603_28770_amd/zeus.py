@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("ZEUS_LIB") or os.path.join(HERE, "libzeus.so")
 ABI_VERSION = 1
 OK, NOT_READY, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ECANCELLED, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
 OBJECTIVES = {"rosenbrock": 0, "rastrigin": 1, "ackley": 2, "styblinski_tang": 3,
-              "goldstein_price": 4, "sphere": 5, "quartic": 6}
+              "goldstein_price": 4, "sphere": 5, "quartic": 6, "user": 7}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 ST_MAXITER, ST_CONVERGED, ST_STOPPED, ST_NONFINITE = 0, 1, 2, 3
 
@@ -29,7 +29,9 @@ EXPORTS = ("zeus_abi_version", "zeus_version", "zeus_last_error", "zeus_validate
            "zeus_context_set_profiling", "zeus_context_get_profile", "zeus_minimize",
            "zeus_minimize_batch", "zeus_minimize_async", "zeus_server_create",
            "zeus_server_submit", "zeus_server_wait", "zeus_server_cancel", "zeus_server_destroy",
-           "zeus_plan_workspace_bytes", "zeus_plan_create", "zeus_plan_launch", "zeus_plan_destroy")
+           "zeus_plan_workspace_bytes", "zeus_plan_create", "zeus_plan_launch", "zeus_plan_destroy",
+           "zeus_objective_compile", "zeus_objective_check", "zeus_objective_destroy",
+           "zeus_minimize_user")
 
 
 class zeus_problem(C.Structure):
@@ -107,6 +109,10 @@ def _load():
                                    P(zeus_result), P(C.c_void_p)]
     L.zeus_plan_launch.argtypes = [C.c_void_p, C.c_void_p]
     L.zeus_plan_destroy.argtypes = [C.c_void_p]
+    L.zeus_objective_compile.argtypes = [C.c_void_p, C.c_char_p, P(C.c_void_p)]
+    L.zeus_objective_check.argtypes = [C.c_char_p]
+    L.zeus_objective_destroy.argtypes = [C.c_void_p]
+    L.zeus_minimize_user.argtypes = [C.c_void_p, C.c_void_p, P(zeus_problem), C.c_int32, P(zeus_result)]
     for name in EXPORTS:
         if name not in ("zeus_abi_version", "zeus_version", "zeus_last_error"):
             getattr(L, name).restype = C.c_int
@@ -219,8 +225,7 @@ def zeus_minimize(ctx, problem, *, trace_len=0, pso_state=False, ls_trials=True)
     return o
 
 
-def zeus_minimize_batch(ctx, problems, *, trace_len=0, pso_state=False, ls_trials=True) -> list:
-    """Blocking solve of a list of problems (dicts or zeus_problem)."""
+def _solve_list(call, problems, trace_len, pso_state, ls_trials) -> list:
     pbs = (zeus_problem * len(problems))(
         *[p if isinstance(p, zeus_problem) else make_problem(p) for p in problems])
     outs, sums = [], []
@@ -230,10 +235,41 @@ def zeus_minimize_batch(ctx, problems, *, trace_len=0, pso_state=False, ls_trial
         outs.append(o)
         sums.append(s)
         res[k] = r
-    _check(lib.zeus_minimize_batch(ctx, pbs, len(problems), res))
+    _check(call(pbs, len(problems), res))
     for o, s in zip(outs, sums):
         o["summary"] = _summary_dict(s)
     return outs
+
+
+def zeus_minimize_batch(ctx, problems, *, trace_len=0, pso_state=False, ls_trials=True) -> list:
+    """Blocking solve of a list of problems (dicts or zeus_problem)."""
+    return _solve_list(lambda p, n, r: lib.zeus_minimize_batch(ctx, p, n, r), problems, trace_len,
+                       pso_state, ls_trials)
+
+
+def zeus_objective_check(source: str) -> None:
+    """Compiles a user objective's source for gfx950 without loading it
+    (raises ZeusError with the compiler's messages)."""
+    _check(lib.zeus_objective_check(source.encode()))
+
+
+def zeus_objective_compile(ctx, source: str):
+    """Compiles and loads a user objective; returns its handle."""
+    h = C.c_void_p()
+    _check(lib.zeus_objective_compile(ctx, source.encode(), C.byref(h)))
+    return h
+
+
+def zeus_objective_destroy(obj) -> None:
+    _check(lib.zeus_objective_destroy(obj))
+
+
+def zeus_minimize_user(ctx, obj, problems, *, trace_len=0, pso_state=False, ls_trials=True) -> list:
+    """Blocking solve of problems (objective "user") of a compiled user objective."""
+    if isinstance(problems, (dict, zeus_problem)):
+        problems = [problems]
+    return _solve_list(lambda p, n, r: lib.zeus_minimize_user(ctx, obj, p, n, r), problems, trace_len,
+                       pso_state, ls_trials)
 
 
 def zeus_minimize_async(ctx, problem, workspace_ptr: int, workspace_bytes: int,
