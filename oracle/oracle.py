@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzeus_oracle.so")
 
 OBJECTIVES = {"rosenbrock": 0, "rastrigin": 1, "ackley": 2, "styblinski_tang": 3,
-              "goldstein_price": 4, "sphere": 5, "quartic": 6}
+              "goldstein_price": 4, "sphere": 5, "quartic": 6, "user": 7}
 MAXITER, CONVERGED, STOPPED, NONFINITE = 0, 1, 2, 3
 TAG_X0, TAG_V0, TAG_R1, TAG_R2 = 0, 1, 2, 3
 

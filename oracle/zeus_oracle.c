@@ -166,6 +166,48 @@ double zo_exp(double x) {
   return ldexp(p, (int)k);
 }
 
+/* Natural logarithm.  x = m 2^e with sqrt(1/2) <= m < sqrt(2) (frexp, then
+ * one doubling), log m = 2 atanh(s) with s = (m - 1)/(m + 1): the atanh
+ * series 2 s (1 + z/3 + z^2/5 + ... + z^11/23), z = s^2 <= 0.0295, summed by
+ * Horner's rule with fused multiply-adds as 2s + 2s (z/3 + ...), and
+ * log x = e ln2_hi + (e ln2_lo + log m), where ln2_hi is ln 2 rounded to a
+ * double with its low 20 significand bits cleared (so e ln2_hi is exact) and
+ * ln2_lo the double nearest ln 2 - ln2_hi. */
+#define ZM_LOG_LN2_HI 0x1.62e42fefp-1
+#define ZM_LOG_LN2_LO 0x1.473de6af278edp-34
+#define ZM_SQRT_HALF 0x1.6a09e667f3bcdp-1
+
+double zo_log(double x) {
+  if (!(x > 0.0)) return x == 0.0 ? -INFINITY : NAN;
+  if (x == INFINITY) return x;
+  int e;
+  double m = frexp(x, &e);
+  if (m < ZM_SQRT_HALF) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  double f = m - 1.0;
+  double s = f / (2.0 + f);
+  double z = s * s;
+  double p = 1.0 / 23.0;
+  p = fma(p, z, 1.0 / 21.0);
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  double t2 = p * z;
+  double s2 = s + s;
+  double lm = fma(s2, t2, s2);
+  double k = (double)e;
+  double r = fma(k, ZM_LOG_LN2_LO, lm);
+  return fma(k, ZM_LOG_LN2_HI, r);
+}
+
 /* ======================================================================== */
 /* Dual numbers a + b*eps with eps^2 = 0 (Sec. III-C).  v = value, t = tangent.*/
 /* ======================================================================== */
@@ -336,8 +378,32 @@ static dual fourth_term(const dual *x, int i) {
 }
 static dual obj_quartic(const dual *x, int d) { return pw_terms(fourth_term, x, 0, d); }
 
+/* User objective (ZO_USER): the value in double and one evaluation on dual
+ * numbers, both from the user's source compiled for the CPU (zo_set_user). */
+static zo_user_value_fn g_user_value = NULL;
+static zo_user_dual_fn g_user_dual = NULL;
+
+void zo_set_user(zo_user_value_fn value, zo_user_dual_fn dual_eval) {
+  g_user_value = value;
+  g_user_dual = dual_eval;
+}
+
+static dual obj_user(const dual *x, int d) {
+  double *xv = (double *)malloc(sizeof(double) * (size_t)(2 * d + 1));
+  double *xt = xv + d;
+  for (int i = 0; i < d; ++i) {
+    xv[i] = x[i].v;
+    xt[i] = x[i].t;
+  }
+  double t = NAN;
+  double v = g_user_dual ? g_user_dual(xv, xt, d, &t) : NAN;
+  free(xv);
+  return dd(v, t);
+}
+
 static dual eval_dual(int objective, const dual *x, int d) {
   switch (objective) {
+    case ZO_USER: return obj_user(x, d);
     case ZO_ROSENBROCK: return obj_rosenbrock(x, d);
     case ZO_RASTRIGIN: return obj_rastrigin(x, d);
     case ZO_ACKLEY: return obj_ackley(x, d);
@@ -350,6 +416,7 @@ static dual eval_dual(int objective, const dual *x, int d) {
 }
 
 double zo_f(int objective, const double *x, int dim) {
+  if (objective == ZO_USER) return g_user_value ? g_user_value(x, dim) : NAN;
   dual *xd = (dual *)malloc(sizeof(dual) * (size_t)dim);
   for (int i = 0; i < dim; ++i) xd[i] = dd(x[i], 0.0);
   double f = eval_dual(objective, xd, dim).v;
@@ -379,7 +446,11 @@ void zo_grad(int objective, const double *x, int dim, double *f, double *g) {
 
 int zo_validate(const zo_problem *pb) {
   if (!pb) return -1;
-  if (pb->objective < ZO_ROSENBROCK || pb->objective > ZO_QUARTIC) return -1;
+  if (pb->objective == ZO_USER) {
+    if (!g_user_value || !g_user_dual) return -1;
+  } else if (pb->objective < ZO_ROSENBROCK || pb->objective > ZO_QUARTIC) {
+    return -1;
+  }
   if (pb->dim < 1) return -1;
   if (pb->objective == ZO_ROSENBROCK && pb->dim < 2) return -1;
   if (pb->objective == ZO_GOLDSTEIN_PRICE && pb->dim != 2) return -1;

@@ -33,7 +33,8 @@ enum {
   ZO_STYBLINSKI_TANG = 3, /* standard Styblinski-Tang test function       */
   ZO_GOLDSTEIN_PRICE = 4, /* Sec. V-B, Goldstein-Price (dim = 2)          */
   ZO_SPHERE = 5,          /* test-only: 0.5 * sum x_i^2                    */
-  ZO_QUARTIC = 6          /* test-only: sum x_i^4                          */
+  ZO_QUARTIC = 6,         /* test-only: sum x_i^4                          */
+  ZO_USER = 7             /* user source, see zo_set_user                  */
 };
 
 /* Relative decision margin below which a branch counts as a near-tie. */
@@ -115,6 +116,16 @@ double zo_uniform(uint64_t seed, uint64_t request_id, uint64_t i, uint64_t t,
 double zo_sin(double x);
 double zo_cos(double x);
 double zo_exp(double x);
+double zo_log(double x);
+
+/* User objective (ZO_USER): `value` returns f(x) evaluated in double,
+ * `dual_eval` evaluates f once on the dual numbers xv[i] + xt[i] eps and
+ * returns the value part, storing the tangent part in *t.  Both come from
+ * the user's source compiled for the CPU (oracle/user.py) and must be safe
+ * to call from several threads.  Process-wide; NULL clears it. */
+typedef double (*zo_user_value_fn)(const double *x, int d);
+typedef double (*zo_user_dual_fn)(const double *xv, const double *xt, int d, double *t);
+void zo_set_user(zo_user_value_fn value, zo_user_dual_fn dual_eval);
 
 /* Objective value (primal evaluation). */
 double zo_f(int objective, const double *x, int dim);

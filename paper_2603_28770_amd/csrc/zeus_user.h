@@ -151,3 +151,12 @@ struct TrialView {  // the trial point x + alpha p, each coordinate rounded
 };
 
 }  // namespace zeus
+
+// The user's source is at namespace scope: make the number type and the
+// functions visible there (for double arguments no lookup reaches zeus::).
+using zeus::Dual;
+using zeus::zcos;
+using zeus::zexp;
+using zeus::zlog;
+using zeus::zsin;
+using zeus::zsqrt;

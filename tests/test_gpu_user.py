@@ -1,0 +1,121 @@
+"""User-defined objectives on the GPU (compiled at run time with hipRTC)
+against the oracle running the same source compiled for the CPU: swarm seeds
+and every start's f, x, iterations, status and line-search trials bit for
+bit, for one to four requests per call (a Goldstein-Price batch), every lane
+count from 4 to 64, trigonometric, logarithmic and exponential user code
+(a binned Poisson likelihood fit), and early stop; plus the refusals."""
+import numpy as np
+import pytest
+
+from oracle import user as OU
+from paper_2603_28770_amd import user_objectives as UO
+from paper_2603_28770_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("f", "x", "iters", "status", "ls_trials")
+
+
+@pytest.fixture(scope="module")
+def Z():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28770_amd import zeus
+    return zeus
+
+
+@pytest.fixture(scope="module")
+def ctx(Z):
+    c = Z.zeus_context_create(0)
+    yield c
+    Z.zeus_context_destroy(c)
+
+
+def _p(d, n, lo, hi, seed, **kw):
+    return W.problem(objective="user", dim=d, n=n, lower=lo, upper=hi, seed=seed,
+                     iter_pso=kw.pop("iter_pso", 5), iter_bfgs=kw.pop("iter_bfgs", 300), **kw)
+
+
+CASES = [
+    ("rosenbrock_d2", UO.ROSENBROCK, [_p(2, 512, -5.0, 5.0, 1)]),
+    ("rosenbrock_d9", UO.ROSENBROCK, [_p(9, 300, -2.0, 2.0, 2)]),
+    ("goldstein_price_batch", UO.GOLDSTEIN_PRICE,
+     [_p(2, 256, -2.0, 2.0, s, request_id=s) for s in range(4)]),
+    ("rastrigin_d5", UO.RASTRIGIN, [_p(5, 400, -5.12, 5.12, 3, iter_pso=10)]),
+    ("chain_log_d20", UO.CHAIN_LOG, [_p(20, 256, -2.0, 2.0, 4)]),
+    ("chain_log_d40", UO.CHAIN_LOG, [_p(40, 128, -2.0, 2.0, 5, iter_bfgs=200)]),
+    ("poisson_fit_d4", "poisson", [_p(4, 512, 0.0, 10.0, 6, iter_pso=10, iter_bfgs=500)]),
+]
+
+
+@pytest.fixture(scope="module")
+def compiled(Z, ctx):
+    objs = {}
+    yield lambda src: objs.setdefault(src, Z.zeus_objective_compile(ctx, src))
+    for h in objs.values():
+        Z.zeus_objective_destroy(h)
+
+
+@pytest.mark.parametrize("name,src,problems", CASES, ids=[c[0] for c in CASES])
+def test_user_objective_matches_oracle(Z, ctx, compiled, oracle_mod, name, src, problems):
+    src = UO.poisson_fit_source() if src == "poisson" else src
+    print(f"\n[user] {name}: {len(problems)} request(s), d = {problems[0]['dim']}", flush=True)
+    obj = compiled(src)
+    outs = Z.zeus_minimize_user(ctx, obj, problems, pso_state=True)
+    OU.use(src, oracle_mod.lib())
+    for p, g in zip(problems, outs):
+        sw = oracle_mod.pso(p)
+        assert np.array_equal(g["seeds"], sw["x"])
+        o = oracle_mod.bfgs(p, sw["x"])
+        for k in KEYS:
+            assert np.array_equal(g[k], o[k], equal_nan=True), (name, k)
+        print(f"[user]   converged {int(np.sum(o['status'] == 1))}/{p['n']}, "
+              f"best f {np.nanmin(o['f']):.6g}", flush=True)
+
+
+def test_user_objective_early_stop(Z, ctx, compiled, oracle_mod):
+    p = _p(20, 256, -2.0, 2.0, 8)
+    print("\n[user] chain_log_d20 with required_converged = 10", flush=True)
+    g = Z.zeus_minimize_user(ctx, compiled(UO.CHAIN_LOG), [dict(p, required_converged=10)])[0]
+    OU.use(UO.CHAIN_LOG, oracle_mod.lib())
+    o, kstar = oracle_mod.bfgs_required(p, oracle_mod.pso(p)["x"], 10)
+    for k in KEYS:
+        assert np.array_equal(g[k], o[k], equal_nan=True), k
+    assert np.sum(g["status"] == Z.ST_STOPPED) > 0
+
+
+def test_poisson_fit_recovers_the_spectrum(Z, ctx, compiled, oracle_mod):
+    """A sanity check of the example, not parity: the best converged start is
+    a maximum-likelihood fit, at least as likely as the generating parameters
+    (which are strongly correlated, so the fit may sit far from them in
+    parameter space), and its expected counts describe the spectrum within
+    the Poisson errors of every bin."""
+    src = UO.poisson_fit_source()
+    g = Z.zeus_minimize_user(ctx, compiled(src),
+                             [_p(4, 2048, 0.0, 10.0, 9, iter_pso=10, iter_bfgs=500)])[0]
+    b = int(np.nanargmin(np.where(g["status"] == 1, g["f"], np.nan)))
+    OU.use(src, oracle_mod.lib())
+    assert g["f"][b] <= oracle_mod.f("user", np.array(UO.POISSON_TRUE, dtype=np.float64))
+    _, l1, lx, n = UO.poisson_histogram()
+
+    def mu(t):
+        return np.exp(t[0] + t[1] * l1 - (t[2] + t[3] * lx) * lx)
+
+    m_fit, m_true = mu(g["x"][b]), mu(UO.POISSON_TRUE)
+    assert np.all(np.abs(m_fit - m_true) <= 4.0 * np.sqrt(m_true) + 1.0)
+
+
+def test_user_refusals(Z, ctx, compiled):
+    obj = compiled(UO.ROSENBROCK)
+    for bad, code in ((dict(dim=65), Z.EUNSUPPORTED), (dict(precision="mixed"), Z.EUNSUPPORTED),
+                      (dict(lbfgs_m=4), Z.EUNSUPPORTED), (dict(objective="rosenbrock"), Z.EINVAL)):
+        with pytest.raises(Z.ZeusError) as e:
+            Z.zeus_minimize_user(ctx, obj, [dict(_p(3, 16, -1.0, 1.0, 0), **bad)])
+        assert e.value.code == code, bad
+    with pytest.raises(Z.ZeusError) as e:
+        Z.zeus_minimize(ctx, _p(3, 16, -1.0, 1.0, 0))
+    assert e.value.code == Z.EINVAL
+    with pytest.raises(Z.ZeusError) as e:
+        Z.zeus_objective_compile(ctx, "this is not C++")
+    assert e.value.code == Z.EINVAL
