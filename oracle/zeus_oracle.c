@@ -88,8 +88,6 @@ static const double ZM_2_OVER_PI = 0x1.45f306dc9c883p-1;
 static const double ZM_LN2_1 = 0x1.62e42fefa39efp-1;
 static const double ZM_LN2_2 = 0x1.abc9e3b39803fp-56;
 static const double ZM_LOG2E = 0x1.71547652b82fep+0;
-/* beyond this |x| the three-term reduction loses accuracy: use libm */
-static const double ZM_TRIG_MAX = 0x1p28;
 
 /* sin r and cos r for |r| <= pi/4 (Taylor series to r^17 and r^16). */
 static double sin_taylor(double r) {
@@ -118,19 +116,27 @@ static double cos_taylor(double r) {
   return fma(z, q, 1.0);
 }
 
+/* x = k pi/2 + r, |r| <= pi/4 (about).  Each fused multiply-add rounds once
+ * at the magnitude of the running remainder, so with pi/2 split in three
+ * doubles the reduced argument is accurate to about an ulp of 1 as long as
+ * k = rint(x 2/pi) is the nearest integer, which holds with margin below
+ * |x| = 2^48 (ulp(x 2/pi) <= 1/16).  The paper does not say how large
+ * arguments are handled; here sin and cos are NaN from |x| = 2^48 on (and for
+ * an infinity or NaN), so an objective evaluated there is non-finite. */
+static const double ZM_TRIG_MAX = 0x1p48;
+
 static void zo_sincos(double x, double *s, double *c) {
-  if (!(fabs(x) <= ZM_TRIG_MAX)) { /* huge, inf or NaN */
-    *s = sin(x);
-    *c = cos(x);
+  if (!(fabs(x) < ZM_TRIG_MAX)) {
+    *s = *c = NAN;
     return;
   }
-  /* x = k pi/2 + r, |r| <= pi/4 (about) */
   double k = rint(x * ZM_2_OVER_PI);
   double r = fma(-k, ZM_PIO2_1, x);
   r = fma(-k, ZM_PIO2_2, r);
   r = fma(-k, ZM_PIO2_3, r);
   double sr = sin_taylor(r), cr = cos_taylor(r);
-  switch ((int)((int64_t)k & 3)) {
+  double q = k - 4.0 * floor(k * 0.25);
+  switch ((int)q) {
     case 0: *s = sr; *c = cr; break;
     case 1: *s = cr; *c = -sr; break;
     case 2: *s = -sr; *c = -cr; break;
