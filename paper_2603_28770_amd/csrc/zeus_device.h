@@ -107,7 +107,7 @@ __device__ __forceinline__ dual<T> ksub(T k, dual<T> a) { return {k - a.v, -a.t}
 // "Software Manual for the Elementary Functions", 1980) and the Taylor series
 // of the reduced argument by Horner's rule with fused multiply-adds (about
 // one ulp).  Every rounding step is explicit, so the value does not depend on
-// the device math library; beyond |x| = 2^28 the library takes over.
+// the device math library (from |x| = 2^48 on sin and cos are NaN, see sincos).
 // ---------------------------------------------------------------------------
 namespace zm {
 constexpr double kPio2A = 0x1.921fb54442d18p+0;   // pi/2 = A + B + C
@@ -117,7 +117,7 @@ constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kLn2A = 0x1.62e42fefa39efp-1;    // ln 2 = A + B
 constexpr double kLn2B = 0x1.abc9e3b39803fp-56;
 constexpr double kLog2e = 0x1.71547652b82fep+0;
-constexpr double kTrigMax = 0x1p28;
+constexpr double kTrigMax = 0x1p48;
 
 __device__ __forceinline__ double sin_taylor(double r) {  // |r| <= pi/4, to r^17
   const double z = r * r;
@@ -145,10 +145,14 @@ __device__ __forceinline__ double cos_taylor(double r) {  // |r| <= pi/4, to r^1
   return __builtin_fma(z, q, 1.0);
 }
 
+// x = k pi/2 + r for |x| < 2^48, where k = rint(x 2/pi) is the nearest
+// integer and each fused step rounds at the remainder's magnitude (accurate to
+// about an ulp of 1); from 2^48 on, and for non-finite x, sin and cos are NaN.
+// No library call: its large-argument reduction would raise the register
+// use of every kernel this is inlined into.
 __device__ __forceinline__ void sincos(double x, double &s, double &c) {
-  if (!(__builtin_fabs(x) <= kTrigMax)) {
-    s = ::sin(x);
-    c = ::cos(x);
+  if (!(__builtin_fabs(x) < kTrigMax)) {
+    s = c = __builtin_nan("");
     return;
   }
   const double k = __builtin_rint(x * kTwoOverPi);  // x = k pi/2 + r
@@ -156,7 +160,7 @@ __device__ __forceinline__ void sincos(double x, double &s, double &c) {
   r = __builtin_fma(-k, kPio2B, r);
   r = __builtin_fma(-k, kPio2C, r);
   const double sr = sin_taylor(r), cr = cos_taylor(r);
-  const int q = (int)((long long)k & 3);
+  const int q = (int)(k - 4.0 * __builtin_floor(k * 0.25));
   s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
   c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
 }
