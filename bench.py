@@ -65,6 +65,9 @@ def _counts(obj, d):
         return 3 * d, 0, 7 * d
     if obj == "goldstein_price":
         return 45, 0, 75
+    if obj == "poisson_fit":  # per bin: 6 for the exponent, then exp, n e, -, +
+        from paper_2603_28770_amd.user_objectives import POISSON_BINS
+        return 10 * POISSON_BINS, 0, 10 * POISSON_BINS
     raise KeyError(obj)
 
 
@@ -132,6 +135,17 @@ def cpu_baseline(p):
 
 
 MULTI = ("uneven_batch", "served_mix")
+
+
+def _user_source(name):
+    from paper_2603_28770_amd import user_objectives as UO
+    return UO.poisson_fit_source() if name == "poisson_fit" else getattr(UO, name.upper())
+
+
+# user-code workloads: problem, the objective its source restates (for the
+# flop counts), the source
+USER_WORKLOADS = {"user_rosenbrock_d50_n131072": (W.USER_ROSENBROCK_D50, "rosenbrock"),
+                  "user_poisson_fit_n65536": (W.USER_POISSON_FIT, "poisson_fit")}
 
 
 def _totals(outs, reqs):
@@ -257,13 +271,80 @@ def run_served_mix(args, Z, ctx):
                                   "single-problem default workload"}
 
 
+def run_user(args, Z, ctx):
+    """A user objective: compiled once (zeus_objective_compile, timed apart),
+    then K solves through the blocking zeus_minimize_user, whose results are
+    copied to host memory inside the timed region.  Kernel times come from
+    HIP events on the context's stream; the roofline uses the BFGS kernel's.
+    A user restatement of a built-in objective is timed beside the built-in
+    one on the same problem, which prices the whole-form evaluation."""
+    p, model = USER_WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    obj = Z.zeus_objective_compile(ctx, _user_source(model))
+    t_compile = time.perf_counter() - t0
+
+    def timed(solve):
+        for _ in range(args.warmup):
+            solve()
+        Z.zeus_context_set_profiling(ctx, True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = solve()
+        wall = time.perf_counter() - t0
+        prof = Z.zeus_context_get_profile(ctx)
+        Z.zeus_context_set_profiling(ctx, False)
+        return wall * 1e3 / args.steps, prof, out
+
+    ms, prof, out = timed(lambda: Z.zeus_minimize_user(ctx, obj, [p])[0])
+    Z.zeus_objective_destroy(obj)
+    s = out["summary"]
+    iters = s["total_iters"]
+    bfgs_ms = prof["bfgs_ms"] / max(1, prof["bfgs_launches"])
+    flops = algorithmic_flops(model, p["dim"], p["n"], iters, s["total_ls_trials"])
+    achieved = flops / (bfgs_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": iters / (ms / 1e3), "unit": "start-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded Philox starts in the box; user objective compiled at run time)",
+        "config": {"workload": args.workload, "objective": f"user ({model})", "dim": p["dim"],
+                   "n_starts": p["n"], "iter_pso": p["iter_pso"], "iter_bfgs": p["iter_bfgs"],
+                   "grad_tol": p["grad_tol"], "precision": "fp64", "method": "bfgs"},
+        "compile_s": t_compile,
+        "converged_starts_per_s": s["n_converged"] / (ms / 1e3),
+        "start_iters_per_step": iters, "ls_trials_per_iter": s["total_ls_trials"] / max(1, iters),
+        "n_converged": s["n_converged"], "best_f": s["best_f"],
+        "kernel_ms": {"pso": prof["pso_ms"] / args.steps, "bfgs": bfgs_ms,
+                      "reduce": prof["reduce_ms"] / args.steps},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "bfgs_kernel (user objective)",
+                     "flops_per_launch": flops},
+        "note": "blocking entry point: ms_per_step includes copying the results to host memory",
+    }
+    if model in W.BOXES:  # a restated built-in objective: the built-in beside it
+        pb = dict(p, objective=model)
+        bms, bprof, bout = timed(lambda: Z.zeus_minimize(ctx, pb))
+        b_bfgs = bprof["bfgs_ms"] / max(1, bprof["bfgs_launches"])
+        line["builtin"] = {"objective": model, "ms_per_step": bms, "bfgs_ms": b_bfgs,
+                           "start_iters_per_step": bout["summary"]["total_iters"],
+                           "n_converged": bout["summary"]["n_converged"],
+                           "user_over_builtin_bfgs_time": bfgs_ms / b_bfgs}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        from oracle import user as OU
+        OU.use(_user_source(model), O.lib())   # the same source, built for the CPU
+        line["cpu_baseline"] = cpu_baseline(p)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rastrigin_d10_n65536",
-                    choices=sorted(WORKLOADS) + list(MULTI))
+                    choices=sorted(WORKLOADS) + list(MULTI) + sorted(USER_WORKLOADS))
     ap.add_argument("--n-scale", type=float, default=0.0,
                     help="multi-request workloads: multiply every request's start count")
     ap.add_argument("--requests", type=int, default=0, help="served_mix: number of requests")
@@ -322,9 +403,10 @@ def main():
                           "rows": rows}), flush=True)
         return
 
-    if args.workload in MULTI:
+    if args.workload in MULTI or args.workload in USER_WORKLOADS:
         ctx = Z.zeus_context_create(0)
-        run = run_uneven_batch if args.workload == "uneven_batch" else run_served_mix
+        run = {"uneven_batch": run_uneven_batch, "served_mix": run_served_mix}.get(
+            args.workload, run_user)
         line = run(args, Z, ctx)
         Z.zeus_context_destroy(ctx)
         print(json.dumps(line), flush=True)

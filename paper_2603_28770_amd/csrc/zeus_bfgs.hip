@@ -147,8 +147,12 @@ hipError_t launch_prec(const Group &g, int64_t want, int cus) {
 // Every tiling computes the same pairwise trees, so results do not depend on
 // it; only speed does.  The rules come from the autotuner's table; a start
 // no rule covers gets the smallest power of two >= max(dim, 4), or the block
-// above 64 dimensions.  ZEUS_TILE_LANES forces a tiling (the autotuner uses
-// it to time the candidates).
+// above 64 dimensions.  A user objective up to 8 dimensions gets 32 lanes:
+// evaluated as a whole it tries one step length per lane in a line-search
+// round, and on four user sources (d = 2..5, 1.9 to 12 trials per iteration)
+// 32 lanes took 0.71 of the time of the smallest group in geometric mean.
+// ZEUS_TILE_LANES forces a tiling (the autotuner uses it to time the
+// candidates).
 #include "zeus_tiling.inc"
 
 namespace {
@@ -168,6 +172,7 @@ int group_lanes(int objective, int precision, int dim) {
     if (r.objective == objective && r.precision == precision && dim >= r.dmin && dim <= r.dmax &&
         tiling_valid(r.lanes, dim))
       return r.lanes;
+  if (objective == kUser && dim <= 8) return 32;
   int g = 4;
   while (g < dim) g <<= 1;
   return g;

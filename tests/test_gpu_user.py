@@ -74,6 +74,24 @@ def test_user_objective_matches_oracle(Z, ctx, compiled, oracle_mod, name, src, 
               f"best f {np.nanmin(o['f']):.6g}", flush=True)
 
 
+def test_user_rosenbrock_bench_size_sample(Z, ctx, compiled, oracle_mod):
+    """The user-code Rosenbrock bench problem at full size (d = 50, 131,072
+    starts, the launch the bench times): every swarm seed equals the oracle
+    swarm's, and 32 strided starts' results equal the oracle's BFGS from those
+    seeds."""
+    p = W.USER_ROSENBROCK_D50
+    print(f"\n[user] rosenbrock d = {p['dim']}, n = {p['n']} (bench size)", flush=True)
+    g = Z.zeus_minimize_user(ctx, compiled(UO.ROSENBROCK), [p], pso_state=True)[0]
+    OU.use(UO.ROSENBROCK, oracle_mod.lib())
+    sw = oracle_mod.pso(p)
+    assert np.array_equal(g["seeds"], sw["x"])
+    idx = W.strided_subset(p["n"], 32)
+    o = oracle_mod.bfgs(p, sw["x"], idx=idx)
+    for k in KEYS:
+        assert np.array_equal(g[k][idx], o[k], equal_nan=True), k
+    print(f"[user]   sample converged {int(np.sum(o['status'] == 1))}/{idx.size}", flush=True)
+
+
 def test_user_objective_early_stop(Z, ctx, compiled, oracle_mod):
     p = _p(20, 256, -2.0, 2.0, 8)
     print("\n[user] chain_log_d20 with required_converged = 10", flush=True)
