@@ -36,6 +36,7 @@ from paper_2603_28770_amd import workloads as W  # noqa: E402
 
 METRIC = "converged starts/s & start-iters/s vs plain FP64; p50/p99 solve latency"
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 157.3  # packed FP32 (two per lane per cycle)
 
 WORKLOADS = {"rastrigin_d10_n65536": W.RASTRIGIN_D10, "rosenbrock_d2_n1024": W.ROSENBROCK_D2,
              "ackley_d50_n131072": W.ACKLEY_D50, "rosenbrock_d50_n131072": W.ROSENBROCK_D50,
@@ -90,16 +91,34 @@ def algorithmic_flops(obj, d, n_starts, total_iters, total_ls_trials, lbfgs_m=0)
     return n_starts * (grad + 2 * d) + total_iters * per_iter + total_ls_trials * (fp + 2 * d)
 
 
-def profiled_traffic(workload):
-    """HBM bytes per launch of the BFGS kernel on this workload, read from the
-    committed rocprofv3 summary (FETCH_SIZE + WRITE_SIZE scaled by a copy
-    kernel's), or None when there is none or the kernel's sources have changed
-    since it was taken."""
+def algorithmic_flops_split(obj, d, n_starts, total_iters, total_ls_trials):
+    """The same work split by the precision the mixed mode computes it in:
+    (FP64 flops: inverse-Hessian and vector work, the trial points; FP32
+    flops: objective values and dual-number gradients)."""
+    fp, fs, ft = _counts(obj, d)
+    grad = fp + fs + d * ft
+    w32 = n_starts * grad + total_iters * grad + total_ls_trials * fp
+    w64 = n_starts * 2 * d + total_iters * (6 * d * d + 14 * d) + total_ls_trials * 2 * d
+    return w64, w32
+
+
+def profile_figures(workload):
+    """The JSON block of the committed rocprofv3 summary of the BFGS kernel on
+    this workload, or None when there is none or the kernel's sources have
+    changed since it was taken."""
     from paper_2603_28770_amd import rocprof_summary as RS
     s = RS.load(os.path.join(ROOT, "profiles", f"bfgs_kernel_{workload}.md"))
     if not s or s.get("sources_sha256") != RS.sources_sha256("bfgs_kernel"):
         return None
-    return s.get("traffic_bytes")
+    return s
+
+
+def profiled_traffic(workload):
+    """HBM bytes per launch of the BFGS kernel on this workload (FETCH_SIZE +
+    WRITE_SIZE scaled by a copy kernel's), from the committed summary while it
+    is current, else None."""
+    s = profile_figures(workload)
+    return s.get("traffic_bytes") if s else None
 
 
 def cpu_baseline(p):
@@ -468,7 +487,7 @@ def main():
     mixed = None
     if not args.no_mixed and p.get("precision", "fp64") == "fp64":
         pm = dict(p, precision="mixed", grad_tol=max(p["grad_tol"], 1e-4))
-        mwall, _, mlat, mout = timed(pm)
+        mwall, mprof, mlat, mout = timed(pm)
         ms = mout["summary"]
         mms = mwall * 1e3 / args.steps
         fstar_m = W.f_star(pm["objective"], pm["dim"])
@@ -479,6 +498,15 @@ def main():
                  "p99_solve_ms": float(np.percentile(mlat, 99)),
                  "success_rate": float(np.mean(mout["f"] - fstar_m < 1e-4)),
                  "speedup_vs_fp64": (wall * 1e3 / args.steps) / mms}
+        # t_ideal = W64 / FP64 peak + W32 / FP32 peak, against the BFGS kernel's time
+        m_bfgs = mprof["bfgs_ms"] / max(1, mprof["bfgs_launches"])
+        w64, w32 = algorithmic_flops_split(pm["objective"], pm["dim"], pm["n"], ms["total_iters"],
+                                           ms["total_ls_trials"])
+        t_ideal = w64 / (FP64_VALU_PEAK_TFLOPS * 1e12) + w32 / (FP32_VALU_PEAK_TFLOPS * 1e12)
+        mixed["roofline"] = {"bound": "alu", "bfgs_ms": m_bfgs, "w64_flops": w64, "w32_flops": w32,
+                             "peak_fp64": FP64_VALU_PEAK_TFLOPS, "peak_fp32": FP32_VALU_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "t_ideal_ms": t_ideal * 1e3,
+                             "frac": t_ideal * 1e3 / m_bfgs}
 
     ms_per_step = wall * 1e3 / args.steps
     iters = s["total_iters"]
@@ -510,6 +538,11 @@ def main():
                      "traffic": profiled_traffic(args.workload), "kernel": "bfgs_kernel",
                      "flops_per_launch": flops},
     }
+    pf = profile_figures(args.workload)
+    if pf and "counter_fp64_tflops" in pf:
+        # FP64 work the SQ counters saw (every lane of a wave, padding included)
+        line["roofline"]["counter_achieved"] = pf["counter_fp64_tflops"]
+        line["roofline"]["valu_busy"] = pf.get("valu_busy")
     line["graph"] = graph
     if args.required_c > 0:
         # time to required_c convergences against the full solve, both through

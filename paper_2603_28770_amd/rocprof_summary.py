@@ -12,6 +12,14 @@ The copy fixes what the counters read per byte actually moved: its reads and
 writes are both exactly ``copy-bytes``, so each counter of the workload is
 scaled by copy-bytes / (what the counter read for the copy).
 
+Optional ``--mix`` databases come from ``rocprofv3 --pmc`` passes of SQ
+instruction counters on the same workload; from them the summary adds the
+kernel's instruction mix and its FP64 rate as the counters see it:
+64 lanes x (2 FMA + ADD + MUL + transcendental) FP64 wave instructions per
+dispatch over the average duration (padding lanes included).  The VALU busy
+share is 4 SQ_ACTIVE_INST_VALU / (32 SQ_BUSY_CYCLES): the wave counters count
+in units of four cycles, and each of the 32 SQs serves 32 SIMDs.
+
 The summary ends with a JSON block (kernel, workload, average duration,
 scaled HBM bytes per dispatch, and a SHA-256 of the kernel's sources at
 summary time), which ``bench.py`` reads to report measured traffic only while
@@ -81,6 +89,8 @@ def main(argv=None):
     ap.add_argument("--copy-bytes", type=int, required=True)
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--note", default="")
+    ap.add_argument("--mix", action="append", default=[],
+                    help="rocprofv3 --pmc database with SQ instruction counters (repeatable)")
     args = ap.parse_args(argv)
 
     stats = kernel_stats(args.trace)
@@ -128,6 +138,25 @@ def main(argv=None):
                "read_bytes": fb, "write_bytes": wb,
                "traffic_bytes": (fb + wb) if fb is not None else None,
                "sources_sha256": sources_sha256(args.kernel)}
+    if args.mix:
+        mix = {}
+        for db in args.mix:
+            c = sqlite3.connect(db)
+            for kn, cn, v in c.execute("select kernel_name, counter_name, avg(value) "
+                                       "from counters_collection group by kernel_name, counter_name"):
+                if _short(kn) == mk["kernel"]:
+                    mix[cn] = v
+        lines += ["", "## Instruction mix of the main kernel per dispatch (PMC)", "",
+                  "| counter | value |", "|---|---|"]
+        lines += [f"| {k} | {v:.4g} |" for k, v in sorted(mix.items())]
+        f64 = [mix.get("SQ_INSTS_VALU_" + k) for k in ("FMA_F64", "ADD_F64", "MUL_F64")]
+        if all(v is not None for v in f64):
+            flops = 64.0 * (2.0 * f64[0] + f64[1] + f64[2] + mix.get("SQ_INSTS_VALU_TRANS_F64", 0.0))
+            summary["counter_fp64_flops"] = flops
+            summary["counter_fp64_tflops"] = flops / (mk["avg_us"] * 1e-6) / 1e12
+        if "SQ_ACTIVE_INST_VALU" in mix and "SQ_BUSY_CYCLES" in mix:
+            summary["valu_busy"] = 4.0 * mix["SQ_ACTIVE_INST_VALU"] / (32.0 * mix["SQ_BUSY_CYCLES"])
+        summary["mix"] = mix
     lines += ["", "## Figures used by bench.py", "", "```json", json.dumps(summary, indent=1), "```", ""]
     os.makedirs(os.path.dirname(os.path.abspath(args.o)), exist_ok=True)
     with open(args.o, "w") as f:
