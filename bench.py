@@ -121,16 +121,18 @@ def profiled_traffic(workload):
     return s.get("traffic_bytes") if s else None
 
 
-def cpu_baseline(p):
+def cpu_baseline(p, sub=256, sub1=None):
     """The oracle on the full workload: its sequential PSO, then BFGS from every
-    start with OpenMP over starts on all threads it is given."""
+    start with OpenMP over starts on all threads it is given (above d = 20
+    from `sub` strided starts; on one thread from `sub1`, default 1024 up to
+    d = 20 and 64 above)."""
     from oracle import oracle as O
     t0 = time.perf_counter()
     sw = O.pso(p)
     t1 = time.perf_counter()
     idx = None
     if p["dim"] > 20:  # large problems: a strided subset of starts (exact per start)
-        idx = W.strided_subset(p["n"], 256)
+        idx = W.strided_subset(p["n"], sub)
     r = O.bfgs(p, sw["x"], idx=idx)
     t2 = time.perf_counter()
     m = p["n"] if idx is None else idx.size
@@ -140,7 +142,7 @@ def cpu_baseline(p):
               f"from {m} of {p['n']} starts; {t1 - t0:.2f} s swarm + {t2 - t1:.2f} s BFGS")
     # one core: the same swarm (sequential already) and BFGS on one thread
     # over a strided subset of the starts
-    idx1 = W.strided_subset(p["n"], 1024 if p["dim"] <= 20 else 64)
+    idx1 = W.strided_subset(p["n"], sub1 or (1024 if p["dim"] <= 20 else 64))
     t3 = time.perf_counter()
     r1 = O.bfgs(p, sw["x"], idx=idx1, nthreads=1)
     t4 = time.perf_counter()
@@ -164,6 +166,7 @@ def _user_source(name):
 # user-code workloads: problem, the objective its source restates (for the
 # flop counts), the source
 USER_WORKLOADS = {"user_rosenbrock_d50_n131072": (W.USER_ROSENBROCK_D50, "rosenbrock"),
+                  "user_rosenbrock_d200_n8192_lbfgs8": (W.USER_ROSENBROCK_D200_LBFGS, "rosenbrock"),
                   "user_poisson_fit_n65536": (W.USER_POISSON_FIT, "poisson_fit")}
 
 
@@ -319,7 +322,8 @@ def run_user(args, Z, ctx):
     s = out["summary"]
     iters = s["total_iters"]
     bfgs_ms = prof["bfgs_ms"] / max(1, prof["bfgs_launches"])
-    flops = algorithmic_flops(model, p["dim"], p["n"], iters, s["total_ls_trials"])
+    lm = p.get("lbfgs_m", 0)
+    flops = algorithmic_flops(model, p["dim"], p["n"], iters, s["total_ls_trials"], lm)
     achieved = flops / (bfgs_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC, "value": iters / (ms / 1e3), "unit": "start-iters/s", "n_gpus": 1,
@@ -328,7 +332,8 @@ def run_user(args, Z, ctx):
         "data": "synthetic (seeded Philox starts in the box; user objective compiled at run time)",
         "config": {"workload": args.workload, "objective": f"user ({model})", "dim": p["dim"],
                    "n_starts": p["n"], "iter_pso": p["iter_pso"], "iter_bfgs": p["iter_bfgs"],
-                   "grad_tol": p["grad_tol"], "precision": "fp64", "method": "bfgs"},
+                   "grad_tol": p["grad_tol"], "precision": "fp64",
+                   "method": f"lbfgs_m{lm}" if lm else "bfgs"},
         "compile_s": t_compile,
         "converged_starts_per_s": s["n_converged"] / (ms / 1e3),
         "start_iters_per_step": iters, "ls_trials_per_iter": s["total_ls_trials"] / max(1, iters),
@@ -337,7 +342,8 @@ def run_user(args, Z, ctx):
                       "reduce": prof["reduce_ms"] / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "bfgs_kernel (user objective)",
+                     "traffic": None,
+                     "kernel": f"{'lbfgs' if lm else 'bfgs'}_kernel (user objective)",
                      "flops_per_launch": flops},
         "note": "blocking entry point: ms_per_step includes copying the results to host memory",
     }
@@ -353,7 +359,8 @@ def run_user(args, Z, ctx):
         from oracle import oracle as O
         from oracle import user as OU
         OU.use(_user_source(model), O.lib())   # the same source, built for the CPU
-        line["cpu_baseline"] = cpu_baseline(p)
+        # whole-form gradients cost d evaluations: fewer sampled starts above d = 64
+        line["cpu_baseline"] = cpu_baseline(p, 64, 8) if p["dim"] > 64 else cpu_baseline(p)
     return line
 
 

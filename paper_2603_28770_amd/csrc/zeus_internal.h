@@ -87,12 +87,15 @@ struct BatchDev {
 };
 
 // Kernels of a user objective, compiled at run time (zeus_user.cpp): the
-// module and its swarm and BFGS kernels by log2 of the lanes per particle /
-// per start (hipModule_t and hipFunction_t handles).
+// module, its swarm kernels by log2 of the coordinate slots per particle
+// (2..256), its BFGS kernels by log2 of the lanes per start (4..64) and its
+// L-BFGS kernels by log2 of the coordinate slots per start (4..256)
+// (hipModule_t and hipFunction_t handles).
 struct UserKernels {
   void *module;
-  void *pso[7];
+  void *pso[9];
   void *bfgs[7];
+  void *lbfgs[9];
 };
 
 // A launch group: device table of nreq requests plus its counters.
@@ -132,11 +135,14 @@ hipError_t launch_lbfgs(const Group &g, int cus);
 // wavefront covers up to 256).
 int lbfgs_slots(int dim);
 hipError_t launch_summary(const Group &g);
-// User objectives: swarm sweep and (d <= 64) BFGS launches of the compiled
-// kernels, and the dynamic LDS of a BFGS block with `lanes` lanes per start.
+// User objectives: swarm sweep, (d <= 64) BFGS and L-BFGS launches of the
+// compiled kernels, and the dynamic LDS of a BFGS block with `lanes` lanes per
+// start and of an L-BFGS block with `slots` coordinate slots per start.
 hipError_t launch_user_pso(const Group &g, int t);
 hipError_t launch_user_bfgs(const Group &g, int64_t want, int cus);
+hipError_t launch_user_lbfgs(const Group &g, int cus);
 size_t bfgs_lds_bytes(int lanes);
+size_t lbfgs_lds_bytes(int slots);
 
 // Lanes per start of the BFGS kernels for a problem (power of two >= dim, at
 // most 64, or kWideLanes for one block per start), from the tiling table.

@@ -1,349 +1,9 @@
-// zeus_lbfgs.hip -- limited-memory BFGS on gfx950: the BFGS run of Alg. 4 /
-// Alg. 10 with the dual-number gradient of Alg. 5 and the Armijo search of
-// Alg. 6, but the search direction comes from the m most recent (s, y) pairs
-// by the two-loop recursion (Nocedal and Wright, "Numerical Optimization",
-// 2nd ed., Alg. 7.4; H0 = gamma I with gamma = s'y / y'y of the newest pair,
-// their eq. 7.20), the remedy the paper names for the O(d^2) update.
-//
-// Mapping: one group of G lanes per start (G a power of two <= 64, so a group
-// never spans two wavefronts); lane j owns coordinates j, j + G, ..., j +
-// (CPL-1) G, so a single wavefront covers up to 256 coordinates.  Each lane
-// keeps its coordinates of the stored pairs in registers (2 m CPL doubles);
-// there is no d x d matrix anywhere.  Sums over coordinates are the pairwise
-// trees used everywhere (a lane butterfly per block of G slots, then the CPL
-// block sums pairwise).  The claim loop, termination, mixed precision and
-// retirement follow the BFGS kernel.
-#include "zeus_bfgs_common.h"
+// zeus_lbfgs.hip -- limited-memory BFGS on gfx950: the launches (the
+// kernel template is in zeus_lbfgs_kernels.h).
+#include "zeus_lbfgs_kernels.h"
 
 namespace zeus {
 namespace {
-
-constexpr int kHist = kLbfgsMaxHistory;  // pairs kept in registers (m <= kHist)
-
-// Per-group LDS slice: the point under evaluation and the search direction
-// (the line search reads both in full), the step lengths and the request.
-__device__ __host__ __forceinline__ constexpr int lbfgs_stride(int slots) {
-  return 2 * slots + kTabTrials + kHotDoubles;
-}
-
-// sum over the group's G * CPL coordinate slots of a[c] b[c] (pairwise).
-template <int G, int CPL>
-__device__ __forceinline__ double slot_dot(const double (&a)[CPL], const double (&b)[CPL]) {
-  double blk[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) blk[c] = lane_tree_sum<G, double>(a[c] * b[c]);
-  return reg_tree_sum<CPL, double>(blk);
-}
-
-// Value and gradient at xs in number type T for coordinates j + G c (see
-// group_value_grad: the same per-coordinate dual terms, the value summed over
-// all G * CPL term slots).
-template <int OBJ, int G, int CPL, class T>
-__device__ __forceinline__ double value_grad_slots(const GroupLanes<G> &L, int d, const double *xs,
-                                                   double (&gj)[CPL]) {
-  using E = Elem<OBJ>;
-  static_assert(E::W <= 2, "the tangent sum assumes at most two terms per coordinate");
-  const int m = E::terms(d);
-  T val[E::K][CPL], tan[E::K][CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    const int jj = L.j + G * c;
-#pragma unroll
-    for (int k = 0; k < E::K; ++k) {
-      tan[k][c] = T(0);
-      val[k][c] = T(0);
-    }
-    // evaluated on every lane (indices clamped), a missing term contributing
-    // an exact zero, so the loads are not behind branches
-#pragma unroll
-    for (int back = E::W - 1; back >= 0; --back) {
-      const int i = jj - back;
-      const bool valid = jj < d && i >= 0 && i < m;
-      dual<T> w[E::W], out[E::K];
-#pragma unroll
-      for (int q = 0; q < E::W; ++q) {
-        int iq = i + q < 0 ? 0 : i + q;
-        iq = iq < G * CPL ? iq : G * CPL - 1;
-        w[q] = dual<T>{(T)xs[iq], q == back ? T(1) : T(0)};
-      }
-      E::template term<dual<T>>(w, out);
-#pragma unroll
-      for (int k = 0; k < E::K; ++k) tan[k][c] = tan[k][c] + (valid ? out[k].t : T(0));
-      if (back == 0)
-#pragma unroll
-        for (int k = 0; k < E::K; ++k) val[k][c] = valid ? out[k].v : T(0);
-    }
-  }
-  T sv[E::K];
-#pragma unroll
-  for (int k = 0; k < E::K; ++k) {
-    T blk[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) blk[c] = lane_tree_sum<G, T>(val[k][c]);
-    sv[k] = reg_tree_sum<CPL, T>(blk);
-  }
-  double fv = 0.0;
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    dual<T> sd[E::K];
-#pragma unroll
-    for (int k = 0; k < E::K; ++k) sd[k] = dual<T>{sv[k], tan[k][c]};
-    const dual<T> r = E::template outer<dual<T>>(d, sd);
-    gj[c] = (L.j + G * c < d) ? (double)r.t : 0.0;
-    fv = (double)r.v;
-  }
-  return fv;
-}
-
-template <int OBJ, int G, int CPL, class T>
-__device__ __forceinline__ double value_slots(const GroupLanes<G> &L, int d, const double *xs) {
-  return group_value_slots<OBJ, G, CPL, T>(L, d, xs);
-}
-
-// Two waves per SIMD for the 4-coordinate kernels of the polynomial
-// objectives, which then fit 256 registers without spilling (the
-// transcendental ones would spill over a hundred and stay at one wave).
-template <int OBJ, int CPL>
-constexpr int kLbfgsWaves = CPL == 4 && OBJ != kRastrigin && OBJ != kAckley ? 2 : 1;
-
-template <int OBJ, int G, int CPL, class T>
-__global__ __launch_bounds__(kBfgsBlock) __attribute__((amdgpu_waves_per_eu(kLbfgsWaves<OBJ, CPL>)))
-void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
-  constexpr bool kMixed = sizeof(T) != sizeof(double);
-  constexpr int S = 64 / G;  // groups per wave
-  constexpr int SLOTS = G * CPL;
-  extern __shared__ double smem[];
-  const GroupLanes<G> L;
-  const int j = L.j;
-  double *xs, *ps, *al;
-  ReqHot *qh;
-  {
-    double *base = smem + (size_t)((threadIdx.x >> 6) * S + L.grp) * lbfgs_stride(SLOTS);
-    xs = base;
-    ps = base + SLOTS;
-    al = base + 2 * SLOTS;
-    qh = reinterpret_cast<ReqHot *>(al + kTabTrials);
-  }
-
-  bool own[CPL];
-  double xj[CPL], gj[CPL], pj[CPL], sj[CPL];
-  double hs[kHist][CPL], hy[kHist][CPL], hrho[kHist];  // pairs, oldest first
-  int count = 0;                                         // pairs stored
-  double f = 0.0;
-  int64_t idx = -1;
-  int k = 0, ls_trials = 0;
-  bool fresh = false, first = true;
-  bool hi = !kMixed;
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) own[c] = false, xj[c] = gj[c] = pj[c] = sj[c] = 0.0;
-
-  for (;;) {
-    // -- claim a start when idle (as the BFGS kernel) -----------------------
-    if (idx < 0) {
-      const unsigned long long groups = (unsigned long long)gridDim.x * (kBfgsBlock / G);
-      unsigned long long got = 0;
-      if (first) {
-        got = (unsigned long long)blockIdx.x * (kBfgsBlock / G) + (threadIdx.x >> 6) * S + L.grp;
-        first = false;
-      } else {
-        if (j == 0) got = groups + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
-        got = __shfl(got, L.grp * G, 64);
-      }
-      if (got >= (unsigned long long)total) break;
-      const int ri = request_of(reqs, nreq, (int64_t)got);
-      const ReqDev &rq = reqs[ri];
-      idx = (int64_t)got - rq.start_offset;
-      const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(*qh, rq, ri);
-      fill_step_lengths(al, rq.shrink, j, G);
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int jj = j + G * c;
-        own[c] = jj < d0;
-        xj[c] = own[c] ? rq.ws.x[idx * d0 + jj] : 0.0;  // x <- swarm[i]
-        xs[jj] = xj[c];
-      }
-      count = 0;
-      k = 0;
-      ls_trials = 0;
-      fresh = true;
-      hi = !kMixed;
-    }
-    wave_sync();
-    const ReqHot &q = *qh;
-    const int d = q.d;
-
-    // -- value and gradient at xs ---------------------------------------------
-    double gn[CPL];
-    double fn;
-    if (hi)
-      fn = value_grad_slots<OBJ, G, CPL, double>(L, d, xs, gn);
-    else
-      fn = value_grad_slots<OBJ, G, CPL, T>(L, d, xs, gn);
-
-    // -- after a step: keep (s, y) when y's > 0, dropping the oldest pair ----
-    if (!fresh) {
-      double yj[CPL];
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) yj[c] = gn[c] - gj[c];
-      const double sy = slot_dot<G, CPL>(yj, sj);
-      if (sy > 0.0) {
-        const int m = q.m_hist;
-        if (count == m) {  // full: shift the pairs one place towards the front
-#pragma unroll
-          for (int i = 0; i + 1 < kHist; ++i)
-            if (i + 1 < m) {
-#pragma unroll
-              for (int c = 0; c < CPL; ++c) {
-                hs[i][c] = hs[i + 1][c];
-                hy[i][c] = hy[i + 1][c];
-              }
-              hrho[i] = hrho[i + 1];
-            }
-          --count;
-        }
-        const double rho = 1.0 / sy;
-#pragma unroll
-        for (int i = 0; i < kHist; ++i)
-          if (i == count) {
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-              hs[i][c] = sj[c];
-              hy[i][c] = yj[c];
-            }
-            hrho[i] = rho;
-          }
-        ++count;
-      }
-      ++k;
-    }
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) gj[c] = gn[c];
-    f = fn;
-    fresh = false;
-    if (q.trace_len && k < q.trace_len)
-#pragma unroll
-      for (int c = 0; c < CPL; ++c)
-        if (own[c]) reqs[q.ri].trace[(idx * q.trace_len + k) * d + j + G * c] = xj[c];
-
-    // -- termination -------------------------------------------------------------
-    bool bad = !__builtin_isfinite(f);
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) bad = bad || (own[c] && !__builtin_isfinite(gj[c]));
-    const bool any_bad = L.ballot(bad) != 0ull;
-    const double gg = slot_dot<G, CPL>(gj, gj);
-    if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * q.tol)) {
-      hi = true;  // escalate: re-evaluate this point in FP64
-      fresh = true;
-      continue;
-    }
-    int status = -1;
-    if (any_bad)
-      status = ZEUS_ST_NONFINITE;
-    else if (sqrt(gg) < q.tol)
-      status = ZEUS_ST_CONVERGED;
-    else if (k == q.iter_bfgs)
-      status = q.stop_status;
-    if (status >= 0) {
-      const ReqDev &rq = reqs[q.ri];
-      const int tl = q.trace_len;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c)
-        if (own[c]) rq.out_x[idx * d + j + G * c] = xj[c];
-      if (kMixed && !hi) f = value_slots<OBJ, G, CPL, double>(L, d, xs);
-      if (j == 0) {
-        rq.out_f[idx] = f;
-        rq.out_iters[idx] = k;
-        rq.out_status[idx] = status;
-        if (rq.out_ls) rq.out_ls[idx] = ls_trials;
-      }
-      if (tl)
-#pragma unroll
-        for (int c = 0; c < CPL; ++c)
-          if (own[c])
-            for (int kk = k + 1; kk < tl; ++kk)
-              rq.trace[(idx * tl + kk) * d + j + G * c] = __builtin_nan("");
-      idx = -1;
-      continue;
-    }
-
-    // -- search direction: two-loop recursion over the stored pairs -------------
-    double qv[CPL], alpha[kHist];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) qv[c] = gj[c];
-#pragma unroll
-    for (int i = kHist - 1; i >= 0; --i) {
-      alpha[i] = 0.0;
-      if (i < count) {  // newest pair first: alpha_i = rho_i s_i'q, q <- q - alpha_i y_i
-        alpha[i] = hrho[i] * slot_dot<G, CPL>(hs[i], qv);
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) qv[c] = __builtin_fma(-alpha[i], hy[i][c], qv[c]);
-      }
-    }
-    if (count > 0) {  // r = gamma q, gamma = s'y / y'y of the newest pair
-      double sn[CPL], yn[CPL];
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) sn[c] = yn[c] = 0.0;
-#pragma unroll
-      for (int i = 0; i < kHist; ++i)
-        if (i == count - 1)
-#pragma unroll
-          for (int c = 0; c < CPL; ++c) {
-            sn[c] = hs[i][c];
-            yn[c] = hy[i][c];
-          }
-      const double gamma = slot_dot<G, CPL>(sn, yn) / slot_dot<G, CPL>(yn, yn);
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) qv[c] = gamma * qv[c];
-    }
-#pragma unroll
-    for (int i = 0; i < kHist; ++i)
-      if (i < count) {  // oldest pair first: beta = rho_i y_i'r, r <- r + (alpha_i - beta) s_i
-        const double beta = hrho[i] * slot_dot<G, CPL>(hy[i], qv);
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) qv[c] = __builtin_fma(alpha[i] - beta, hs[i][c], qv[c]);
-      }
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) pj[c] = own[c] ? -qv[c] : 0.0;
-    double ddir = slot_dot<G, CPL>(gj, pj);
-    if (!(ddir < 0.0)) {  // not a descent direction: forget the pairs, p = -g
-      count = 0;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) pj[c] = own[c] ? -gj[c] : 0.0;
-      ddir = slot_dot<G, CPL>(gj, pj);
-    }
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) ps[j + G * c] = pj[c];
-    wave_sync();
-
-    // -- Armijo backtracking ---------------------------------------------------
-    int taken;
-    if (hi) {
-      taken = armijo_search<OBJ, G, SLOTS, double>(L, xs, ps, al, q, f, ddir);
-    } else {
-      taken = armijo_search<OBJ, G, SLOTS, T>(L, xs, ps, al, q, f, ddir);
-      if (taken < 0) {
-        ls_trials += q.iter_ls;
-        hi = true;
-        fresh = true;
-        continue;
-      }
-    }
-    const int nshrink = taken >= 0 ? taken : q.iter_ls;
-    ls_trials += taken >= 0 ? taken + 1 : q.iter_ls;
-    const double a = step_length(al, q.shrink, nshrink);
-
-    // -- step ---------------------------------------------------------------------
-    wave_sync();  // every lane has read xs and ps in the line search
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const double xnew = xj[c] + a * pj[c];
-      sj[c] = own[c] ? xnew - xj[c] : 0.0;
-      xj[c] = own[c] ? xnew : 0.0;
-      xs[j + G * c] = xj[c];
-    }
-  }
-}
 
 template <int OBJ, int G, int CPL, class T>
 hipError_t launch_l(const Group &g, int cus) {
@@ -392,6 +52,11 @@ hipError_t launch_l_prec(const Group &g, int cus) {
 
 }  // namespace
 
+size_t lbfgs_lds_bytes(int slots) {
+  const int lanes = slots < 64 ? slots : 64;
+  return sizeof(double) * (size_t)lbfgs_stride(slots) * (kBfgsBlock / lanes);
+}
+
 int lbfgs_slots(int dim) {
   int s = 4;
   while (s < dim) s <<= 1;
@@ -399,6 +64,7 @@ int lbfgs_slots(int dim) {
 }
 
 hipError_t launch_lbfgs(const Group &g, int cus) {
+  if (g.objective == kUser) return launch_user_lbfgs(g, cus);
   if (g.precision == ZEUS_MIXED) return launch_l_prec<float>(g, cus);
   return launch_l_prec<double>(g, cus);
 }

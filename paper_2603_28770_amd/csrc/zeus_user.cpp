@@ -2,8 +2,10 @@
 // templates with the user's source (hipRTC) and their launches.
 //
 // The program is zeus_user.h, the user's source, zeus_user_elem.h and the
-// swarm and BFGS kernel templates, instantiated for kUser at every lane count
-// (swarm: 2..64 lanes per particle; BFGS: 4..64 lanes per start, FP64).  The
+// swarm, BFGS and L-BFGS kernel templates, instantiated for kUser at every
+// size (swarm: 2..256 coordinate slots per particle, one per lane up to 64
+// lanes and 2 or 4 per lane beyond; BFGS: 4..64 lanes per start; L-BFGS:
+// 4..256 coordinate slots per start; FP64).  The
 // headers are compiled into the library as text (zeus_rtc_headers.inc,
 // generated from the sources by the build), so the same template code runs
 // for built-in and user objectives.  The build's code-generation flags are
@@ -60,7 +62,8 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
   prog += "#include \"zeus_user.h\"\n";
   prog += "#line 1 \"objective\"\n";
   prog += source;
-  prog += "\n#include \"zeus_user_elem.h\"\n#include \"zeus_pso_kernels.h\"\n#include \"zeus_bfgs_kernels.h\"\n";
+  prog += "\n#include \"zeus_user_elem.h\"\n#include \"zeus_pso_kernels.h\"\n"
+          "#include \"zeus_bfgs_kernels.h\"\n#include \"zeus_lbfgs_kernels.h\"\n";
   std::vector<const char *> names, texts;
   for (int i = 0; i < kRtcHeaderCount; ++i) {
     names.push_back(kRtcHeaders[i].name);
@@ -76,14 +79,23 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
     *log = "hiprtcCreateProgram failed";
     return 2;
   }
-  std::vector<std::string> pso_expr, bfgs_expr;
-  for (int l = 1; l <= 6; ++l) {
-    pso_expr.push_back("&zeus::pso_kernel<7, " + std::to_string(1 << l) + ", 1>");
+  // slots 2^l as lanes x coordinates per lane
+  auto split = [](int l) {
+    const int s = 1 << l, lanes = s < 64 ? s : 64;
+    return std::to_string(lanes) + ", " + std::to_string(s / lanes);
+  };
+  std::vector<std::string> pso_expr, bfgs_expr, lbfgs_expr;
+  for (int l = 1; l <= 8; ++l) {
+    pso_expr.push_back("&zeus::pso_kernel<7, " + split(l) + ">");
     hiprtcAddNameExpression(p, pso_expr.back().c_str());
   }
   for (int l = 2; l <= 6; ++l) {
     bfgs_expr.push_back("&zeus::bfgs_kernel<7, " + std::to_string(1 << l) + ", double>");
     hiprtcAddNameExpression(p, bfgs_expr.back().c_str());
+  }
+  for (int l = 2; l <= 8; ++l) {
+    lbfgs_expr.push_back("&zeus::lbfgs_kernel<7, " + split(l) + ", double>");
+    hiprtcAddNameExpression(p, lbfgs_expr.back().c_str());
   }
   const std::string arch_opt = std::string("--offload-arch=") + arch;
   const char *opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
@@ -102,17 +114,17 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
   hiprtcGetCodeSize(p, &cs);
   std::vector<char> code(cs);
   hiprtcGetCode(p, code.data());
-  std::vector<std::string> pso_names, bfgs_names;
-  for (auto &e : pso_expr) {
-    const char *n = nullptr;
-    hiprtcGetLoweredName(p, e.c_str(), &n);
-    pso_names.push_back(n ? n : "");
-  }
-  for (auto &e : bfgs_expr) {
-    const char *n = nullptr;
-    hiprtcGetLoweredName(p, e.c_str(), &n);
-    bfgs_names.push_back(n ? n : "");
-  }
+  auto lowered = [&](const std::vector<std::string> &exprs) {
+    std::vector<std::string> out_names;
+    for (auto &e : exprs) {
+      const char *n = nullptr;
+      hiprtcGetLoweredName(p, e.c_str(), &n);
+      out_names.push_back(n ? n : "");
+    }
+    return out_names;
+  };
+  const std::vector<std::string> pso_names = lowered(pso_expr), bfgs_names = lowered(bfgs_expr),
+                                 lbfgs_names = lowered(lbfgs_expr);
   hiprtcDestroyProgram(&p);
   if (!load) return 0;
   hipModule_t mod;
@@ -122,7 +134,7 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
     return 2;
   }
   out->module = mod;
-  for (int l = 1; l <= 6; ++l) {
+  for (int l = 1; l <= 8; ++l) {
     hipFunction_t f;
     if ((he = hipModuleGetFunction(&f, mod, pso_names[l - 1].c_str())) != hipSuccess) break;
     out->pso[l] = f;
@@ -131,6 +143,11 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
     hipFunction_t f;
     if ((he = hipModuleGetFunction(&f, mod, bfgs_names[l - 2].c_str())) != hipSuccess) break;
     out->bfgs[l] = f;
+  }
+  for (int l = 2; he == hipSuccess && l <= 8; ++l) {
+    hipFunction_t f;
+    if ((he = hipModuleGetFunction(&f, mod, lbfgs_names[l - 2].c_str())) != hipSuccess) break;
+    out->lbfgs[l] = f;
   }
   if (he != hipSuccess) {
     *log = std::string("hipModuleGetFunction: ") + hipGetErrorString(he);
@@ -148,7 +165,7 @@ void user_release(UserKernels *k) {
 
 hipError_t launch_user_pso(const Group &g, int t) {
   const int l = log2_of(g.g_pso);
-  if (!g.user || l < 1 || l > 6 || !g.user->pso[l]) return hipErrorInvalidValue;
+  if (!g.user || l < 1 || l > 8 || !g.user->pso[l]) return hipErrorInvalidValue;
   const ReqDev *reqs = g.reqs;
   int nreq = g.nreq;
   void *args[] = {&reqs, &nreq, &t};
@@ -165,6 +182,31 @@ hipError_t launch_user_bfgs(const Group &g, int64_t want, int cus) {
   hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBfgsBlock, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
+  const int64_t cap = (int64_t)cus * per_cu;
+  const unsigned blocks = (unsigned)(want < cap ? want : cap);
+  const ReqDev *reqs = g.reqs;
+  int nreq = g.nreq;
+  BatchDev *hdr = g.hdr;
+  int64_t total = g.total_starts;
+  void *args[] = {&reqs, &nreq, &hdr, &total};
+  return hipModuleLaunchKernel(f, blocks, 1, 1, kBfgsBlock, 1, 1, (unsigned)lds, g.stream, args, nullptr);
+}
+
+// The persistent L-BFGS kernel of `g.g_bfgs` coordinate slots: as many
+// blocks as can be resident, at most one group per start.
+hipError_t launch_user_lbfgs(const Group &g, int cus) {
+  const int l = log2_of(g.g_bfgs);
+  if (!g.user || l < 2 || l > 8 || (1 << l) != g.g_bfgs || !g.user->lbfgs[l])
+    return hipErrorInvalidValue;
+  hipFunction_t f = static_cast<hipFunction_t>(g.user->lbfgs[l]);
+  const int lanes = g.g_bfgs < 64 ? g.g_bfgs : 64;
+  const size_t lds = lbfgs_lds_bytes(g.g_bfgs);
+  int per_cu = 0;
+  hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBfgsBlock, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  const int64_t per_block = kBfgsBlock / lanes;
+  const int64_t want = (g.total_starts + per_block - 1) / per_block;
   const int64_t cap = (int64_t)cus * per_cu;
   const unsigned blocks = (unsigned)(want < cap ? want : cap);
   const ReqDev *reqs = g.reqs;

@@ -3,7 +3,8 @@ against the oracle running the same source compiled for the CPU: swarm seeds
 and every start's f, x, iterations, status and line-search trials bit for
 bit, for one to four requests per call (a Goldstein-Price batch), every lane
 count from 4 to 64, trigonometric, logarithmic and exponential user code
-(a binned Poisson likelihood fit), and early stop; plus the refusals."""
+(a binned Poisson likelihood fit), L-BFGS from d = 5 to d = 200 (one, two and
+four coordinates per lane), and early stop; plus the refusals."""
 import numpy as np
 import pytest
 
@@ -46,6 +47,12 @@ CASES = [
     ("chain_log_d20", UO.CHAIN_LOG, [_p(20, 256, -2.0, 2.0, 4)]),
     ("chain_log_d40", UO.CHAIN_LOG, [_p(40, 128, -2.0, 2.0, 5, iter_bfgs=200)]),
     ("poisson_fit_d4", "poisson", [_p(4, 512, 0.0, 10.0, 6, iter_pso=10, iter_bfgs=500)]),
+    # L-BFGS: one coordinate per lane, then two and four per lane (d > 64)
+    ("chain_log_d20_lbfgs", UO.CHAIN_LOG, [_p(20, 256, -2.0, 2.0, 11, lbfgs_m=5)]),
+    ("rastrigin_d5_lbfgs", UO.RASTRIGIN, [_p(5, 300, -5.12, 5.12, 12, lbfgs_m=3)]),
+    ("chain_log_d100_lbfgs", UO.CHAIN_LOG, [_p(100, 96, -2.0, 2.0, 13, lbfgs_m=6, iter_bfgs=150)]),
+    ("rosenbrock_d200_lbfgs", UO.ROSENBROCK,
+     [_p(200, 64, -2.0, 2.0, 14, iter_pso=2, lbfgs_m=8, iter_bfgs=150)]),
 ]
 
 
@@ -127,7 +134,8 @@ def test_poisson_fit_recovers_the_spectrum(Z, ctx, compiled, oracle_mod):
 def test_user_refusals(Z, ctx, compiled):
     obj = compiled(UO.ROSENBROCK)
     for bad, code in ((dict(dim=65), Z.EUNSUPPORTED), (dict(precision="mixed"), Z.EUNSUPPORTED),
-                      (dict(lbfgs_m=4), Z.EUNSUPPORTED), (dict(objective="rosenbrock"), Z.EINVAL)):
+                      (dict(dim=257, lbfgs_m=4), Z.EUNSUPPORTED), (dict(lbfgs_m=9), Z.EUNSUPPORTED),
+                      (dict(objective="rosenbrock"), Z.EINVAL)):
         with pytest.raises(Z.ZeusError) as e:
             Z.zeus_minimize_user(ctx, obj, [dict(_p(3, 16, -1.0, 1.0, 0), **bad)])
         assert e.value.code == code, bad
