@@ -290,3 +290,16 @@ def test_full_size_rastrigin_sampled(Z, ctx, oracle_mod):
     _check_pso(g, sw, True)
     _check_bfgs(g, o, p, idx=idx)
     _check_summary(g)
+
+
+@pytest.mark.parametrize("p", [W.ACKLEY_D50, W.ROSENBROCK_D50], ids=lambda p: p["name"])
+def test_full_size_d50_sampled(Z, ctx, oracle_mod, p):
+    """The d = 50 bench workloads at full size (N = 131,072, 64 lanes per
+    start): the whole swarm bit for bit and a strided sample of 64 starts,
+    with their first 20 iterates, against the oracle."""
+    print(f"\n[parity] {p['name']} full size, 64 sampled starts", flush=True)
+    idx = W.strided_subset(p["n"], 64)
+    g, sw, o = _run_both(Z, ctx, oracle_mod, p, idx=idx)
+    _check_pso(g, sw, True)
+    _check_bfgs(g, o, p, idx=idx)
+    _check_summary(g)
