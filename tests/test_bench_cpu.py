@@ -1,0 +1,79 @@
+"""bench.py's host logic on the CPU: the single-GPU refusal, the algorithmic
+flop counts against hand-computed cases, the mixed-precision split against
+the whole count, and the reading of the committed rocprofv3 summaries (used
+only while the kernel's sources still match them)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2603_28770_amd import rocprof_summary as RS  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_flops_hand_computed_rosenbrock_d2():
+    # F_p = 8, F_s = 0, F_t = 13 at d = 2: gradient 8 + 2 * 13 = 34.
+    # per start 34 + 4 = 38; per iteration 6 * 4 + 34 + 14 * 2 = 86;
+    # per trial 8 + 4 = 12
+    assert bench.algorithmic_flops("rosenbrock", 2, 1, 0, 0) == 38
+    assert bench.algorithmic_flops("rosenbrock", 2, 1, 1, 0) == 38 + 86
+    assert bench.algorithmic_flops("rosenbrock", 2, 1, 1, 1) == 38 + 86 + 12
+    assert bench.algorithmic_flops("rosenbrock", 2, 3, 5, 7) == 3 * 38 + 5 * 86 + 7 * 12
+
+
+def test_flops_hand_computed_lbfgs():
+    # Rastrigin d = 4: F_p = 25, F_s = 4, F_t = 32, gradient 25 + 4 + 128 = 157;
+    # two-loop direction with m = 3: 8 * 3 * 4 + 3 * 4 = 108
+    per_iter = 108 + 157 + 14 * 4
+    assert bench.algorithmic_flops("rastrigin", 4, 0, 1, 0, lbfgs_m=3) == per_iter
+
+
+@pytest.mark.parametrize("obj,d", [("rosenbrock", 50), ("rastrigin", 10), ("ackley", 50),
+                                   ("styblinski_tang", 128), ("sphere", 7), ("quartic", 3),
+                                   ("goldstein_price", 2), ("poisson_fit", 4)])
+def test_mixed_split_adds_up(obj, d):
+    n, iters, trials = 1000, 12345, 67890
+    w64, w32 = bench.algorithmic_flops_split(obj, d, n, iters, trials)
+    assert w64 > 0 and w32 > 0
+    assert w64 + w32 == bench.algorithmic_flops(obj, d, n, iters, trials)
+
+
+def test_every_bench_workload_has_a_flop_model():
+    for name, p in bench.WORKLOADS.items():
+        assert bench.algorithmic_flops(p["objective"], p["dim"], p["n"], 10, 10) > 0, name
+    for name, (p, model) in bench.USER_WORKLOADS.items():
+        assert p["objective"] == "user"
+        assert bench.algorithmic_flops(model, p["dim"], p["n"], 10, 10) > 0, name
+
+
+@pytest.mark.parametrize("workload", ["rastrigin_d10_n65536", "rosenbrock_d50_n131072"])
+def test_committed_profiles_are_current(workload):
+    s = RS.load(os.path.join(ROOT, "profiles", f"bfgs_kernel_{workload}.md"))
+    assert s is not None and s["workload"] == workload
+    assert s["sources_sha256"] == RS.sources_sha256("bfgs_kernel")
+    assert s["traffic_bytes"] == pytest.approx(s["read_bytes"] + s["write_bytes"])
+    assert bench.profiled_traffic(workload) == s["traffic_bytes"]
+    assert 0.0 < s["counter_fp64_tflops"] < 78.6
+    assert 0.0 < s["valu_busy"] <= 1.0
+
+
+def test_stale_profile_is_not_used(monkeypatch):
+    monkeypatch.setattr(RS, "sources_sha256", lambda kernel: "0" * 64)
+    assert bench.profile_figures("rastrigin_d10_n65536") is None
+    assert bench.profiled_traffic("rastrigin_d10_n65536") is None
+
+
+def test_missing_profile_is_not_used():
+    assert bench.profiled_traffic("no_such_workload") is None
