@@ -91,33 +91,44 @@ def algorithmic_flops(obj, d, n_starts, total_iters, total_ls_trials, lbfgs_m=0)
     return n_starts * (grad + 2 * d) + total_iters * per_iter + total_ls_trials * (fp + 2 * d)
 
 
-def algorithmic_flops_split(obj, d, n_starts, total_iters, total_ls_trials):
+def algorithmic_flops_split(obj, d, n_starts, total_iters, total_ls_trials, lbfgs_m=0):
     """The same work split by the precision the mixed mode computes it in:
-    (FP64 flops: inverse-Hessian and vector work, the trial points; FP32
-    flops: objective values and dual-number gradients)."""
+    (FP64 flops: inverse-Hessian (or two-loop) and vector work, the trial
+    points; FP32 flops: objective values and dual-number gradients)."""
     fp, fs, ft = _counts(obj, d)
     grad = fp + fs + d * ft
+    h_work = 8 * lbfgs_m * d + 3 * d if lbfgs_m else 6 * d * d
     w32 = n_starts * grad + total_iters * grad + total_ls_trials * fp
-    w64 = n_starts * 2 * d + total_iters * (6 * d * d + 14 * d) + total_ls_trials * 2 * d
+    w64 = n_starts * 2 * d + total_iters * (h_work + 14 * d) + total_ls_trials * 2 * d
     return w64, w32
 
 
-def profile_figures(workload):
-    """The JSON block of the committed rocprofv3 summary of the BFGS kernel on
-    this workload, or None when there is none or the kernel's sources have
-    changed since it was taken."""
+def main_kernel(p):
+    """The kernel that runs the BFGS phase of problem p, and the name its
+    rocprofv3 summary carries under profiles/ (kernel_workload[_mM].md)."""
+    if p.get("lbfgs_m", 0):
+        return "lbfgs_kernel", f"lbfgs_kernel_{p['name']}_m{p['lbfgs_m']}"
+    kernel = "bfgs_wide_kernel" if p["dim"] > 64 else "bfgs_kernel"
+    return kernel, f"{kernel}_{p['name']}"
+
+
+def profile_figures(workload, kernel="bfgs_kernel", stem=None):
+    """The JSON block of the committed rocprofv3 summary of `kernel` on this
+    workload (profiles/<stem>.md, stem = kernel_workload by default), or None
+    when there is none or the kernel's sources have changed since it was
+    taken."""
     from paper_2603_28770_amd import rocprof_summary as RS
-    s = RS.load(os.path.join(ROOT, "profiles", f"bfgs_kernel_{workload}.md"))
-    if not s or s.get("sources_sha256") != RS.sources_sha256("bfgs_kernel"):
+    s = RS.load(os.path.join(ROOT, "profiles", f"{stem or kernel + '_' + workload}.md"))
+    if not s or kernel not in RS.KERNEL_SOURCES or s.get("sources_sha256") != RS.sources_sha256(kernel):
         return None
     return s
 
 
-def profiled_traffic(workload):
-    """HBM bytes per launch of the BFGS kernel on this workload (FETCH_SIZE +
+def profiled_traffic(workload, kernel="bfgs_kernel", stem=None):
+    """HBM bytes per launch of `kernel` on this workload (FETCH_SIZE +
     WRITE_SIZE scaled by a copy kernel's), from the committed summary while it
     is current, else None."""
-    s = profile_figures(workload)
+    s = profile_figures(workload, kernel, stem)
     return s.get("traffic_bytes") if s else None
 
 
@@ -508,7 +519,7 @@ def main():
         # t_ideal = W64 / FP64 peak + W32 / FP32 peak, against the BFGS kernel's time
         m_bfgs = mprof["bfgs_ms"] / max(1, mprof["bfgs_launches"])
         w64, w32 = algorithmic_flops_split(pm["objective"], pm["dim"], pm["n"], ms["total_iters"],
-                                           ms["total_ls_trials"])
+                                           ms["total_ls_trials"], pm.get("lbfgs_m", 0))
         t_ideal = w64 / (FP64_VALU_PEAK_TFLOPS * 1e12) + w32 / (FP32_VALU_PEAK_TFLOPS * 1e12)
         mixed["roofline"] = {"bound": "alu", "bfgs_ms": m_bfgs, "w64_flops": w64, "w32_flops": w32,
                              "peak_fp64": FP64_VALU_PEAK_TFLOPS, "peak_fp32": FP32_VALU_PEAK_TFLOPS,
@@ -522,6 +533,7 @@ def main():
     bfgs_ms = prof["bfgs_ms"] / max(1, prof["bfgs_launches"])
     flops = algorithmic_flops(p["objective"], p["dim"], p["n"], iters, s["total_ls_trials"],
                               p.get("lbfgs_m", 0))
+    kernel, stem = main_kernel(p)
     achieved = flops / (bfgs_ms * 1e-3) / 1e12
     fstar = W.f_star(p["objective"], p["dim"])
     line = {
@@ -542,10 +554,10 @@ def main():
                       "reduce": prof["reduce_ms"] / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": profiled_traffic(args.workload), "kernel": "bfgs_kernel",
+                     "traffic": profiled_traffic(args.workload, kernel, stem), "kernel": kernel,
                      "flops_per_launch": flops},
     }
-    pf = profile_figures(args.workload)
+    pf = profile_figures(args.workload, kernel, stem)
     if pf and "counter_fp64_tflops" in pf:
         # FP64 work the SQ counters saw (every lane of a wave, padding included)
         line["roofline"]["counter_achieved"] = pf["counter_fp64_tflops"]

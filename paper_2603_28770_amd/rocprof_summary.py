@@ -40,6 +40,8 @@ KERNEL_SOURCES = {
                     "csrc/zeus_device.h", "csrc/zeus_internal.h"],
     "pso_kernel": ["csrc/zeus_pso_kernels.h", "csrc/zeus_group.h", "csrc/zeus_device.h",
                    "csrc/zeus_internal.h"],
+    "lbfgs_kernel": ["csrc/zeus_lbfgs_kernels.h", "csrc/zeus_bfgs_common.h", "csrc/zeus_group.h",
+                     "csrc/zeus_device.h", "csrc/zeus_internal.h"],
 }
 
 

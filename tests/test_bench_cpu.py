@@ -45,9 +45,10 @@ def test_flops_hand_computed_lbfgs():
                                    ("goldstein_price", 2), ("poisson_fit", 4)])
 def test_mixed_split_adds_up(obj, d):
     n, iters, trials = 1000, 12345, 67890
-    w64, w32 = bench.algorithmic_flops_split(obj, d, n, iters, trials)
-    assert w64 > 0 and w32 > 0
-    assert w64 + w32 == bench.algorithmic_flops(obj, d, n, iters, trials)
+    for m in (0, 1, 8):
+        w64, w32 = bench.algorithmic_flops_split(obj, d, n, iters, trials, m)
+        assert w64 > 0 and w32 > 0
+        assert w64 + w32 == bench.algorithmic_flops(obj, d, n, iters, trials, m)
 
 
 def test_every_bench_workload_has_a_flop_model():
