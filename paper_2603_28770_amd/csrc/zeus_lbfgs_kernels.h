@@ -29,12 +29,39 @@ __device__ __host__ __forceinline__ constexpr int lbfgs_stride(int slots) {
 }
 
 // sum over the group's G * CPL coordinate slots of a[c] b[c] (pairwise).
+//
+// With 64 lanes and several blocks the blocks' butterflies share their two
+// lane-swap levels: after the levels within 16 lanes, the 16-lane swap leaves
+// block 0's 32-lane partial in the lower half of each 32 lanes and block 1's
+// in the upper half (blocks 2 and 3 likewise), and the 32-lane swap finishes
+// one block per 16 lanes (four blocks) or per half (two).  Two (or one) more
+// swaps then add the block sums as (S0 + S1) + (S2 + S3).  Every addition has
+// the operands it has in the separate butterflies followed by the register
+// tree, so the bits agree; each lane pays one swap level per value instead of
+// one per block.
 template <int G, int CPL>
 __device__ __forceinline__ double slot_dot(const double (&a)[CPL], const double (&b)[CPL]) {
-  double blk[CPL];
+  if constexpr (G == 64 && CPL == 4) {
+    double v[4];
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) blk[c] = lane_tree_sum<G, double>(a[c] * b[c]);
-  return reg_tree_sum<CPL, double>(blk);
+    for (int c = 0; c < 4; ++c) v[c] = lane_tree_sum<16, double>(a[c] * b[c]);
+    const double q0 = half_pair_sum<16>(v[0], v[1]);
+    const double q1 = half_pair_sum<16>(v[2], v[3]);
+    const double s = half_pair_sum<32>(q0, q1);  // S0, S1, S2, S3 by 16 lanes
+    const double p = half_pair_sum<16>(s, s);    // S0 + S1 in lanes 0-31, S2 + S3 above
+    return half_pair_sum<32>(p, p);
+  } else if constexpr (G == 64 && CPL == 2) {
+    const double v0 = lane_tree_sum<16, double>(a[0] * b[0]);
+    const double v1 = lane_tree_sum<16, double>(a[1] * b[1]);
+    const double q = half_pair_sum<16>(v0, v1);
+    const double s = half_pair_sum<32>(q, q);  // S0 in lanes 0-15 and 32-47, S1 in the others
+    return half_pair_sum<16>(s, s);
+  } else {
+    double blk[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) blk[c] = lane_tree_sum<G, double>(a[c] * b[c]);
+    return reg_tree_sum<CPL, double>(blk);
+  }
 }
 
 // Value and gradient at xs in number type T for coordinates j + G c (see
