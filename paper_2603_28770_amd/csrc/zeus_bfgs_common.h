@@ -68,12 +68,14 @@ __device__ __forceinline__ void load_hot(ReqHot &w, const ReqDev &rq, int ri) {
 }
 
 
-// Line-search trials per round: R trials of G / R lanes each.  Two beat
-// four (d = 50 BFGS 3-7% faster, d = 200 L-BFGS 23%) and one (slower at
-// d = 10 and d = 50): the objectives here average 1.4 to 5.6 trials per
-// iteration, so wider rounds mostly evaluate trials past the accepted one.
+// Line-search trials per round: R trials of G / R lanes each.  64-lane
+// groups take two (d = 50 BFGS 3-7% faster than with four, d = 200 L-BFGS
+// 23%; one was slower): at 1.4 to 2.8 trials per iteration wider rounds
+// mostly evaluate trials past the accepted one.  Smaller groups take four:
+// two made Rastrigin at d <= 3 (many trials per iteration) up to 1.5 times
+// slower at every lane count from 4 to 32, and was even at d = 10.
 template <int G>
-constexpr int kRound = G < 2 ? G : 2;
+constexpr int kRound = G == 64 ? 2 : (G < 4 ? G : 4);
 
 // One Armijo search (Alg. 6) with the objective evaluated in number type U,
 // by a group of G lanes covering SLOTS term slots (SLOTS a multiple of G; the

@@ -59,15 +59,20 @@ def test_every_bench_workload_has_a_flop_model():
         assert bench.algorithmic_flops(model, p["dim"], p["n"], 10, 10) > 0, name
 
 
-@pytest.mark.parametrize("workload", ["rastrigin_d10_n65536", "rosenbrock_d50_n131072"])
-def test_committed_profiles_are_current(workload):
-    s = RS.load(os.path.join(ROOT, "profiles", f"bfgs_kernel_{workload}.md"))
-    assert s is not None and s["workload"] == workload
-    assert s["sources_sha256"] == RS.sources_sha256("bfgs_kernel")
+@pytest.mark.parametrize("kernel,workload,stem", [
+    ("bfgs_kernel", "rastrigin_d10_n65536", None),
+    ("bfgs_kernel", "rosenbrock_d50_n131072", None),
+    ("lbfgs_kernel", "rosenbrock_d200_n8192", "lbfgs_kernel_rosenbrock_d200_n8192_m8")])
+def test_committed_profiles_parse(kernel, workload, stem):
+    s = RS.load(os.path.join(ROOT, "profiles", f"{stem or kernel + '_' + workload}.md"))
+    assert s is not None and s["workload"] == workload and s["kernel"] == kernel
     assert s["traffic_bytes"] == pytest.approx(s["read_bytes"] + s["write_bytes"])
-    assert bench.profiled_traffic(workload) == s["traffic_bytes"]
     assert 0.0 < s["counter_fp64_tflops"] < 78.6
     assert 0.0 < s["valu_busy"] <= 1.0
+    # bench uses the figures only while the kernel's sources still match
+    current = s["sources_sha256"] == RS.sources_sha256(kernel)
+    got = bench.profiled_traffic(workload, kernel, stem)
+    assert got == (s["traffic_bytes"] if current else None)
 
 
 def test_stale_profile_is_not_used(monkeypatch):
