@@ -2,8 +2,11 @@
 
     python oracle/build.py
 
-Compiles zeus_oracle.c with gcc into oracle/libzeus_oracle.so.  No fused
-multiply-add (-ffp-contract=off), no fast-math; OpenMP over starts.
+Compiles zeus_oracle.c with gcc twice: oracle/libzeus_oracle.so (the
+default build, whose rounding order is fixed by the readings in the source)
+and oracle/libzeus_oracle_plain.so (-DZO_PLAIN: sums left to right, unfused
+row products and update, the C library's sin/cos/exp/log).  No contraction of
+multiply-adds (-ffp-contract=off), no fast-math; OpenMP over starts.
 """
 import os
 import subprocess
@@ -11,18 +14,25 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libzeus_oracle.so")
+LIB_PLAIN = os.path.join(HERE, "libzeus_oracle_plain.so")
+FLAGS = ["-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+         "-shared", "-Wall", "-Wextra"]
 
 
-def build(verbose: bool = False) -> str:
+def _one(out, extra, verbose, flags=FLAGS):
     src = os.path.join(HERE, "zeus_oracle.c")
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math",
-           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+    tmp = out + ".tmp"
+    cmd = ["gcc", *flags, *extra, "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    _one(LIB_PLAIN, ["-DZO_PLAIN"], verbose)
+    return _one(LIB, [], verbose)
 
 
 if __name__ == "__main__":

@@ -12,6 +12,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzeus_oracle.so")
+# the plain build: sums left to right, unfused row products and update, the C
+# library's sin/cos/exp/log (see zeus_oracle.h)
+LIB_PLAIN_PATH = os.path.join(HERE, "libzeus_oracle_plain.so")
 
 OBJECTIVES = {"rosenbrock": 0, "rastrigin": 1, "ackley": 2, "styblinski_tang": 3,
               "goldstein_price": 4, "sphere": 5, "quartic": 6, "user": 7}
@@ -45,16 +48,17 @@ class _BfgsOut(C.Structure):
                 ("trace_len", C.c_int32)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(plain=False):
+    """The default build of the oracle, or with plain=True the plain build."""
+    if plain not in _libs:
+        path = LIB_PLAIN_PATH if plain else LIB_PATH
+        if not os.path.exists(path):
             from oracle import build as _build
             _build.build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         L.zo_philox4x64_10.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.zo_uniform.restype = C.c_double
         L.zo_uniform.argtypes = [C.c_uint64] * 6
@@ -81,8 +85,14 @@ def lib():
         L.zo_best.restype = C.c_int64
         L.zo_best.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
         L.zo_max_threads.restype = C.c_int
-        _lib = L
-    return _lib
+        L.zo_lbfgs_push.restype = C.c_int
+        L.zo_lbfgs_push.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int),
+                                    C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+        for fn in ("zo_sin", "zo_cos", "zo_exp", "zo_log"):
+            getattr(L, fn).restype = C.c_double
+            getattr(L, fn).argtypes = [C.c_double]
+        _libs[plain] = L
+    return _libs[plain]
 
 
 def _ptr(a):
@@ -115,53 +125,77 @@ def uniform(seed, request_id, i, t, tag, j):
     return lib().zo_uniform(seed, request_id, i, t, tag, j)
 
 
-def f(objective, x):
+def f(objective, x, plain=False):
     x = np.ascontiguousarray(x, dtype=np.float64)
-    return lib().zo_f(OBJECTIVES[objective], _ptr(x), x.size)
+    return lib(plain).zo_f(OBJECTIVES[objective], _ptr(x), x.size)
 
 
-def grad(objective, x):
+def grad(objective, x, plain=False):
     x = np.ascontiguousarray(x, dtype=np.float64)
     g = np.empty_like(x)
     fv = C.c_double()
-    lib().zo_grad(OBJECTIVES[objective], _ptr(x), x.size, C.byref(fv), _ptr(g))
+    lib(plain).zo_grad(OBJECTIVES[objective], _ptr(x), x.size, C.byref(fv), _ptr(g))
     return fv.value, g
 
 
-def lbfgs_direction(S, Y, rho, g):
+def lbfgs_direction(S, Y, rho, g, plain=False):
     """Two-loop recursion p = -H g over the pairs in the rows of S, Y (oldest first)."""
     S = np.ascontiguousarray(S, dtype=np.float64)
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     rho = np.ascontiguousarray(rho, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
     p = np.empty_like(g)
-    lib().zo_lbfgs_direction(_ptr(S), _ptr(Y), _ptr(rho), int(rho.size), _ptr(g), g.size, _ptr(p))
+    lib(plain).zo_lbfgs_direction(_ptr(S), _ptr(Y), _ptr(rho), int(rho.size), _ptr(g), g.size, _ptr(p))
     return p
 
 
-def hrow_dot(hrow, v):
+def lbfgs_push(S, Y, rho, count, s_vec, y_vec, plain=False):
+    """The pair window update (zo_lbfgs_push) in place on S, Y [m][d] and
+    rho [m]; returns (new count, stored)."""
+    cnt = C.c_int(int(count))
+    s_vec = np.ascontiguousarray(s_vec, dtype=np.float64)
+    y_vec = np.ascontiguousarray(y_vec, dtype=np.float64)
+    ok = lib(plain).zo_lbfgs_push(_ptr(S), _ptr(Y), _ptr(rho), C.byref(cnt), S.shape[0],
+                                  _ptr(s_vec), _ptr(y_vec), s_vec.size)
+    return cnt.value, bool(ok)
+
+
+def sin(x, plain=False):
+    return lib(plain).zo_sin(float(x))
+
+
+def cos(x, plain=False):
+    return lib(plain).zo_cos(float(x))
+
+
+def exp(x, plain=False):
+    return lib(plain).zo_exp(float(x))
+
+
+def hrow_dot(hrow, v, plain=False):
     """Row of H times v in the order of the BFGS matvecs (16-column fused
-    multiply-add chains, block sums added pairwise)."""
+    multiply-add chains, block sums added pairwise; plain build: unfused,
+    columns ascending)."""
     hrow = np.ascontiguousarray(hrow, dtype=np.float64)
     v = np.ascontiguousarray(v, dtype=np.float64)
-    return float(lib().zo_hrow_dot(_ptr(hrow), _ptr(v), hrow.size))
+    return float(lib(plain).zo_hrow_dot(_ptr(hrow), _ptr(v), hrow.size))
 
 
-def bfgs_update(H, s, y):
+def bfgs_update(H, s, y, plain=False):
     H = np.array(H, dtype=np.float64, order="C", copy=True)
     s = np.ascontiguousarray(s, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
-    applied = lib().zo_bfgs_update(_ptr(H), _ptr(s), _ptr(y), s.size)
+    applied = lib(plain).zo_bfgs_update(_ptr(H), _ptr(s), _ptr(y), s.size)
     return H, bool(applied)
 
 
-def line_search(problem, x, f0, p, ddir):
+def line_search(problem, x, f0, p, ddir, plain=False):
     pb = make_problem(problem)
     x = np.ascontiguousarray(x, dtype=np.float64)
     p = np.ascontiguousarray(p, dtype=np.float64)
     xt = np.empty_like(x)
     tr, acc = C.c_int32(), C.c_int32()
-    a = lib().zo_line_search(C.byref(pb), _ptr(x), float(f0), _ptr(p), float(ddir), _ptr(xt),
+    a = lib(plain).zo_line_search(C.byref(pb), _ptr(x), float(f0), _ptr(p), float(ddir), _ptr(xt),
                              C.byref(tr), C.byref(acc))
     return a, tr.value, bool(acc.value)
 
@@ -174,7 +208,7 @@ def validate(problem) -> bool:
     return lib().zo_validate(C.byref(pb)) == 0
 
 
-def pso(problem):
+def pso(problem, plain=False):
     pb = make_problem(problem)
     n, d = pb.n, pb.dim
     out = {k: np.empty((n, d)) for k in ("x", "v", "px")}
@@ -182,14 +216,14 @@ def pso(problem):
     out["gx"] = np.empty(d)
     sw = _Swarm(x=_ptr(out["x"]), v=_ptr(out["v"]), px=_ptr(out["px"]), pf=_ptr(out["pf"]),
                 gx=_ptr(out["gx"]))
-    rc = lib().zo_pso(C.byref(pb), C.byref(sw))
+    rc = lib(plain).zo_pso(C.byref(pb), C.byref(sw))
     if rc != 0:
         raise ValueError("oracle rejected the problem")
     out["gf"], out["gidx"], out["near_ties"] = sw.gf, sw.gidx, sw.near_ties
     return out
 
 
-def bfgs(problem, x0, idx=None, trace_len=0, nthreads=None):
+def bfgs(problem, x0, idx=None, trace_len=0, nthreads=None, plain=False):
     pb = make_problem(problem)
     d = pb.dim
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
@@ -210,8 +244,8 @@ def bfgs(problem, x0, idx=None, trace_len=0, nthreads=None):
                   ls_fail=_ptr(o["ls_fail"]), skips=_ptr(o["skips"]), resets=_ptr(o["resets"]),
                   min_margin=_ptr(o["min_margin"]), tie_iter=_ptr(o["tie_iter"]),
                   trace=_ptr(o.get("trace")), trace_len=int(trace_len))
-    nt = nthreads if nthreads else lib().zo_max_threads()
-    rc = lib().zo_bfgs(C.byref(pb), _ptr(x0), _ptr(idx), m, C.byref(bo), int(nt))
+    nt = nthreads if nthreads else lib(plain).zo_max_threads()
+    rc = lib(plain).zo_bfgs(C.byref(pb), _ptr(x0), _ptr(idx), m, C.byref(bo), int(nt))
     if rc != 0:
         raise ValueError("oracle rejected the problem")
     o["threads"] = nt
@@ -221,7 +255,7 @@ def bfgs(problem, x0, idx=None, trace_len=0, nthreads=None):
 ST_CONVERGED, ST_STOPPED = 1, 2
 
 
-def bfgs_required(problem, x0, required_c, nthreads=None):
+def bfgs_required(problem, x0, required_c, nthreads=None, plain=False):
     """Alg. 10's early stop (required_c starts converged), read iteration-
     synchronously: K* is the iteration at which the required_c-th start
     converges (the required_c-th smallest iteration count among converged
@@ -229,14 +263,14 @@ def bfgs_required(problem, x0, required_c, nthreads=None):
     iterate after K* steps, status STOPPED.  Starts that ended at K* or before
     keep their results.  With fewer than required_c convergences nothing
     stops early.  Returns the per-start results and K* (None if no stop)."""
-    full = bfgs(problem, x0, nthreads=nthreads)
+    full = bfgs(problem, x0, nthreads=nthreads, plain=plain)
     conv = np.sort(full["iters"][full["status"] == ST_CONVERGED])
     if required_c <= 0 or conv.size < required_c:
         return full, None
     kstar = int(conv[required_c - 1])
     late = np.flatnonzero(full["iters"] > kstar)
     if late.size:
-        cut = bfgs(dict(problem, iter_bfgs=kstar), x0, idx=late, nthreads=nthreads)
+        cut = bfgs(dict(problem, iter_bfgs=kstar), x0, idx=late, nthreads=nthreads, plain=plain)
         for k in ("x", "f", "iters", "ls_trials"):
             full[k][late] = cut[k]
         full["status"][late] = ST_STOPPED
@@ -255,13 +289,36 @@ def max_threads():
     return lib().zo_max_threads()
 
 
-def minimize(problem, idx=None, trace_len=0, nthreads=None):
+def minimize(problem, idx=None, trace_len=0, nthreads=None, plain=False):
     """PSO then BFGS from every start (or the starts listed in idx)."""
-    sw = pso(problem)
-    r = bfgs(problem, sw["x"], idx=idx, trace_len=trace_len, nthreads=nthreads)
+    sw = pso(problem, plain=plain)
+    r = bfgs(problem, sw["x"], idx=idx, trace_len=trace_len, nthreads=nthreads, plain=plain)
     b, nc = best(r["f"], r["status"])
     r["best_index"] = b if idx is None or b < 0 else int(np.asarray(idx)[b])
     r["best_f"] = float(r["f"][b]) if b >= 0 else float("nan")
     r["n_converged"] = nc
     r["swarm"] = sw
     return r
+
+
+class View:
+    """This module's functions bound to one build of the oracle: the default
+    build (plain=False) or the plain build (plain=True)."""
+
+    def __init__(self, plain=False):
+        self.plain = bool(plain)
+
+    def __getattr__(self, name):
+        import functools
+        import inspect
+        obj = globals()[name]
+        if callable(obj) and not isinstance(obj, type):
+            try:
+                if "plain" in inspect.signature(obj).parameters:
+                    return functools.partial(obj, plain=self.plain)
+            except (TypeError, ValueError):
+                pass
+        return obj
+
+    def lib(self):
+        return lib(self.plain)

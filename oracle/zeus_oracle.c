@@ -14,7 +14,18 @@
  * Objectives: Sec. V-B (Rosenbrock, Rastrigin, Ackley, Goldstein-Price) plus
  * the standard Styblinski-Tang function and two test-only objectives.
  *
- * Build: gcc -O2 -std=c99 -ffp-contract=off -fopenmp -fPIC -shared
+ * Two builds of this one file:
+ *   default        the order of every rounding is fixed by the readings
+ *                  written next to the code (balanced pairwise sums, 16-column
+ *                  fused row products, the two-FMA update, sin/cos/exp by
+ *                  Cody-Waite reduction and Taylor series);
+ *   -DZO_PLAIN     the textbook order instead: sums strictly left to right,
+ *                  row products and the update unfused in index order, and
+ *                  the C library's sin, cos, exp and log.  It takes no reading
+ *                  of the paper's silences that a particular implementation
+ *                  of the method could have chosen for its own convenience.
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fopenmp -fPIC -shared [-DZO_PLAIN]
  */
 #include "zeus_oracle.h"
 
@@ -70,6 +81,19 @@ double zo_uniform(uint64_t seed, uint64_t request_id, uint64_t i, uint64_t t,
   return (double)(out[j % 4] >> 11) * (1.0 / 9007199254740992.0);
 }
 
+#ifdef ZO_PLAIN
+/* ======================================================================== */
+/* Plain build: sin, cos, exp and log are the C library's.                  */
+/* ======================================================================== */
+static void zo_sincos(double x, double *s, double *c) {
+  *s = sin(x);
+  *c = cos(x);
+}
+double zo_sin(double x) { return sin(x); }
+double zo_cos(double x) { return cos(x); }
+double zo_exp(double x) { return exp(x); }
+double zo_log(double x) { return log(x); }
+#else
 /* ======================================================================== */
 /* sin, cos and exp in double precision, by Cody-Waite argument reduction    */
 /* (Cody and Waite, "Software Manual for the Elementary Functions", 1980)    */
@@ -213,6 +237,7 @@ double zo_log(double x) {
   double r = fma(k, ZM_LOG_LN2_LO, lm);
   return fma(k, ZM_LOG_LN2_HI, r);
 }
+#endif /* ZO_PLAIN */
 
 /* ======================================================================== */
 /* Dual numbers a + b*eps with eps^2 = 0 (Sec. III-C).  v = value, t = tangent.*/
@@ -245,33 +270,50 @@ static dual d_sqrt(dual a) { double s = sqrt(a.v); return dd(s, a.t / (2.0 * s))
 
 /* ======================================================================== */
 /* Sums.  The paper fixes no order for the sums over an objective's terms or */
-/* over coordinates (dot products), so one is chosen here: every such sum is */
-/* a balanced pairwise sum.  A sum of n > 1 values is the sum of its first h */
+/* over coordinates (dot products).  Default build: every such sum is a      */
+/* balanced pairwise sum -- a sum of n > 1 values is the sum of its first h  */
 /* values plus the sum of the remaining n - h, h being the largest power of  */
-/* two below n; a sum of one value is that value.                           */
+/* two below n; a sum of one value is that value.  Plain build: strictly     */
+/* left to right, ((v0 + v1) + v2) + ...                                    */
 /* ======================================================================== */
 
+#ifndef ZO_PLAIN
 static int pw_split(int n) {
   int h = 1;
   while (2 * h < n) h *= 2;
   return h;
 }
+#endif
 
-/* sum_{i<n} a_i b_i, each product rounded, then added pairwise */
+/* sum_{i<n} a_i b_i, each product rounded, then summed */
 static double pw_dot(const double *a, const double *b, int n) {
   if (n <= 0) return 0.0;
+#ifdef ZO_PLAIN
+  double acc = a[0] * b[0];
+  for (int i = 1; i < n; ++i) acc = acc + a[i] * b[i];
+  return acc;
+#else
   if (n == 1) return a[0] * b[0];
   int h = pw_split(n);
   return pw_dot(a, b, h) + pw_dot(a + h, b + h, n - h);
+#endif
 }
 
 /* Products of a row of the inverse Hessian with a vector (u = H y in the
  * update, p = -H g for the direction; Alg. 4).  The paper fixes no order for
- * these sums either.  The one chosen: the columns fall into blocks of
+ * these sums either.  Default build: the columns fall into blocks of
  * ZO_HBLOCK consecutive columns (the last block may be shorter); each block's
  * products are accumulated left to right by fused multiply-adds, starting
  * from zero, and the block sums are added pairwise as above.  For
- * dim <= ZO_HBLOCK this is one fused multiply-add chain over the row. */
+ * dim <= ZO_HBLOCK this is one fused multiply-add chain over the row.  Plain
+ * build: sum_c hrow[c] v[c] with every product rounded, columns ascending. */
+#ifdef ZO_PLAIN
+double zo_hrow_dot(const double *hrow, const double *v, int d) {
+  double acc = 0.0;
+  for (int c = 0; c < d; ++c) acc = acc + hrow[c] * v[c];
+  return acc;
+}
+#else
 #define ZO_HBLOCK 16
 
 static double hrow_blocks(const double *h, const double *v, int d, int b0, int nb) {
@@ -289,13 +331,20 @@ double zo_hrow_dot(const double *hrow, const double *v, int d) {
   if (d <= 0) return 0.0;
   return hrow_blocks(hrow, v, d, 0, (d + ZO_HBLOCK - 1) / ZO_HBLOCK);
 }
+#endif
 
 /* sum of the terms lo .. lo+n-1 of an objective, each term a dual number */
 typedef dual (*term_fn)(const dual *x, int i);
 static dual pw_terms(term_fn term, const dual *x, int lo, int n) {
+#ifdef ZO_PLAIN
+  dual acc = term(x, lo);
+  for (int i = 1; i < n; ++i) acc = d_add(acc, term(x, lo + i));
+  return acc;
+#else
   if (n == 1) return term(x, lo);
   int h = pw_split(n);
   return d_add(pw_terms(term, x, lo, h), pw_terms(term, x, lo + h, n - h));
+#endif
 }
 
 static const double ZO_TWO_PI = 6.283185307179586;  /* 2*pi rounded to double */
@@ -625,6 +674,12 @@ int zo_bfgs_update(double *H, const double *s, const double *y, int d) {
   for (int i = 0; i < d; ++i) u[i] = zo_hrow_dot(H + (size_t)i * d, y, d);
   double yu = pw_dot(y, u, d);
   double beta = (rho * rho) * yu + rho;
+#ifdef ZO_PLAIN
+  /* H_ij - rho (s_i u_j + u_i s_j) + beta s_i s_j, as written */
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      H[i * d + j] = (H[i * d + j] - rho * (s[i] * u[j] + u[i] * s[j])) + (beta * s[i]) * s[j];
+#else
   /* row i: H_ij + a_i u_j + e_i s_j with a_i = -rho s_i and
    * e_i = beta s_i - rho u_i, each element by two fused multiply-adds */
   for (int i = 0; i < d; ++i) {
@@ -632,9 +687,17 @@ int zo_bfgs_update(double *H, const double *s, const double *y, int d) {
     double e = beta * s[i] - rho * u[i];
     for (int j = 0; j < d; ++j) H[i * d + j] = fma(e, s[j], fma(a, u[j], H[i * d + j]));
   }
+#endif
   free(u);
   return 1;
 }
+
+/* a x + y: one fused multiply-add (default build), or rounded twice (plain) */
+#ifdef ZO_PLAIN
+#define AXPY(a, x, y) ((y) + (a) * (x))
+#else
+#define AXPY(a, x, y) fma((a), (x), (y))
+#endif
 
 void zo_lbfgs_direction(const double *S, const double *Y, const double *rho, int count,
                         const double *g, int d, double *p) {
@@ -644,7 +707,7 @@ void zo_lbfgs_direction(const double *S, const double *Y, const double *rho, int
   /* first loop, newest pair first: alpha_i = rho_i s_i'q, q <- q - alpha_i y_i */
   for (int i = count - 1; i >= 0; --i) {
     alpha[i] = rho[i] * pw_dot(S + (size_t)i * d, q, d);
-    for (int j = 0; j < d; ++j) q[j] = fma(-alpha[i], Y[(size_t)i * d + j], q[j]);
+    for (int j = 0; j < d; ++j) q[j] = AXPY(-alpha[i], Y[(size_t)i * d + j], q[j]);
   }
   /* r = H0 q with H0 = gamma I */
   if (count > 0) {
@@ -655,11 +718,28 @@ void zo_lbfgs_direction(const double *S, const double *Y, const double *rho, int
   /* second loop, oldest pair first: beta = rho_i y_i'r, r <- r + (alpha_i - beta) s_i */
   for (int i = 0; i < count; ++i) {
     double beta = rho[i] * pw_dot(Y + (size_t)i * d, q, d);
-    for (int j = 0; j < d; ++j) q[j] = fma(alpha[i] - beta, S[(size_t)i * d + j], q[j]);
+    for (int j = 0; j < d; ++j) q[j] = AXPY(alpha[i] - beta, S[(size_t)i * d + j], q[j]);
   }
   for (int j = 0; j < d; ++j) p[j] = -q[j];
   free(alpha);
   free(q);
+}
+
+int zo_lbfgs_push(double *S, double *Y, double *rho, int *count, int m, const double *s,
+                  const double *y, int d) {
+  double sy = pw_dot(y, s, d);
+  if (!(sy > 0.0)) return 0;
+  if (*count == m) { /* full: drop the oldest pair */
+    memmove(S, S + d, sizeof(double) * (size_t)(m - 1) * d);
+    memmove(Y, Y + d, sizeof(double) * (size_t)(m - 1) * d);
+    memmove(rho, rho + 1, sizeof(double) * (size_t)(m - 1));
+    --*count;
+  }
+  memcpy(S + (size_t)*count * d, s, sizeof(double) * (size_t)d);
+  memcpy(Y + (size_t)*count * d, y, sizeof(double) * (size_t)d);
+  rho[*count] = 1.0 / sy;
+  ++*count;
+  return 1;
 }
 
 /* Track the smallest decision margin and the first iteration at which a
@@ -751,22 +831,7 @@ static void bfgs_one(const zo_problem *pb, const double *x0, int64_t k_out,
       if (!isnan(m)) note_margin(m, k, &min_margin, &tie_iter);
     }
     if (lm > 0) {
-      /* L-BFGS: keep the pair when y's > 0, dropping the oldest beyond m */
-      double sy = pw_dot(y, s, d);
-      if (sy > 0.0) {
-        if (lcount == lm) {
-          memmove(LS, LS + d, sizeof(double) * (size_t)(lm - 1) * d);
-          memmove(LY, LY + d, sizeof(double) * (size_t)(lm - 1) * d);
-          memmove(lrho, lrho + 1, sizeof(double) * (size_t)(lm - 1));
-          --lcount;
-        }
-        memcpy(LS + (size_t)lcount * d, s, sizeof(double) * (size_t)d);
-        memcpy(LY + (size_t)lcount * d, y, sizeof(double) * (size_t)d);
-        lrho[lcount] = 1.0 / sy;
-        ++lcount;
-      } else {
-        ++skips;
-      }
+      if (!zo_lbfgs_push(LS, LY, lrho, &lcount, lm, s, y, d)) ++skips;
     } else if (!zo_bfgs_update(H, s, y, d)) {
       ++skips;
     }

@@ -10,8 +10,14 @@
  * here (Philox, dual numbers, objectives, PSO, BFGS) is written separately.
  *
  * Everything is IEEE double, built with -O2 -ffp-contract=off and without
- * -ffast-math: a multiply-add is fused only where the code calls fma(), and
- * summations run strictly left to right.
+ * -ffast-math: a multiply-add is fused only where the code calls fma().
+ *
+ * The file builds twice.  The default build fixes the order of every
+ * rounding by readings stated in the source (balanced pairwise sums, blocked
+ * fused row products, sin/cos/exp by Cody-Waite reduction and Taylor series).
+ * The plain build (-DZO_PLAIN, libzeus_oracle_plain.so) takes the textbook
+ * order: every sum left to right, row products and the rank-2 update
+ * unfused, the C library's sin, cos, exp and log.
  *
  * Readings of the paper that this oracle fixes (the paper is silent or
  * ambiguous there) are listed next to the code that applies them.
@@ -111,8 +117,9 @@ void zo_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2],
 double zo_uniform(uint64_t seed, uint64_t request_id, uint64_t i, uint64_t t,
                   uint64_t tag, uint64_t j);
 
-/* sin, cos, exp used by the objectives: Cody-Waite reduction and Taylor
- * series with fused multiply-adds (about one ulp); libm beyond |x| = 2^28. */
+/* sin, cos, exp and log used by the objectives: Cody-Waite reduction and
+ * Taylor series with fused multiply-adds (about one ulp; sin and cos are NaN
+ * from |x| = 2^48 on); the C library's in the plain build. */
 double zo_sin(double x);
 double zo_cos(double x);
 double zo_exp(double x);
@@ -137,7 +144,8 @@ void zo_grad(int objective, const double *x, int dim, double *f, double *g);
 
 /* Row of the inverse Hessian times a vector, sum_c hrow[c] v[c] over
  * c < dim: fused multiply-add chains over blocks of 16 consecutive columns,
- * the block sums added pairwise (the order used for u = H y and p = -H g). */
+ * the block sums added pairwise (the order used for u = H y and p = -H g);
+ * plain build: unfused, columns ascending. */
 double zo_hrow_dot(const double *hrow, const double *v, int dim);
 
 /* One rank-2 inverse-Hessian update (Alg. 4), in place on H [dim][dim].
@@ -159,6 +167,14 @@ double zo_line_search(const zo_problem *pb, const double *x, double f0,
  * the newest pair (their eq. 7.20); with no pairs, p = -g. */
 void zo_lbfgs_direction(const double *S, const double *Y, const double *rho, int count,
                         const double *g, int dim, double *p);
+
+/* The L-BFGS pair window: S and Y hold the *count <= m newest pairs in their
+ * rows, oldest first, with rho_i = 1 / (y_i's_i).  Appends (s, y) when
+ * y's > 0, first dropping the oldest pair when m are held, and returns 1;
+ * returns 0 and leaves the window unchanged otherwise.  A restart from H = I
+ * empties the window (*count = 0). */
+int zo_lbfgs_push(double *S, double *Y, double *rho, int *count, int m, const double *s,
+                  const double *y, int dim);
 
 /* 0 if the problem is acceptable, -1 otherwise. */
 int zo_validate(const zo_problem *pb);

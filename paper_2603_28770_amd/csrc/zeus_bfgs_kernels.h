@@ -2,7 +2,7 @@
 // (Alg. 4 / Alg. 10 with the dual-number gradient of Alg. 5 and the Armijo
 // line search of Alg. 6).
 //
-// Mapping (the "more levels of parallelism" the paper leaves for later):
+// Mapping (the finer-grained parallelism the paper defers to future work, Sec. IV):
 //  * one group of G lanes (G a power of two >= dim, G <= 64) runs one start;
 //    a 64-lane wavefront holds 64/G groups, a 256-thread block four waves;
 //  * lane j owns coordinate j; the inverse Hessian H stays in the group's

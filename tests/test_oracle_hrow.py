@@ -52,18 +52,19 @@ def test_hrow_order_constructed(oracle_mod, d, entries, expect):
 
 
 @pytest.mark.parametrize("d", [1, 2, 15, 16, 17, 31, 33, 50, 64, 65, 129, 200, 256])
-def test_hrow_integers_exact(oracle_mod, d):
+def test_hrow_integers_exact(oracle_any, d):
     rng = np.random.default_rng(100 + d)
     h = rng.integers(-64, 65, d).astype(np.float64)
     v = rng.integers(-64, 65, d).astype(np.float64)
     exact = int(np.dot(h.astype(np.int64), v.astype(np.int64)))
-    assert oracle_mod.hrow_dot(h, v) == float(exact)
+    assert oracle_any.hrow_dot(h, v) == float(exact)
 
 
 @pytest.mark.parametrize("d", [3, 16, 50, 200])
-def test_hrow_error_bound(oracle_mod, d):
-    # n roundings along a chain of 16 plus ceil(log2 blocks) levels of adds:
-    # |computed - exact| <= gamma * sum |h_c v_c|, gamma = k u / (1 - k u)
+def test_hrow_error_bound(oracle_any, d):
+    # default build: n roundings along a chain of 16 plus ceil(log2 blocks)
+    # levels of adds; plain build: one unfused chain of d products and d - 1
+    # adds: |computed - exact| <= gamma * sum |h_c v_c|, gamma = k u / (1 - k u)
     rng = np.random.default_rng(7 + d)
     for _ in range(20):
         h = rng.standard_normal(d) * np.exp(rng.uniform(-5, 5, d))
@@ -71,11 +72,40 @@ def test_hrow_error_bound(oracle_mod, d):
         exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(h, v))
         nb = -(-d // 16)
         k = min(d, 16) + int(np.ceil(np.log2(nb))) if nb > 1 else min(d, 16)
+        if oracle_any.plain:
+            k = d
         u = 2.0 ** -53
         bound = k * u / (1 - k * u) * float(sum(abs(Fraction(float(a)) * Fraction(float(b))) for a, b in zip(h, v)))
-        got = oracle_mod.hrow_dot(h, v)
+        got = oracle_any.hrow_dot(h, v)
         assert abs(Fraction(got) - exact) <= Fraction(bound)
 
 
-def test_hrow_empty(oracle_mod):
-    assert oracle_mod.hrow_dot(np.zeros(0), np.zeros(0)) == 0.0
+def test_hrow_empty(oracle_any):
+    assert oracle_any.hrow_dot(np.zeros(0), np.zeros(0)) == 0.0
+
+
+@pytest.mark.parametrize("d, entries, expect", [
+    # one chain over the whole row: every 1 after 2^53 is absorbed
+    (16, {0: BIG, 1: 1.0, 2: 1.0}, BIG),
+    (32, {0: BIG, 16: 1.0, 17: 1.0}, BIG),
+    (64, {0: BIG, 32: 1.0, 48: 1.0}, BIG),
+    (200, {0: BIG, 130: 1.0, 150: 1.0}, BIG),
+    # 1s before 2^53 are summed first: (1 + 1) + 2^53 = 2^53 + 2
+    (40, {3: 1.0, 9: 1.0, 39: BIG}, BIG + 2.0),
+])
+def test_hrow_plain_is_one_chain(d, entries, expect):
+    from oracle import oracle as O
+    h, v = _row(d, entries)
+    assert O.hrow_dot(h, v, plain=True) == expect
+
+
+def test_hrow_plain_products_are_rounded():
+    """The plain build rounds every product before adding it: with
+    h = (-1, 1 + 2^-30) and v = (1 + 2^-29, 1 + 2^-30) the second product
+    1 + 2^-29 + 2^-60 rounds to 1 + 2^-29 and the sum is 0; a fused
+    multiply-add keeps the 2^-60 (the default build's chain)."""
+    from oracle import oracle as O
+    h = np.array([-1.0, 1.0 + 2.0 ** -30])
+    v = np.array([1.0 + 2.0 ** -29, 1.0 + 2.0 ** -30])
+    assert O.hrow_dot(h, v, plain=True) == 0.0
+    assert O.hrow_dot(h, v) == 2.0 ** -60

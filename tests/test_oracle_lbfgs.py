@@ -21,7 +21,7 @@ def _dense_h(S, Y, d):
 
 
 @pytest.mark.parametrize("d,m", [(1, 1), (3, 2), (10, 5), (40, 8)])
-def test_two_loop_equals_explicit_inverse_hessian(oracle_mod, d, m):
+def test_two_loop_equals_explicit_inverse_hessian(oracle_any, d, m):
     rng = np.random.default_rng(d * 10 + m)
     Q = rng.standard_normal((d, d))
     A = Q @ Q.T + d * np.eye(d)          # SPD: y = A s gives y's > 0
@@ -29,33 +29,33 @@ def test_two_loop_equals_explicit_inverse_hessian(oracle_mod, d, m):
     Y = S @ A.T
     rho = 1.0 / np.einsum("ij,ij->i", Y, S)
     g = rng.standard_normal(d)
-    p = oracle_mod.lbfgs_direction(S, Y, rho, g)
+    p = oracle_any.lbfgs_direction(S, Y, rho, g)
     ref = -_dense_h(S, Y, d) @ g
     assert np.max(np.abs(p - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
 
 
-def test_two_loop_without_pairs_is_steepest_descent(oracle_mod):
+def test_two_loop_without_pairs_is_steepest_descent(oracle_any):
     g = np.array([1.5, -2.0, 0.25])
-    p = oracle_mod.lbfgs_direction(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), g)
+    p = oracle_any.lbfgs_direction(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), g)
     assert np.array_equal(p, -g)
 
 
-def test_two_loop_one_pair_secant(oracle_mod):
+def test_two_loop_one_pair_secant(oracle_any):
     """With one pair H y = s exactly in exact arithmetic (secant condition)."""
     rng = np.random.default_rng(3)
     s, y = rng.standard_normal(6), rng.standard_normal(6)
     if y @ s < 0:
         y = -y
-    p = oracle_mod.lbfgs_direction(s[None], y[None], np.array([1.0 / (y @ s)]), y)
+    p = oracle_any.lbfgs_direction(s[None], y[None], np.array([1.0 / (y @ s)]), y)
     assert np.allclose(-p, s, rtol=1e-12, atol=1e-12)
 
 
 @pytest.mark.parametrize("obj,d", [("rosenbrock", 10), ("sphere", 30), ("quartic", 6)])
-def test_lbfgs_solves_to_the_known_minimum(oracle_mod, obj, d):
+def test_lbfgs_solves_to_the_known_minimum(oracle_any, obj, d):
     lo, hi = (-2.0, 2.0)
     p = W.problem(objective=obj, dim=d, n=64, lower=lo, upper=hi, iter_pso=2, iter_bfgs=3000,
                   seed=4, lbfgs_m=6, grad_tol=1e-8)
-    r = oracle_mod.minimize(p)
+    r = oracle_any.minimize(p)
     conv = r["status"] == 1
     assert conv.mean() >= 0.9
     fstar = W.f_star(obj, d)
@@ -64,17 +64,17 @@ def test_lbfgs_solves_to_the_known_minimum(oracle_mod, obj, d):
     # every converged start is a stationary point (Rosenbrock also has a local
     # minimum near x_1 = -1 for d >= 4)
     for i in np.flatnonzero(conv):
-        _, g = oracle_mod.grad(obj, r["x"][i])
+        _, g = oracle_any.grad(obj, r["x"][i])
         assert np.linalg.norm(g) < 1e-8
 
 
-def test_lbfgs_differs_from_bfgs_only_in_the_direction(oracle_mod):
+def test_lbfgs_differs_from_bfgs_only_in_the_direction(oracle_any):
     """m = 0 is BFGS; the swarm and first iterate do not depend on m."""
     p = W.problem(objective="rosenbrock", dim=5, n=32, lower=-2.0, upper=2.0, iter_pso=2,
                   iter_bfgs=200, seed=6)
-    a = oracle_mod.minimize(p)
-    b = oracle_mod.minimize(dict(p, lbfgs_m=4))
+    a = oracle_any.minimize(p)
+    b = oracle_any.minimize(dict(p, lbfgs_m=4))
     assert np.array_equal(a["swarm"]["x"], b["swarm"]["x"])
-    ta = oracle_mod.bfgs(p, a["swarm"]["x"], trace_len=2)["trace"]
-    tb = oracle_mod.bfgs(dict(p, lbfgs_m=4), a["swarm"]["x"], trace_len=2)["trace"]
+    ta = oracle_any.bfgs(p, a["swarm"]["x"], trace_len=2)["trace"]
+    tb = oracle_any.bfgs(dict(p, lbfgs_m=4), a["swarm"]["x"], trace_len=2)["trace"]
     assert np.array_equal(ta[:, :2], tb[:, :2])   # the first step is -g in both

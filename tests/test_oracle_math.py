@@ -1,7 +1,9 @@
-"""Pins for the oracle's sin, cos and exp (Cody-Waite reduction + Taylor
-series with fused multiply-adds), which the objectives evaluate instead of the
-C library: error against an extended-precision reference, exact special
-values and symmetries, large arguments up to 2^48, NaN beyond."""
+"""Pins for the oracle's sin, cos and exp: in the default build Cody-Waite
+reduction + Taylor series with fused multiply-adds, which the objectives
+evaluate instead of the C library; in the plain build the C library's.  Both
+are held to the same bars: error against an extended-precision reference,
+exact special values and symmetries, large arguments up to 2^48; beyond that
+the default build's sin and cos are NaN."""
 import ctypes as C
 
 import numpy as np
@@ -9,11 +11,12 @@ import pytest
 
 
 @pytest.fixture(scope="module")
-def M(oracle_mod):
-    L = oracle_mod.lib()
+def M(oracle_any):
+    L = oracle_any.lib()
     for n in ("zo_sin", "zo_cos", "zo_exp"):
         getattr(L, n).restype = C.c_double
         getattr(L, n).argtypes = [C.c_double]
+    L.plain = oracle_any.plain
     return L
 
 
@@ -56,7 +59,9 @@ def test_special_values(M):
     assert M.zo_exp(1.0) == np.e or abs(M.zo_exp(1.0) - np.e) <= np.spacing(np.e)
     assert M.zo_exp(1000.0) == np.inf and M.zo_exp(-1000.0) == 0.0
     assert M.zo_exp(-np.inf) == 0.0 and M.zo_exp(np.inf) == np.inf
-    assert np.isnan(M.zo_exp(np.nan)) and np.isnan(M.zo_cos(np.inf)) and np.isnan(M.zo_sin(np.nan))
+    with np.errstate(invalid="ignore"):
+        assert np.isnan(M.zo_exp(np.nan)) and np.isnan(M.zo_cos(np.inf))
+        assert np.isnan(M.zo_sin(np.nan))
     # subnormal results still follow exp
     v = M.zo_exp(-740.0)
     assert 0.0 < v < 1e-300 and abs(v - np.exp(np.longdouble(-740.0))) <= 2 * np.spacing(v)
@@ -82,6 +87,8 @@ def test_large_arguments_keep_the_reduction_accurate(M, lo, hi):
 
 
 def test_out_of_range_arguments_are_nan(M):
+    if M.plain:
+        pytest.skip("the C library reduces every finite argument")
     for v in (2.0 ** 48, -(2.0 ** 48), 1e300, np.inf, -np.inf, np.nan):
         assert np.isnan(M.zo_sin(v)) and np.isnan(M.zo_cos(v))
     v = np.nextafter(2.0 ** 48, 0.0)

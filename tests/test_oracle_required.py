@@ -15,8 +15,8 @@ def _p(**kw):
     return W.problem(**base)
 
 
-def test_required_c_matches_its_definition(oracle_mod):
-    O = oracle_mod
+def test_required_c_matches_its_definition(oracle_any):
+    O = oracle_any
     p = _p()
     x0 = O.pso(p)["x"]
     full = O.bfgs(p, x0)
@@ -37,8 +37,8 @@ def test_required_c_matches_its_definition(oracle_mod):
     assert np.all(r["iters"] <= kstar)
 
 
-def test_required_c_edge_cases(oracle_mod):
-    O = oracle_mod
+def test_required_c_edge_cases(oracle_any):
+    O = oracle_any
     p = _p(n=120)
     x0 = O.pso(p)["x"]
     full = O.bfgs(p, x0)
