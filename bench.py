@@ -103,6 +103,57 @@ def algorithmic_flops_split(obj, d, n_starts, total_iters, total_ls_trials, lbfg
     return w64, w32
 
 
+# Per-unit counts of the method's algorithmic work as this benchmark defines
+# it for the roofline fraction: a primal evaluation F_p and the flops one
+# dense tangent sweep adds, F_t, with each cos/exp/sqrt counted as one flop:
+#   Rosenbrock       F_p = 8(d-1)        F_t = 10(d-1)
+#   Rastrigin        F_p = 5d + d (cos)  F_t = 5d
+#   Ackley           F_p = 6d + d (cos) + 2 (exp) + 1 (sqrt)   F_t = 6d
+#   Styblinski-Tang  F_p = 7d            F_t = 6d
+# (the test-only and user objectives take this file's own counts above).
+def _survey_counts(obj, d):
+    if obj == "rosenbrock":
+        return 8 * (d - 1), 10 * (d - 1)
+    if obj == "rastrigin":
+        return 6 * d, 5 * d
+    if obj == "ackley":
+        return 7 * d + 3, 6 * d
+    if obj == "styblinski_tang":
+        return 7 * d, 6 * d
+    fp, fs, ft = _counts(obj, d)
+    return fp + fs, ft
+
+
+# Tangent flops per direction when only the terms that hold x_j are swept
+# (each direction of Alg. 5 has at most two nonzero term tangents for
+# Rosenbrock, one for the separable objectives; Ackley adds the outer chain
+# of its two sums).
+_SPARSE_TANGENT = {"rosenbrock": 20, "rastrigin": 5, "ackley": 14, "styblinski_tang": 6,
+                   "sphere": 2, "quartic": 3}
+
+
+def survey_flops(obj, d, total_iters, total_ls_trials, lbfgs_m=0):
+    """The method's algorithmic work as the survey defines it, per start-
+    iteration W_H + W_grad + W_LS: W_H = 6 d^2 (one matrix-vector product and
+    the rank-2 update; with L-BFGS the two-loop recursion 8 m d + 3 d),
+    W_grad = F_p + d F_t (one primal and d dense tangent sweeps), and per
+    line-search trial F_p + 2 d."""
+    fp, ft = _survey_counts(obj, d)
+    h_work = 8 * lbfgs_m * d + 3 * d if lbfgs_m else 6 * d * d
+    return total_iters * (h_work + fp + d * ft) + total_ls_trials * (fp + 2 * d)
+
+
+def sparse_flops(obj, d, total_iters, total_ls_trials, lbfgs_m=0):
+    """The same work with each gradient direction sweeping only the terms
+    that hold its coordinate (what a term-parallel evaluation needs); for
+    objectives without a term structure the dense count."""
+    fp, ft = _survey_counts(obj, d)
+    tan = _SPARSE_TANGENT.get(obj)
+    grad = fp + d * (min(tan, ft) if tan is not None else ft)
+    h_work = 8 * lbfgs_m * d + 3 * d if lbfgs_m else 6 * d * d
+    return total_iters * (h_work + grad) + total_ls_trials * (fp + 2 * d)
+
+
 def main_kernel(p):
     """The kernel that runs the BFGS phase of problem p, and the name its
     rocprofv3 summary carries under profiles/ (kernel_workload[_mM].md)."""
@@ -167,6 +218,8 @@ def cpu_baseline(p, sub=256, sub1=None):
 
 
 MULTI = ("uneven_batch", "served_mix")
+HEADLINE = "rosenbrock_d50_n131072"
+SECONDARY = ("ackley_d50_n131072", "rastrigin_d10_n65536")
 
 
 def _user_source(name):
@@ -227,11 +280,12 @@ def run_uneven_batch(args, Z, ctx):
                                   "single-problem default workload"}
 
 
-def run_served_mix(args, Z, ctx):
+def run_served_mix(args, Z, ctx, compact=False):
     """The served mix (d in [2,200], N log-uniform; mixed precision, Theta 1e-4)
     at reduced size: plain FP64 one request at a time, then the server closed
     loop (all submitted at once: saturation rate mu), then Poisson arrivals at
-    0.5, 0.7 and 0.9 mu with per-request latency t_done - t_submit."""
+    0.5, 0.7 and 0.9 mu with per-request latency t_done - t_submit.  With
+    compact=True returns the comparison block the default line nests."""
     import torch
     count = args.requests or 256
     scale = args.n_scale if args.n_scale else 1.0 / 16
@@ -288,6 +342,17 @@ def run_served_mix(args, Z, ctx):
                 "p99_ms": float(np.percentile(lat, 99)), "start_iters_per_s": oi / span,
                 "converged_starts_per_s": oc / span, "success_rate": osc}
     main_ol = open_loop["0.7"]
+    if compact:
+        return {"config": _mix_config("served_mix", reqs, scale), "precision": "mixed",
+                "grad_tol": float(reqs[0]["grad_tol"]),
+                "fp64_one_at_a_time_ms": t_seq * 1e3, "served_closed_loop_ms": t_closed * 1e3,
+                "speedup_vs_fp64_one_at_a_time": t_seq / t_closed,
+                "success_rate": succ, "fp64_success_rate": s_succ,
+                "equal_success": bool(abs(succ - s_succ) <= 0.01),
+                "start_iters_per_s": iters / t_closed, "converged_starts_per_s": conv / t_closed,
+                "fp64_start_iters_per_s": s_iters / t_seq,
+                "saturation_req_per_s": mu, "p50_solve_ms": main_ol["p50_ms"],
+                "p99_solve_ms": main_ol["p99_ms"], "open_loop": open_loop}
     return {
         "metric": METRIC, "value": iters / t_closed, "unit": "start-iters/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": t_closed * 1e3, "higher_is_better": True,
@@ -380,8 +445,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rastrigin_d10_n65536",
-                    choices=sorted(WORKLOADS) + list(MULTI) + sorted(USER_WORKLOADS))
+    ap.add_argument("--workload", default=None,
+                    choices=sorted(WORKLOADS) + list(MULTI) + sorted(USER_WORKLOADS),
+                    help="one workload only (default: the d = 50 Rosenbrock headline with "
+                         "Ackley d = 50, Rastrigin d = 10 and the served set beside it)")
     ap.add_argument("--n-scale", type=float, default=0.0,
                     help="multi-request workloads: multiply every request's start count")
     ap.add_argument("--requests", type=int, default=0, help="served_mix: number of requests")
@@ -391,6 +458,8 @@ def main():
                     help="also time the solve with early stop at C converged starts (the "
                          "paper's time-to-C-convergences metric; blocking entry point)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true",
+                    help="default run: skip the served mixed-precision set")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run of the same workload")
     ap.add_argument("--study", choices=("ncorrect_vs_d", "pso_iters"), default=None,
@@ -449,11 +518,49 @@ def main():
         print(json.dumps(line), flush=True)
         return
 
-    p = WORKLOADS[args.workload]
-    if args.lbfgs_m:
-        p = dict(p, lbfgs_m=args.lbfgs_m)
     ctx = Z.zeus_context_create(0)
     stream = torch.cuda.Stream()   # the library's kernels and torch's events share it
+    if args.workload:
+        p = WORKLOADS[args.workload]
+        if args.lbfgs_m:
+            p = dict(p, lbfgs_m=args.lbfgs_m)
+        line = measure_single(args, Z, ctx, stream, p, args.workload)
+        if args.required_c > 0:
+            line["time_to_c"] = time_to_c(Z, ctx, p, args.required_c, max(1, args.steps))
+        Z.zeus_context_destroy(ctx)
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline(p)
+        print(json.dumps(line), flush=True)
+        return
+
+    # default: the d = 50 Rosenbrock problem (the largest single problem) in
+    # FP64 as the headline, with Ackley d = 50, the d = 10 Rastrigin problem
+    # and the served mixed-precision set against plain FP64 beside it
+    head = HEADLINE
+    line = measure_single(args, Z, ctx, stream, WORKLOADS[head], head)
+    also = {}
+    for name in SECONDARY:
+        r = measure_single(args, Z, ctx, stream, WORKLOADS[name], name)
+        also[name] = {k: r[k] for k in ("value", "unit", "ms_per_step", "converged_starts_per_s",
+                                        "p50_solve_ms", "p99_solve_ms", "success_rate",
+                                        "best_f", "ls_trials_per_iter", "kernel_ms", "roofline",
+                                        "mixed", "config") if k in r}
+        print(f"[bench] {name}: {r['value']:.4g} start-iters/s", file=sys.stderr, flush=True)
+    line["also"] = also
+    if not args.no_served:
+        line["served"] = run_served_mix(args, Z, ctx, compact=True)
+    Z.zeus_context_destroy(ctx)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(WORKLOADS[head])
+    print(json.dumps(line), flush=True)
+
+
+def measure_single(args, Z, ctx, stream, p, name):
+    """One problem on the device: K eager solves through the async entry
+    point (state resident in HBM) timed with HIP events on `stream`, the same
+    solve replayed from a captured HIP graph, and (FP64 problems) the mixed-
+    precision solve.  Returns the JSON line of the problem."""
+    import torch
     sptr = stream.cuda_stream
 
     def timed(problem):
@@ -502,20 +609,24 @@ def main():
              "p99_solve_ms": float(np.percentile(glat, 99)),
              "same_results": bool(np.array_equal(gout["f"], out["f"], equal_nan=True)
                                   and gout["summary"] == s)}
+    ms_per_step = wall * 1e3 / args.steps
+    fstar = W.f_star(p["objective"], p["dim"])
+    success = float(np.mean(out["f"] - fstar < 1e-4))
     mixed = None
     if not args.no_mixed and p.get("precision", "fp64") == "fp64":
         pm = dict(p, precision="mixed", grad_tol=max(p["grad_tol"], 1e-4))
         mwall, mprof, mlat, mout = timed(pm)
         ms = mout["summary"]
         mms = mwall * 1e3 / args.steps
-        fstar_m = W.f_star(pm["objective"], pm["dim"])
+        msucc = float(np.mean(mout["f"] - fstar < 1e-4))
         mixed = {"grad_tol": pm["grad_tol"], "ms_per_step": mms,
                  "start_iters_per_s": ms["total_iters"] / (mms / 1e3),
                  "converged_starts_per_s": ms["n_converged"] / (mms / 1e3),
                  "p50_solve_ms": float(np.percentile(mlat, 50)),
                  "p99_solve_ms": float(np.percentile(mlat, 99)),
-                 "success_rate": float(np.mean(mout["f"] - fstar_m < 1e-4)),
-                 "speedup_vs_fp64": (wall * 1e3 / args.steps) / mms}
+                 "success_rate": msucc, "fp64_success_rate": success,
+                 "speedup_vs_fp64": ms_per_step / mms,
+                 "equal_success": bool(abs(msucc - success) <= 0.01)}
         # t_ideal = W64 / FP64 peak + W32 / FP32 peak, against the BFGS kernel's time
         m_bfgs = mprof["bfgs_ms"] / max(1, mprof["bfgs_launches"])
         w64, w32 = algorithmic_flops_split(pm["objective"], pm["dim"], pm["n"], ms["total_iters"],
@@ -526,68 +637,67 @@ def main():
                              "unit": "TFLOP/s", "t_ideal_ms": t_ideal * 1e3,
                              "frac": t_ideal * 1e3 / m_bfgs}
 
-    ms_per_step = wall * 1e3 / args.steps
     iters = s["total_iters"]
     value = iters / (ms_per_step / 1e3)
     conv_per_s = s["n_converged"] / (ms_per_step / 1e3)
     bfgs_ms = prof["bfgs_ms"] / max(1, prof["bfgs_launches"])
-    flops = algorithmic_flops(p["objective"], p["dim"], p["n"], iters, s["total_ls_trials"],
-                              p.get("lbfgs_m", 0))
+    lm = p.get("lbfgs_m", 0)
+    trials = s["total_ls_trials"]
+    flops = survey_flops(p["objective"], p["dim"], iters, trials, lm)
+    sparse = sparse_flops(p["objective"], p["dim"], iters, trials, lm)
     kernel, stem = main_kernel(p)
     achieved = flops / (bfgs_ms * 1e-3) / 1e12
-    fstar = W.f_star(p["objective"], p["dim"])
     line = {
         "metric": METRIC, "value": value, "unit": "start-iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded Philox starts in the box; analytic objective)",
-        "config": {"workload": args.workload, "objective": p["objective"], "dim": p["dim"],
+        "config": {"workload": name, "objective": p["objective"], "dim": p["dim"],
                    "n_starts": p["n"], "iter_pso": p["iter_pso"], "iter_bfgs": p["iter_bfgs"],
                    "grad_tol": p["grad_tol"], "precision": p.get("precision", "fp64"),
-                   "method": f"lbfgs_m{args.lbfgs_m}" if args.lbfgs_m else "bfgs"},
+                   "method": f"lbfgs_m{lm}" if lm else "bfgs"},
         "converged_starts_per_s": conv_per_s,
         "p50_solve_ms": float(np.percentile(lat, 50)), "p99_solve_ms": float(np.percentile(lat, 99)),
-        "start_iters_per_step": iters, "ls_trials_per_iter": s["total_ls_trials"] / max(1, iters),
-        "n_converged": s["n_converged"], "best_f": s["best_f"],
-        "success_rate": float(np.mean(out["f"] - fstar < 1e-4)),
+        "start_iters_per_step": iters, "ls_trials_per_iter": trials / max(1, iters),
+        "n_converged": s["n_converged"], "best_f": s["best_f"], "success_rate": success,
         "kernel_ms": {"pso": prof["pso_ms"] / args.steps, "bfgs": bfgs_ms,
                       "reduce": prof["reduce_ms"] / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": profiled_traffic(args.workload, kernel, stem), "kernel": kernel,
-                     "flops_per_launch": flops},
+                     "traffic": profiled_traffic(name, kernel, stem), "kernel": kernel,
+                     "flops_per_launch": flops, "count": "method (dense tangent sweeps)",
+                     "sparse_achieved": sparse / (bfgs_ms * 1e-3) / 1e12,
+                     "sparse_frac": sparse / (bfgs_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS},
     }
-    pf = profile_figures(args.workload, kernel, stem)
+    pf = profile_figures(name, kernel, stem)
     if pf and "counter_fp64_tflops" in pf:
         # FP64 work the SQ counters saw (every lane of a wave, padding included)
         line["roofline"]["counter_achieved"] = pf["counter_fp64_tflops"]
+        line["roofline"]["counter_frac"] = pf["counter_fp64_tflops"] / FP64_VALU_PEAK_TFLOPS
         line["roofline"]["valu_busy"] = pf.get("valu_busy")
     line["graph"] = graph
-    if args.required_c > 0:
-        # time to required_c convergences against the full solve, both through
-        # the blocking entry point (results copied to the host)
-        Z.zeus_minimize(ctx, dict(p, required_converged=args.required_c))
-        reps = max(1, args.steps)
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            full = Z.zeus_minimize(ctx, p)
-        t_full = (time.perf_counter() - t0) / reps
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            early = Z.zeus_minimize(ctx, dict(p, required_converged=args.required_c))
-        t_early = (time.perf_counter() - t0) / reps
-        line["time_to_c"] = {
-            "required_c": args.required_c, "ms": t_early * 1e3, "full_solve_ms": t_full * 1e3,
+    if mixed is not None:
+        line["mixed"] = mixed
+    return line
+
+
+def time_to_c(Z, ctx, p, required_c, reps):
+    """Time to required_c convergences against the full solve, both through
+    the blocking entry point (results copied to the host)."""
+    Z.zeus_minimize(ctx, dict(p, required_converged=required_c))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        full = Z.zeus_minimize(ctx, p)
+    t_full = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        early = Z.zeus_minimize(ctx, dict(p, required_converged=required_c))
+    t_early = (time.perf_counter() - t0) / reps
+    return {"required_c": required_c, "ms": t_early * 1e3, "full_solve_ms": t_full * 1e3,
             "speedup": t_full / t_early, "k_star": int(early["iters"].max()),
             "converged": int(np.sum(early["status"] == 1)),
             "stopped": int(np.sum(early["status"] == 2)),
             "full_converged": int(np.sum(full["status"] == 1))}
-    if mixed is not None:
-        line["mixed"] = mixed
-    Z.zeus_context_destroy(ctx)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p)
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
