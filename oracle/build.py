@@ -35,6 +35,21 @@ def build(verbose: bool = False) -> str:
     return _one(LIB, [], verbose)
 
 
+SAN_FLAGS = ["-O1", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+             "-shared", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined"]
+
+
+def build_sanitized(out_dir: str, verbose: bool = False) -> dict:
+    """Both builds of the oracle with AddressSanitizer and
+    UndefinedBehaviorSanitizer, into out_dir (for CPU runs with the sanitizer
+    runtimes preloaded).  Returns {"default": path, "plain": path}."""
+    os.makedirs(out_dir, exist_ok=True)
+    d = _one(os.path.join(out_dir, "libzeus_oracle.so"), [], verbose, SAN_FLAGS)
+    p = _one(os.path.join(out_dir, "libzeus_oracle_plain.so"), ["-DZO_PLAIN"], verbose, SAN_FLAGS)
+    return {"default": d, "plain": p}
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

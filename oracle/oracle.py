@@ -11,10 +11,13 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libzeus_oracle.so")
+# ZEUS_ORACLE_DIR names a directory holding other builds of both libraries
+# (the sanitizer builds of build.build_sanitized)
+_DIR = os.environ.get("ZEUS_ORACLE_DIR") or HERE
+LIB_PATH = os.path.join(_DIR, "libzeus_oracle.so")
 # the plain build: sums left to right, unfused row products and update, the C
 # library's sin/cos/exp/log (see zeus_oracle.h)
-LIB_PLAIN_PATH = os.path.join(HERE, "libzeus_oracle_plain.so")
+LIB_PLAIN_PATH = os.path.join(_DIR, "libzeus_oracle_plain.so")
 
 OBJECTIVES = {"rosenbrock": 0, "rastrigin": 1, "ackley": 2, "styblinski_tang": 3,
               "goldstein_price": 4, "sphere": 5, "quartic": 6, "user": 7}
