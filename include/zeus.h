@@ -212,6 +212,31 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem,
                              void *workspace, size_t workspace_bytes,
                              const zeus_result *out, void *stream);
 
+/* Largest device workspace that zeus_minimize_async_static can serve: 64 MiB
+ * (zeus_workspace_bytes() grows as 24 N dim bytes of swarm state, so for
+ * example N = 65,536 starts up to dim 40, or N = 131,072 up to dim 20). */
+#define ZEUS_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/* zeus_minimize_async with no device allocation at all, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  The workspace is a fixed device
+ * array of ZEUS_STATIC_WORKSPACE_BYTES inside the library, one per GPU, held
+ * from the first zeus_context_create on that GPU until the process ends; the
+ * caller passes the device result arrays in *out as for
+ * zeus_minimize_async, and the results are the same.  Only enqueues work on
+ * `stream` (NULL = the context's stream).  ZEUS_ENOMEM, with nothing
+ * enqueued, when zeus_workspace_bytes() of the problem exceeds
+ * ZEUS_STATIC_WORKSPACE_BYTES; ZEUS_EUNSUPPORTED with required_converged > 0
+ * (as zeus_minimize_async).  Every call on one GPU uses that GPU's one
+ * array, which keeps the last call's contents: calls whose device work
+ * overlaps (different streams, or different contexts on the same GPU,
+ * without ordering between them) race and give wrong results; calls on one
+ * stream run in order and are safe.  The kernels initialise everything they
+ * read from the array (a kernel clears the work counter), so no call depends
+ * on what an earlier call left there. */
+zeus_err zeus_minimize_async_static(zeus_context *ctx, const zeus_problem *problem,
+                                    const zeus_result *out, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Plans: a batch captured once into a HIP graph and replayed.              */
 /*                                                                          */

@@ -166,6 +166,36 @@ Workspace carve_workspace(void *base, int64_t n, int dim) {
 
 }  // namespace zeus
 
+// The workspace of zeus_minimize_async_static: a fixed device array, one copy
+// on every GPU the library runs on.  Host code never uses the array's name as
+// an address (on the host it is a stand-in, not device memory); it uses the
+// per-device address that hipGetSymbolAddress returns at context creation.
+static __device__ __align__(256) unsigned char scratch[ZEUS_STATIC_WORKSPACE_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // by device; nullptr until resolved
+
+// Resolves this device's copy of `scratch` once (the device must be current).
+zeus_err bind_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((size_t)device < g_scratch_ptr.size() && g_scratch_ptr[(size_t)device]) return ZEUS_OK;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static workspace");
+  if (!ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign != 0)
+    return fail(ZEUS_EHIP, "static workspace address is not 256-byte aligned");
+  if (g_scratch_ptr.size() <= (size_t)device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  g_scratch_ptr[(size_t)device] = ptr;
+  return ZEUS_OK;
+}
+
+void *scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (size_t)device < g_scratch_ptr.size() ? g_scratch_ptr[(size_t)device] : nullptr;
+}
+}  // namespace
+
 struct zeus_context {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -872,6 +902,12 @@ zeus_err zeus_context_create(int device, zeus_context **out) {
     delete ctx;
     return hip_fail(e, "hipStreamCreate");
   }
+  zeus_err se = bind_scratch(device);
+  if (se != ZEUS_OK) {
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return se;
+  }
   *out = ctx;
   return ZEUS_OK;
 }
@@ -915,26 +951,24 @@ zeus_err zeus_context_get_profile(zeus_context *ctx, zeus_profile *out) {
   return e;
 }
 
-zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, void *workspace,
-                             size_t workspace_bytes, const zeus_result *out, void *stream) {
-  g_last_error.clear();
+namespace {
+// Argument checks of the asynchronous entry points; *need receives the
+// workspace bytes of the problem.
+zeus_err check_async(zeus_context *ctx, const zeus_problem *problem, const zeus_result *out,
+                     size_t *need) {
   if (!ctx) return fail(ZEUS_EINVAL, "ctx is NULL");
   zeus_err e = check_problem(problem);
   if (e != ZEUS_OK) return e;
   if ((e = check_result(out, problem)) != ZEUS_OK) return e;
   if (problem->required_converged > 0)
     return fail(ZEUS_EUNSUPPORTED, "early stopping needs zeus_minimize, zeus_minimize_batch or a server");
-  const zeus_problem pb = *problem;
-  size_t need = 0;
-  (void)zeus_workspace_bytes(&pb, &need);
-  if (!workspace || workspace_bytes < need)
-    return fail(ZEUS_EINVAL, "workspace missing or smaller than zeus_workspace_bytes()");
-  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
-    return fail(ZEUS_EINVAL, "workspace must be 256-byte aligned");
-  DeviceGuard g(ctx->device);
-  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  return zeus_workspace_bytes(problem, need);
+}
+
+// Enqueues one solve on `stream` in the workspace at `workspace` (256-byte
+// aligned, at least zeus_workspace_bytes()); the device is current.
+zeus_err enqueue_async(zeus_context *ctx, const zeus_problem &pb, void *workspace,
+                       const zeus_result *out, hipStream_t s) {
   char *base = static_cast<char *>(workspace);
   std::vector<Planned> one(1);
   one[0].pb = &pb;
@@ -949,6 +983,44 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, voi
                      ? base + kHdrBytes + table_bytes(1) + ws_bytes
                      : nullptr;
   return enqueue_group(ctx, one, base, hslots, s);
+}
+}  // namespace
+
+zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, void *workspace,
+                             size_t workspace_bytes, const zeus_result *out, void *stream) {
+  g_last_error.clear();
+  size_t need = 0;
+  zeus_err e = check_async(ctx, problem, out, &need);
+  if (e != ZEUS_OK) return e;
+  if (!workspace || workspace_bytes < need)
+    return fail(ZEUS_EINVAL, "workspace missing or smaller than zeus_workspace_bytes()");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(ZEUS_EINVAL, "workspace must be 256-byte aligned");
+  const zeus_problem pb = *problem;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return enqueue_async(ctx, pb, workspace, out,
+                       stream ? static_cast<hipStream_t>(stream) : ctx->stream);
+}
+
+zeus_err zeus_minimize_async_static(zeus_context *ctx, const zeus_problem *problem,
+                                    const zeus_result *out, void *stream) {
+  g_last_error.clear();
+  size_t need = 0;
+  zeus_err e = check_async(ctx, problem, out, &need);
+  if (e != ZEUS_OK) return e;
+  if (need > ZEUS_STATIC_WORKSPACE_BYTES)
+    return fail(ZEUS_ENOMEM, "problem needs " + std::to_string(need) +
+                                 " bytes of workspace; the static workspace holds " +
+                                 std::to_string(ZEUS_STATIC_WORKSPACE_BYTES));
+  void *ws = scratch_of(ctx->device);
+  if (!ws) return fail(ZEUS_EHIP, "static workspace not resolved on this device");
+  const zeus_problem pb = *problem;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return enqueue_async(ctx, pb, ws, out, stream ? static_cast<hipStream_t>(stream) : ctx->stream);
 }
 
 zeus_err zeus_minimize(zeus_context *ctx, const zeus_problem *problem, const zeus_result *out) {

@@ -27,7 +27,8 @@ ST_MAXITER, ST_CONVERGED, ST_STOPPED, ST_NONFINITE = 0, 1, 2, 3
 EXPORTS = ("zeus_abi_version", "zeus_version", "zeus_last_error", "zeus_validate",
            "zeus_workspace_bytes", "zeus_context_create", "zeus_context_destroy",
            "zeus_context_set_profiling", "zeus_context_get_profile", "zeus_minimize",
-           "zeus_minimize_batch", "zeus_minimize_async", "zeus_server_create",
+           "zeus_minimize_batch", "zeus_minimize_async", "zeus_minimize_async_static",
+           "zeus_server_create",
            "zeus_server_submit", "zeus_server_wait", "zeus_server_cancel", "zeus_server_destroy",
            "zeus_plan_workspace_bytes", "zeus_plan_create", "zeus_plan_launch", "zeus_plan_destroy",
            "zeus_objective_compile", "zeus_objective_check", "zeus_objective_destroy",
@@ -99,6 +100,8 @@ def _load():
     L.zeus_minimize_batch.argtypes = [C.c_void_p, P(zeus_problem), C.c_int32, P(zeus_result)]
     L.zeus_minimize_async.argtypes = [C.c_void_p, P(zeus_problem), C.c_void_p, C.c_size_t,
                                       P(zeus_result), C.c_void_p]
+    L.zeus_minimize_async_static.argtypes = [C.c_void_p, P(zeus_problem), P(zeus_result),
+                                             C.c_void_p]
     L.zeus_server_create.argtypes = [C.c_void_p, C.c_size_t, P(C.c_void_p)]
     L.zeus_server_submit.argtypes = [C.c_void_p, P(zeus_problem), P(zeus_result), P(C.c_uint64)]
     L.zeus_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, P(zeus_request_times)]
@@ -281,6 +284,19 @@ def zeus_minimize_async(ctx, problem, workspace_ptr: int, workspace_bytes: int,
                                    C.c_void_p(stream_ptr) if stream_ptr else None))
 
 
+# ZEUS_STATIC_WORKSPACE_BYTES of zeus.h: the largest workspace the
+# allocation-free entry point serves.
+STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def zeus_minimize_async_static(ctx, problem, result: zeus_result, stream_ptr: int = 0) -> None:
+    """Enqueue a solve into caller-owned device outputs with the library's
+    fixed device workspace (no device allocation)."""
+    pb = problem if isinstance(problem, zeus_problem) else make_problem(problem)
+    _check(lib.zeus_minimize_async_static(ctx, C.byref(pb), C.byref(result),
+                                          C.c_void_p(stream_ptr) if stream_ptr else None))
+
+
 class Server:
     """A zeus_server: submit problems from any thread, wait for their results.
 
@@ -427,6 +443,11 @@ class DeviceSolve:
 
     def enqueue(self, ctx, stream_ptr: int = 0):
         zeus_minimize_async(ctx, self.pb, self.ws_ptr, self.ws_bytes, self.result, stream_ptr)
+
+    def enqueue_static(self, ctx, stream_ptr: int = 0):
+        """The same solve in the library's fixed workspace (this object's own
+        workspace tensor is not used)."""
+        zeus_minimize_async_static(ctx, self.pb, self.result, stream_ptr)
 
     def summary(self) -> dict:
         raw = bytes(self.t["summary"].cpu().numpy().tobytes())

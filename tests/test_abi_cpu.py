@@ -127,3 +127,10 @@ def test_context_without_device_is_a_clean_error(Z):
     with pytest.raises(Z.ZeusError) as e:
         Z.zeus_context_create(0)
     assert e.value.code in (Z.EHIP, Z.EINVAL)
+
+
+def test_static_workspace_size_matches_header(Z):
+    src = open(HEADER).read()
+    m = re.search(r"#define ZEUS_STATIC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m, "ZEUS_STATIC_WORKSPACE_BYTES not found"
+    assert Z.STATIC_WORKSPACE_BYTES == int(m.group(1)) << int(m.group(2))
