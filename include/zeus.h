@@ -108,8 +108,10 @@ typedef struct zeus_problem {
                             (Alg. 10), read iteration-synchronously: K* is the
                             iteration at which the c-th start converges, and
                             every start still running at K* ends there with
-                            status ZEUS_ST_STOPPED.  Blocking and server entry
-                            points only (async and plans: ZEUS_EUNSUPPORTED)   */
+                            status ZEUS_ST_STOPPED (its K*-th iterate).  Decided
+                            on the device, with no host round trip, at every
+                            entry point; the workspace grows by
+                            4 (iter_bfgs + 5) bytes                           */
   uint64_t seed;         /* Philox key word 0                                      */
   uint64_t request_id;   /* Philox key word 1                                      */
 } zeus_problem;
@@ -226,8 +228,7 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem,
  * zeus_minimize_async, and the results are the same.  Only enqueues work on
  * `stream` (NULL = the context's stream).  ZEUS_ENOMEM, with nothing
  * enqueued, when zeus_workspace_bytes() of the problem exceeds
- * ZEUS_STATIC_WORKSPACE_BYTES; ZEUS_EUNSUPPORTED with required_converged > 0
- * (as zeus_minimize_async).  Every call on one GPU uses that GPU's one
+ * ZEUS_STATIC_WORKSPACE_BYTES.  Every call on one GPU uses that GPU's one
  * array, which keeps the last call's contents: calls whose device work
  * overlaps (different streams, or different contexts on the same GPU,
  * without ordering between them) race and give wrong results; calls on one
@@ -263,23 +264,33 @@ zeus_err zeus_plan_launch(zeus_plan *plan, void *stream);
 zeus_err zeus_plan_destroy(zeus_plan *plan);
 
 /* ------------------------------------------------------------------------ */
-/* Serving: a request loop with continuous batching.                        */
+/* Serving: a request loop with continuous batching of starts.              */
 /*                                                                          */
-/* The paper solves one problem per call (Alg. 7).  A server keeps a queue  */
-/* of such problems from any number of callers and runs them as batches    */
-/* (see zeus_minimize_batch) while further requests arrive:                 */
-/*  - zeus_server_create allocates the server's whole device-memory budget  */
-/*    once and starts one worker thread;                                    */
-/*  - requests wait in arrival order; whenever fewer than four batches are  */
-/*    running, the worker forms a new batch from the longest prefix of the  */
-/*    queue whose device footprint (results, swarm state, tables, H slots)  */
-/*    fits in the largest free piece of the budget, and launches it on its  */
-/*    own stream;                                                           */
-/*  - when a batch finishes, its results are in the callers' host arrays,   */
-/*    its memory returns to the budget and its tickets complete.            */
-/* Inside a batch every start retires on its own (the BFGS kernels take the */
-/* next start when one converges).  A request's results are bit-identical  */
-/* to solving it alone with zeus_minimize.                                  */
+/* The paper solves one problem per call (Alg. 7).  A server takes such     */
+/* problems from any number of callers and runs them together while more   */
+/* arrive, sharing the GPU at the level of starts:                          */
+/*  - zeus_server_create allocates the server's device-memory budget once   */
+/*    and starts one scheduling thread;                                     */
+/*  - requests wait in arrival order and are admitted, oldest first, as     */
+/*    soon as their own device memory (result arrays, swarm state, early-   */
+/*    stop state, a one-request table) fits in the free budget; there is no */
+/*    limit on the number of requests in flight but memory.  An admitted    */
+/*    request runs its swarm (Alg. 2 / 3) at once;                          */
+/*  - BFGS runs in steps: one persistent kernel launch over slices of the   */
+/*    starts of every swarm-finished request of one kernel class (objective,*/
+/*    precision, method, lanes), each request taking an equal share, so a   */
+/*    short request is not queued behind a long one.  Inside a step a      */
+/*    group of lanes takes the next start of any slice when its start       */
+/*    retires.  A step runs about four starts per resident group, and two   */
+/*    steps run at a time, so requests join within a step's time;          */
+/*  - when all starts of a request have run, its best-of-N (Alg. 7) and the */
+/*    copies into the caller's arrays finish it and its memory returns to   */
+/*    the budget at once.                                                   */
+/* A request with required_converged > 0 runs whole in one step of its own */
+/* (its stop depends on all its starts).  A request's results are bit-      */
+/* identical to solving it alone with zeus_minimize.  A quarter of the      */
+/* budget (at most 2 GiB) is kept for the two steps' request tables and the */
+/* H slots of problems above 64 dimensions.                                 */
 /* All server calls are thread-safe.                                        */
 /* ------------------------------------------------------------------------ */
 typedef struct zeus_server zeus_server;
@@ -287,13 +298,21 @@ typedef struct zeus_server zeus_server;
 /* Host steady-clock times (nanoseconds, arbitrary origin) of one request. */
 typedef struct zeus_request_times {
   uint64_t t_submit_ns;  /* zeus_server_submit accepted it                  */
-  uint64_t t_admit_ns;   /* its batch was launched                          */
+  uint64_t t_admit_ns;   /* its memory was allocated and its swarm launched */
   uint64_t t_done_ns;    /* its results were in the host arrays             */
 } zeus_request_times;
 
 /* Creates a server on the device of ctx with hbm_budget_bytes of device
- * memory (>= 1 MiB).  The context must outlive the server. */
+ * memory (>= 1 MiB).  min(budget / 4, 2 GiB) of it holds the two steps'
+ * tables and H slots; the rest is for requests.  The context must outlive
+ * the server. */
 zeus_err zeus_server_create(zeus_context *ctx, size_t hbm_budget_bytes, zeus_server **out);
+
+/* Device bytes a request holds from admission until its results are in
+ * host_out: its result arrays (the outputs host_out asks for), swarm state,
+ * early-stop state and one-request table.  ZEUS_EINVAL as zeus_server_submit. */
+zeus_err zeus_server_request_bytes(const zeus_problem *problem, const zeus_result *host_out,
+                                   size_t *bytes);
 
 /* Queues one problem.  host_out is as for zeus_minimize (host memory) and,
  * with the problem it points to, must stay valid until the ticket has been
@@ -317,9 +336,28 @@ zeus_err zeus_server_wait(zeus_server *srv, uint64_t ticket, int64_t timeout_ns,
  * request already launched cannot be stopped: ZEUS_NOT_READY, wait for it. */
 zeus_err zeus_server_cancel(zeus_server *srv, uint64_t ticket);
 
-/* Cancels every queued request, waits for the running batches, stops the
- * worker and frees the budget. */
+/* Cancels every queued request, waits for the admitted ones, stops the
+ * scheduling thread and frees the budget. */
 zeus_err zeus_server_destroy(zeus_server *srv);
+
+/* The scheduling of a server without a GPU, for testing admission, queueing,
+ * cancellation and the sharing of steps on the host.  Nothing runs on a
+ * device and no device memory is touched: the budget is only accounted.  An
+ * admitted request's swarm takes swarm_ns of host time, a step takes
+ * step_ns plus start_ns for every resident_starts starts it runs (rounded
+ * up), and finishing a request takes finish_ns; the results written into the
+ * caller's arrays are placeholders (f = request_id, x = 0, iters = 0, status
+ * ZEUS_ST_MAXITER; summary best_index 0, best_f = request_id, counts 0). */
+typedef struct zeus_emulation {
+  uint64_t swarm_ns, step_ns, start_ns, finish_ns;
+  int64_t resident_starts;  /* starts a step runs at once (> 0)              */
+} zeus_emulation;
+
+/* A server as zeus_server_create, on the emulated device of *emu (copied);
+ * use it with zeus_server_submit / wait / cancel / destroy.  ZEUS_EINVAL
+ * for a NULL argument, resident_starts < 1 or a budget below 1 MiB. */
+zeus_err zeus_server_create_emulated(size_t hbm_budget_bytes, const zeus_emulation *emu,
+                                     zeus_server **out);
 
 /* ------------------------------------------------------------------------ */
 /* User-defined objectives.                                                 */

@@ -24,9 +24,11 @@
 #include <string>
 #include <vector>
 
+#include "zeus_host.h"
 #include "zeus_internal.h"
 
-namespace {
+namespace zeus {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -39,11 +41,7 @@ zeus_err hip_fail(hipError_t e, const char *what) {
   return fail(ZEUS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Argument checks shared by every entry point taking a problem.
-zeus_err check_problem(const zeus_problem *p, bool user = false) {
+zeus_err check_problem(const zeus_problem *p, bool user) {
   if (!p) return fail(ZEUS_EINVAL, "problem is NULL");
   if (p->abi_version != ZEUS_ABI_VERSION) return fail(ZEUS_EINVAL, "abi_version mismatch");
   if (user) {
@@ -95,28 +93,18 @@ zeus_err check_result(const zeus_result *r, const zeus_problem *p) {
   return ZEUS_OK;
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  hipError_t err = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    err = hipGetDevice(&prev);
-    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+}  // namespace host
+}  // namespace zeus
 
-}  // namespace
+using namespace zeus::host;
 
 namespace zeus {
 
 namespace {
 struct Layout {
-  size_t best, gx, best_store, gx_store, part_key, part_f, part_idx, part_x, x, v, px, pf, total;
+  size_t best, gx, best_store, gx_store, part_key, part_f, part_idx, part_x, x, v, px, pf, es, total;
 };
-Layout layout(int64_t n, int dim) {
+Layout layout(int64_t n, int dim, int es_len) {
   const size_t P = (size_t)pso_blocks(n, dim), N = (size_t)n, D = (size_t)dim;
   Layout l;
   size_t o = 0;
@@ -137,15 +125,16 @@ Layout layout(int64_t n, int dim) {
   l.v = take(sizeof(double) * N * D);
   l.px = take(sizeof(double) * N * D);
   l.pf = take(sizeof(double) * N);
+  l.es = es_len > 0 ? take(sizeof(int32_t) * (size_t)es_len) : SIZE_MAX;
   l.total = o;
   return l;
 }
 }  // namespace
 
-size_t workspace_bytes(int64_t n, int dim) { return layout(n, dim).total; }
+size_t workspace_bytes(int64_t n, int dim, int es_len) { return layout(n, dim, es_len).total; }
 
-Workspace carve_workspace(void *base, int64_t n, int dim) {
-  const Layout l = layout(n, dim);
+Workspace carve_workspace(void *base, int64_t n, int dim, int es_len) {
+  const Layout l = layout(n, dim, es_len);
   char *p = static_cast<char *>(base);
   Workspace w;
   w.best = reinterpret_cast<PsoBest *>(p + l.best);
@@ -160,6 +149,7 @@ Workspace carve_workspace(void *base, int64_t n, int dim) {
   w.v = reinterpret_cast<double *>(p + l.v);
   w.px = reinterpret_cast<double *>(p + l.px);
   w.pf = reinterpret_cast<double *>(p + l.pf);
+  w.es = l.es == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(p + l.es);
   w.pso_blocks = pso_blocks(n, dim);
   return w;
 }
@@ -218,6 +208,8 @@ struct zeus_context {
   const zeus::UserKernels *active_user = nullptr;
 };
 
+int zeus::host::context_device(const zeus_context *ctx) { return ctx->device; }
+
 struct zeus_user_objective {
   int device = 0;
   zeus::UserKernels k{};
@@ -228,11 +220,8 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
 void user_release(UserKernels *k);
 }  // namespace zeus
 
-namespace {
-
-constexpr size_t kHdrBytes = 256;  // BatchDev, padded
-
-size_t table_bytes(int nreq) { return align_up(sizeof(zeus::ReqDev) * (size_t)nreq); }
+namespace zeus {
+namespace host {
 
 zeus_err ensure(void **buf, size_t *cap, size_t need) {
   if (*cap >= need) return ZEUS_OK;
@@ -267,13 +256,6 @@ zeus_err drain_profile(zeus_context *ctx) {
   return ZEUS_OK;
 }
 
-// One request of a launch group: its problem, device outputs and workspace.
-struct Planned {
-  const zeus_problem *pb;
-  zeus_result dev;          // device pointers
-  zeus::Workspace ws;
-};
-
 int max_dim(const std::vector<Planned> &reqs) {
   int d = 0;
   for (const Planned &q : reqs) d = q.pb->dim > d ? q.pb->dim : d;
@@ -305,18 +287,21 @@ int lanes_of(const zeus_problem &p) {
 }
 // Only BFGS above the narrow limit keeps H in device-memory slots.
 int hslot_lanes(const zeus_problem &p) { return method_of(p) ? 0 : lanes_of(p); }
-
-// A launch group ready to run: the kernels' view (Group) and the host copy of
-// its request table.
-struct GroupRun {
-  zeus::Group g;
-  std::vector<zeus::ReqDev> host;
-};
+// Ints of early-stop state in a request's workspace (0 without early stop).
+int es_len_of(const zeus_problem &p) {
+  return p.required_converged > 0 ? zeus::es_ints(p.iter_bfgs) : 0;
+}
+size_t request_ws_bytes(const zeus_problem &p) {
+  return zeus::workspace_bytes(p.n_starts, p.dim, es_len_of(p));
+}
+zeus::Workspace carve_request_ws(void *base, const zeus_problem &p) {
+  return zeus::carve_workspace(base, p.n_starts, p.dim, es_len_of(p));
+}
 
 // Builds the launch group of requests that share objective, precision and
 // lane counts (nothing is enqueued).
 zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hslots,
-                     hipStream_t stream, GroupRun *run) {
+                     hipStream_t stream, GroupRun *run, bool need_hslots) {
   zeus::Group &g = run->g;
   std::vector<zeus::ReqDev> &host = run->host;
   const zeus_problem &p0 = *reqs[0].pb;
@@ -337,6 +322,8 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
   g.wide_cs = 0;
   g.wide_slot_doubles = 0;
   g.user = nullptr;
+  g.early_stop = false;
+  g.resident = nullptr;
   host.assign(reqs.size(), zeus::ReqDev{});
   for (size_t r = 0; r < reqs.size(); ++r) {
     const zeus_problem &p = *reqs[r].pb;
@@ -371,6 +358,8 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
     q.summary = reqs[r].dev.summary;
     q.start_offset = g.total_starts;
     q.block_offset = g.pso_grid;
+    q.required_c = p.required_converged;
+    if (p.required_converged > 0) g.early_stop = true;
     g.total_starts += p.n_starts;
     g.pso_grid += q.ws.pso_blocks;
     if (p.iter_pso > g.max_iter_pso) g.max_iter_pso = p.iter_pso;
@@ -380,7 +369,7 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
     g.wide_slots = zeus::wide_slots(g.total_starts);
     g.wide_cs = zeus::wide_cs(dmax);
     g.wide_slot_doubles = (int64_t)dmax * g.wide_cs;
-    if (!hslots) return fail(ZEUS_EINVAL, "wide problem without H slots");
+    if (!hslots && need_hslots) return fail(ZEUS_EINVAL, "wide problem without H slots");
   }
   return ZEUS_OK;
 }
@@ -419,7 +408,7 @@ zeus_err enqueue_copies(const std::vector<Planned> &reqs, hipStream_t stream) {
 // its starts, one summary block per request, then (with_copies) the optional
 // swarm-state copies.  The request table must already be on the device.
 zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<Planned> &reqs,
-                      bool with_copies, bool with_swarm = true) {
+                      bool with_copies, bool with_swarm) {
   zeus::Group g = run.g;
   if (g.objective == ZEUS_USER) {
     g.user = ctx ? ctx->active_user : nullptr;
@@ -441,6 +430,10 @@ zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<
   }
   if (prof) (void)hipEventRecord(pend.ev[1], stream);
   if ((e = zeus::launch_bfgs(g)) != hipSuccess) return hip_fail(e, "BFGS launch");
+  if (g.early_stop) {  // K*, then the rerun of the starts that went past it
+    if ((e = zeus::launch_es_finish(g)) != hipSuccess) return hip_fail(e, "early-stop launch");
+    if ((e = zeus::launch_bfgs(g)) != hipSuccess) return hip_fail(e, "BFGS launch");
+  }
   if (prof) (void)hipEventRecord(pend.ev[2], stream);
   if ((e = zeus::launch_summary(g)) != hipSuccess) return hip_fail(e, "summary launch");
   if (prof) (void)hipEventRecord(pend.ev[3], stream);
@@ -451,58 +444,10 @@ zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<
   if (prof) {
     ctx->pending.push_back(pend);
     ctx->prof.pso_launches += with_swarm ? 3 + g.max_iter_pso : 0;
-    ctx->prof.bfgs_launches += 1;
+    ctx->prof.bfgs_launches += g.early_stop ? 2 : 1;
     ctx->prof.reduce_launches += 1;
   }
   return ZEUS_OK;
-}
-
-// Alg. 10's early stop for one request (required_converged = c > 0), read
-// iteration-synchronously: K* is the iteration at which the c-th start
-// converges; every start still running at K* ends there with status STOPPED.
-// The swarm runs once; BFGS then runs from its seeds with an iteration cap
-// of 16, 64, ... (x4, at most iter_bfgs) until at least c starts have
-// converged, and a last time with the cap at K* when K* is below the cap.
-// Each pass is deterministic, so the result is the same as a run that stops
-// every start at K*.  Synchronises `stream` between passes.
-zeus_err run_required(zeus_context *ctx, const std::vector<Planned> &reqs, void *hdr_table,
-                      void *hslots, hipStream_t stream) {
-  const zeus_problem &p = *reqs[0].pb;
-  const int64_t c = p.required_converged, n = p.n_starts;
-  std::vector<int32_t> it((size_t)n), st((size_t)n);
-  int cap = p.iter_bfgs < 16 ? p.iter_bfgs : 16;
-  bool swarm = true, last = false;
-  zeus_err e;
-  for (;;) {
-    GroupRun run;
-    if ((e = build_group(reqs, hdr_table, hslots, stream, &run)) != ZEUS_OK) return e;
-    run.host[0].iter_bfgs = cap;
-    run.host[0].stop_status = cap < p.iter_bfgs ? ZEUS_ST_STOPPED : ZEUS_ST_MAXITER;
-    if ((e = upload_group(run, stream)) != ZEUS_OK) return e;
-    if ((e = launch_group(ctx, run, reqs, false, swarm)) != ZEUS_OK) return e;
-    swarm = false;
-    if (last) break;
-    hipError_t he = hipMemcpyAsync(it.data(), reqs[0].dev.iters, 4 * (size_t)n, hipMemcpyDeviceToHost, stream);
-    if (he == hipSuccess)
-      he = hipMemcpyAsync(st.data(), reqs[0].dev.status, 4 * (size_t)n, hipMemcpyDeviceToHost, stream);
-    if (he == hipSuccess) he = hipStreamSynchronize(stream);
-    if (he != hipSuccess) return hip_fail(he, "early-stop pass");
-    std::vector<int32_t> conv;
-    for (int64_t i = 0; i < n; ++i)
-      if (st[(size_t)i] == ZEUS_ST_CONVERGED) conv.push_back(it[(size_t)i]);
-    if ((int64_t)conv.size() >= c) {
-      std::nth_element(conv.begin(), conv.begin() + (c - 1), conv.end());
-      const int kstar = conv[(size_t)(c - 1)];
-      if (kstar == cap) break;
-      cap = kstar;
-      last = true;
-    } else if (cap >= p.iter_bfgs) {
-      break;  // fewer than c starts converge within the budget: no early stop
-    } else {
-      cap = cap * 4 < p.iter_bfgs ? cap * 4 : p.iter_bfgs;
-    }
-  }
-  return enqueue_copies(reqs, stream);
 }
 
 // Build, upload and launch one group on `stream`.
@@ -514,11 +459,6 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
   if (e == ZEUS_OK) e = launch_group(ctx, run, reqs, true);
   return e;
 }
-
-// Device result layout of one request for the blocking entry points.
-struct ResLayout {
-  size_t f, x, it, st, ls, seed, v, px, pf, gx, tr, sum, total;
-};
 
 ResLayout res_layout(const zeus_problem &pb, const zeus_result &out) {
   const size_t n = (size_t)pb.n_starts, d = (size_t)pb.dim;
@@ -591,9 +531,7 @@ zeus_err copy_back(const zeus_problem &pb, const zeus_result &out, const zeus_re
 // lane counts run in one group.
 struct GroupKey {
   int objective, precision, method, g_pso, g_bfgs;
-  int64_t solo;  // > 0: a request with early stop, in a group of its own
   bool operator<(const GroupKey &o) const {
-    if (solo != o.solo) return solo < o.solo;
     if (objective != o.objective) return objective < o.objective;
     if (method != o.method) return method < o.method;
     if (precision != o.precision) return precision < o.precision;
@@ -602,9 +540,9 @@ struct GroupKey {
   }
 };
 
-GroupKey key_of(const zeus_problem &p, int32_t index) {
+GroupKey key_of(const zeus_problem &p) {
   return GroupKey{p.objective, p.precision, method_of(p), zeus::pso_group_lanes(p.dim),
-                  lanes_of(p), p.required_converged > 0 ? (int64_t)index + 1 : 0};
+                  lanes_of(p)};
 }
 
 // Device memory plan of a batch: result arrays of every request, then the
@@ -621,7 +559,7 @@ struct BatchPlan {
 BatchPlan plan_batch(const zeus_problem *problems, const zeus_result *outs, int32_t n) {
   BatchPlan b;
   for (int32_t r = 0; r < n; ++r) {
-    const GroupKey k = key_of(problems[r], r);
+    const GroupKey k = key_of(problems[r]);
     auto it = b.groups.find(k);
     if (it == b.groups.end()) b.order.push_back(k);
     b.groups[k].push_back(r);
@@ -634,7 +572,7 @@ BatchPlan plan_batch(const zeus_problem *problems, const zeus_result *outs, int3
     b.res_off[r] = b.res_total;
     b.res_total += b.rl[r].total;
     b.ws_off[r] = b.ws_total;
-    b.ws_total += zeus::workspace_bytes(problems[r].n_starts, problems[r].dim);
+    b.ws_total += request_ws_bytes(problems[r]);
   }
   b.tab_off.resize(b.order.size());
   b.h_off.resize(b.order.size());
@@ -671,14 +609,10 @@ zeus_err enqueue_batch(zeus_context *ctx, const BatchPlan &b, const zeus_problem
       const int32_t r = members[k];
       plan[k].pb = &problems[r];
       plan[k].dev = carve_result(R + b.res_off[r], b.rl[r], outs[r]);
-      plan[k].ws = zeus::carve_workspace(Wb + b.ws_off[r], problems[r].n_starts, problems[r].dim);
+      plan[k].ws = carve_request_ws(Wb + b.ws_off[r], problems[r]);
     }
     void *hs = b.h_off[gi] == SIZE_MAX ? nullptr : Wb + b.h_off[gi];
-    if (b.order[gi].solo > 0)
-      e = run_required(ctx, plan, Wb + b.tab_off[gi], hs, s);
-    else
-      e = enqueue_group(ctx, plan, Wb + b.tab_off[gi], hs, s);
-    if (e != ZEUS_OK) return e;
+    if ((e = enqueue_group(ctx, plan, Wb + b.tab_off[gi], hs, s)) != ZEUS_OK) return e;
     for (size_t k = 0; k < members.size(); ++k)
       if ((e = copy_back(problems[members[k]], outs[members[k]], plan[k].dev, s)) != ZEUS_OK)
         return e;
@@ -692,64 +626,54 @@ uint64_t now_ns() {
       .count();
 }
 
-// First-fit allocator over [0, size) of one device allocation.
-class Pool {
- public:
-  void reset(size_t size) {
-    free_.clear();
-    if (size) free_[0] = size;
-  }
-  bool alloc(size_t bytes, size_t *off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it)
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes, at = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        return true;
-      }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    auto it = free_.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != free_.end() && it->first + it->second == next->first) {
-      it->second += next->second;
-      free_.erase(next);
+void Pool::reset(size_t size) {
+  free_.clear();
+  if (size) free_[0] = size;
+}
+
+bool Pool::alloc(size_t bytes, size_t *off) {
+  for (auto it = free_.begin(); it != free_.end(); ++it)
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes, at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      return true;
     }
-    if (it != free_.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == it->first) {
-        prev->second += it->second;
-        free_.erase(it);
-      }
+  return false;
+}
+
+void Pool::release(size_t off, size_t bytes) {
+  auto it = free_.emplace(off, bytes).first;
+  auto next = std::next(it);
+  if (next != free_.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    free_.erase(next);
+  }
+  if (it != free_.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      free_.erase(it);
     }
   }
-  size_t largest() const {
-    size_t m = 0;
-    for (auto &kv : free_) m = kv.second > m ? kv.second : m;
-    return m;
-  }
+}
 
- private:
-  std::map<size_t, size_t> free_;  // offset -> size
-};
+size_t Pool::largest() const {
+  size_t m = 0;
+  for (auto &kv : free_) m = kv.second > m ? kv.second : m;
+  return m;
+}
 
-enum TicketState { kQueued, kRunning, kDone, kCancelled, kFailed };
+size_t Pool::free_bytes() const {
+  size_t t = 0;
+  for (auto &kv : free_) t += kv.second;
+  return t;
+}
 
-struct Ticket {
-  zeus_problem pb;
-  zeus_result out;
-  size_t bytes = 0;  // footprint of the request alone
-  TicketState state = kQueued;
-  zeus_err err = ZEUS_OK;
-  std::string msg;
-  zeus_request_times times{};
-};
 
-size_t footprint(const BatchPlan &b) { return align_up(b.res_total) + align_up(b.ws_total); }
-
-}  // namespace
+}  // namespace host
+}  // namespace zeus
 
 // A captured solve: the kernels of every launch group of a batch in one HIP
 // graph, bound to a caller-owned workspace and device outputs.
@@ -757,105 +681,6 @@ struct zeus_plan {
   int device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-};
-
-constexpr int kServerSlots = 4;       // batches in flight, one worker thread each
-constexpr int kServerMaxBatch = 512;  // requests per batch
-
-struct zeus_server {
-  zeus_context *ctx = nullptr;
-  int device = 0;
-  void *mem = nullptr;
-  size_t budget = 0;
-  Pool pool;
-  hipStream_t streams[kServerSlots] = {};
-  std::mutex mu;
-  std::condition_variable cv;        // workers: new requests or freed memory
-  std::condition_variable done_cv;   // waiters: a ticket changed state
-  std::deque<uint64_t> queue;
-  std::unordered_map<uint64_t, Ticket> tickets;
-  uint64_t next_id = 1;
-  bool stopping = false;
-  std::vector<std::thread> workers;
-
-  // Takes the longest prefix of the queue whose batch fits in the largest
-  // free piece of the budget (lock held).  Returns false if the queue is
-  // empty or its head does not fit now.
-  bool take_batch(std::vector<uint64_t> &ids, std::vector<zeus_problem> &pbs,
-                  std::vector<zeus_result> &outs, BatchPlan &plan, size_t &off, size_t &need) {
-    const size_t room = pool.largest();
-    ids.clear();
-    pbs.clear();
-    outs.clear();
-    need = 0;
-    for (uint64_t id : queue) {
-      if ((int)ids.size() == kServerMaxBatch) break;
-      const Ticket &t = tickets.at(id);
-      pbs.push_back(t.pb);
-      outs.push_back(t.out);
-      BatchPlan trial = plan_batch(pbs.data(), outs.data(), (int32_t)pbs.size());
-      const size_t f = footprint(trial);
-      if (f > room) {
-        pbs.pop_back();
-        outs.pop_back();
-        break;
-      }
-      ids.push_back(id);
-      plan = std::move(trial);
-      need = f;
-    }
-    if (ids.empty()) return false;
-    for (size_t k = 0; k < ids.size(); ++k) queue.pop_front();
-    (void)pool.alloc(need, &off);
-    const uint64_t t0 = now_ns();
-    for (uint64_t id : ids) {
-      Ticket &t = tickets.at(id);
-      t.state = kRunning;
-      t.times.t_admit_ns = t0;
-    }
-    return true;
-  }
-
-  void work(int slot) {
-    (void)hipSetDevice(device);
-    std::vector<uint64_t> ids;
-    std::vector<zeus_problem> pbs;
-    std::vector<zeus_result> outs;
-    BatchPlan plan;
-    std::unique_lock<std::mutex> lk(mu);
-    for (;;) {
-      if (stopping && queue.empty()) break;
-      size_t off = 0, need = 0;
-      if (!take_batch(ids, pbs, outs, plan, off, need)) {
-        cv.wait(lk);
-        continue;
-      }
-      lk.unlock();
-      // enqueue the batch and its copies into the callers' arrays, then wait
-      char *base = static_cast<char *>(mem) + off;
-      std::vector<hipStream_t> st{streams[slot]};
-      zeus_err e = enqueue_batch(nullptr, plan, pbs.data(), outs.data(), base,
-                                 base + align_up(plan.res_total), st);
-      std::string msg = e != ZEUS_OK ? g_last_error : std::string();
-      hipError_t he = hipStreamSynchronize(streams[slot]);
-      if (e == ZEUS_OK && he != hipSuccess) {
-        e = ZEUS_EHIP;
-        msg = std::string("hipStreamSynchronize: ") + hipGetErrorString(he);
-      }
-      const uint64_t t1 = now_ns();
-      lk.lock();
-      for (uint64_t id : ids) {
-        Ticket &t = tickets.at(id);
-        t.state = e == ZEUS_OK ? kDone : kFailed;
-        t.err = e;
-        t.msg = msg;
-        t.times.t_done_ns = t1;
-      }
-      pool.release(off, need);
-      done_cv.notify_all();
-      cv.notify_all();  // freed memory may let a waiting head in
-    }
-  }
 };
 
 extern "C" {
@@ -876,7 +701,7 @@ zeus_err zeus_workspace_bytes(const zeus_problem *problem, size_t *bytes) {
   if (!bytes) return fail(ZEUS_EINVAL, "bytes is NULL");
   zeus_err e = check_problem(problem);
   if (e != ZEUS_OK) return e;
-  *bytes = kHdrBytes + table_bytes(1) + zeus::workspace_bytes(problem->n_starts, problem->dim) +
+  *bytes = kHdrBytes + table_bytes(1) + request_ws_bytes(*problem) +
            hslot_bytes(hslot_lanes(*problem), problem->n_starts, problem->dim);
   return ZEUS_OK;
 }
@@ -960,8 +785,6 @@ zeus_err check_async(zeus_context *ctx, const zeus_problem *problem, const zeus_
   zeus_err e = check_problem(problem);
   if (e != ZEUS_OK) return e;
   if ((e = check_result(out, problem)) != ZEUS_OK) return e;
-  if (problem->required_converged > 0)
-    return fail(ZEUS_EUNSUPPORTED, "early stopping needs zeus_minimize, zeus_minimize_batch or a server");
   return zeus_workspace_bytes(problem, need);
 }
 
@@ -977,8 +800,8 @@ zeus_err enqueue_async(zeus_context *ctx, const zeus_problem &pb, void *workspac
     one[0].dev.trace = nullptr;
     one[0].dev.trace_len = 0;
   }
-  const size_t ws_bytes = zeus::workspace_bytes(pb.n_starts, pb.dim);
-  one[0].ws = zeus::carve_workspace(base + kHdrBytes + table_bytes(1), pb.n_starts, pb.dim);
+  const size_t ws_bytes = request_ws_bytes(pb);
+  one[0].ws = carve_request_ws(base + kHdrBytes + table_bytes(1), pb);
   void *hslots = hslot_bytes(hslot_lanes(pb), pb.n_starts, pb.dim)
                      ? base + kHdrBytes + table_bytes(1) + ws_bytes
                      : nullptr;
@@ -1131,150 +954,6 @@ zeus_err zeus_objective_destroy(zeus_user_objective *obj) {
 }
 
 
-zeus_err zeus_server_create(zeus_context *ctx, size_t hbm_budget_bytes, zeus_server **out) {
-  g_last_error.clear();
-  if (!ctx || !out) return fail(ZEUS_EINVAL, "NULL argument");
-  *out = nullptr;
-  if (hbm_budget_bytes < ((size_t)1 << 20)) return fail(ZEUS_EINVAL, "budget below 1 MiB");
-  auto *srv = new (std::nothrow) zeus_server;
-  if (!srv) return fail(ZEUS_ENOMEM, "server allocation failed");
-  srv->ctx = ctx;
-  srv->device = ctx->device;
-  DeviceGuard g(ctx->device);
-  if (g.err != hipSuccess) {
-    delete srv;
-    return hip_fail(g.err, "hipSetDevice");
-  }
-  srv->budget = hbm_budget_bytes / kAlign * kAlign;
-  hipError_t e = hipMalloc(&srv->mem, srv->budget);
-  if (e != hipSuccess) {
-    delete srv;
-    return fail(ZEUS_ENOMEM, std::string("hipMalloc of the budget: ") + hipGetErrorString(e));
-  }
-  srv->pool.reset(srv->budget);
-  for (auto &st : srv->streams) {
-    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) {
-      for (auto &s2 : srv->streams)
-        if (s2) (void)hipStreamDestroy(s2);
-      (void)hipFree(srv->mem);
-      delete srv;
-      return hip_fail(e, "hipStreamCreate");
-    }
-  }
-  for (int k = 0; k < kServerSlots; ++k) srv->workers.emplace_back([srv, k] { srv->work(k); });
-  *out = srv;
-  return ZEUS_OK;
-}
-
-zeus_err zeus_server_submit(zeus_server *srv, const zeus_problem *problem,
-                            const zeus_result *host_out, uint64_t *ticket) {
-  g_last_error.clear();
-  if (!srv || !ticket) return fail(ZEUS_EINVAL, "NULL argument");
-  zeus_err e = check_problem(problem);
-  if (e == ZEUS_OK) e = check_result(host_out, problem);
-  if (e != ZEUS_OK) return e;
-  Ticket t;
-  t.pb = *problem;
-  t.out = *host_out;
-  if (!t.out.trace || t.out.trace_len == 0) {
-    t.out.trace = nullptr;
-    t.out.trace_len = 0;
-  }
-  t.bytes = footprint(plan_batch(&t.pb, &t.out, 1));
-  if (t.bytes > srv->budget)
-    return fail(ZEUS_ENOMEM, "request needs " + std::to_string(t.bytes) +
-                                 " bytes of device memory, more than the server's budget");
-  t.times.t_submit_ns = now_ns();
-  std::lock_guard<std::mutex> lk(srv->mu);
-  if (srv->stopping) return fail(ZEUS_ECANCELLED, "server is shutting down");
-  const uint64_t id = srv->next_id++;
-  srv->tickets.emplace(id, t);
-  srv->queue.push_back(id);
-  *ticket = id;
-  srv->cv.notify_one();
-  return ZEUS_OK;
-}
-
-zeus_err zeus_server_wait(zeus_server *srv, uint64_t ticket, int64_t timeout_ns,
-                          zeus_request_times *times) {
-  g_last_error.clear();
-  if (!srv) return fail(ZEUS_EINVAL, "srv is NULL");
-  std::unique_lock<std::mutex> lk(srv->mu);
-  const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns > 0 ? timeout_ns : 0);
-  for (;;) {
-    auto it = srv->tickets.find(ticket);
-    if (it == srv->tickets.end()) return fail(ZEUS_EINVAL, "unknown or released ticket");
-    Ticket &t = it->second;
-    if (t.state == kDone || t.state == kCancelled || t.state == kFailed) {
-      if (times) *times = t.times;
-      const TicketState st = t.state;
-      const zeus_err err = t.err;
-      const std::string msg = t.msg;
-      srv->tickets.erase(it);
-      if (st == kDone) return ZEUS_OK;
-      if (st == kCancelled) return fail(ZEUS_ECANCELLED, "request was cancelled");
-      return fail(err, msg);
-    }
-    if (timeout_ns == 0) return ZEUS_NOT_READY;
-    if (timeout_ns < 0) {
-      srv->done_cv.wait(lk);
-    } else if (srv->done_cv.wait_until(lk, deadline) == std::cv_status::timeout) {
-      auto again = srv->tickets.find(ticket);
-      if (again != srv->tickets.end() && (again->second.state == kQueued || again->second.state == kRunning))
-        return fail(ZEUS_ETIMEOUT, "timed out");
-    }
-  }
-}
-
-zeus_err zeus_server_cancel(zeus_server *srv, uint64_t ticket) {
-  g_last_error.clear();
-  if (!srv) return fail(ZEUS_EINVAL, "srv is NULL");
-  std::lock_guard<std::mutex> lk(srv->mu);
-  auto it = srv->tickets.find(ticket);
-  if (it == srv->tickets.end()) return fail(ZEUS_EINVAL, "unknown or released ticket");
-  if (it->second.state != kQueued) {
-    if (it->second.state == kRunning) {
-      g_last_error = "request is running; wait for it";
-      return ZEUS_NOT_READY;
-    }
-    return ZEUS_OK;  // already finished
-  }
-  for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q)
-    if (*q == ticket) {
-      srv->queue.erase(q);
-      break;
-    }
-  it->second.state = kCancelled;
-  srv->done_cv.notify_all();
-  srv->cv.notify_one();
-  return ZEUS_OK;
-}
-
-zeus_err zeus_server_destroy(zeus_server *srv) {
-  g_last_error.clear();
-  if (!srv) return ZEUS_OK;
-  {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    srv->stopping = true;
-    for (uint64_t id : srv->queue) srv->tickets.at(id).state = kCancelled;
-    srv->queue.clear();
-    srv->cv.notify_all();
-    srv->done_cv.notify_all();
-  }
-  for (auto &w : srv->workers) w.join();
-  {
-    DeviceGuard g(srv->device);
-    for (auto &st : srv->streams) {
-      (void)hipStreamSynchronize(st);
-      (void)hipStreamDestroy(st);
-    }
-    (void)hipFree(srv->mem);
-  }
-  delete srv;
-  return ZEUS_OK;
-}
-
-
 zeus_err zeus_plan_workspace_bytes(const zeus_problem *problems, int32_t n, size_t *bytes) {
   g_last_error.clear();
   if (!problems || n < 1 || !bytes) return fail(ZEUS_EINVAL, "need n >= 1 problems and bytes");
@@ -1300,8 +979,6 @@ zeus_err zeus_plan_create(zeus_context *ctx, const zeus_problem *problems, int32
     if (e == ZEUS_OK && (outs[r].seeds || outs[r].pso_v || outs[r].pso_px || outs[r].pso_pf ||
                          outs[r].pso_best_x))
       e = fail(ZEUS_EINVAL, "swarm-state outputs are not available in a plan");
-    if (e == ZEUS_OK && problems[r].required_converged > 0)
-      e = fail(ZEUS_EUNSUPPORTED, "early stopping is not available in a plan");
     if (e != ZEUS_OK) return fail(e, "request " + std::to_string(r) + ": " + g_last_error);
   }
   std::vector<zeus_result> res(outs, outs + n);
@@ -1329,8 +1006,7 @@ zeus_err zeus_plan_create(zeus_context *ctx, const zeus_problem *problems, int32
     for (size_t k = 0; k < idx.size(); ++k) {
       members[gi][k].pb = &problems[idx[k]];
       members[gi][k].dev = res[idx[k]];
-      members[gi][k].ws =
-          zeus::carve_workspace(Wb + b.ws_off[idx[k]], problems[idx[k]].n_starts, problems[idx[k]].dim);
+      members[gi][k].ws = carve_request_ws(Wb + b.ws_off[idx[k]], problems[idx[k]]);
     }
     void *hs = b.h_off[gi] == SIZE_MAX ? nullptr : Wb + b.h_off[gi];
     if ((e = build_group(members[gi], Wb + b.tab_off[gi], hs, ctx->stream, &runs[gi])) != ZEUS_OK)

@@ -96,6 +96,20 @@ __global__ __launch_bounds__(kSumBlock) void summary_kernel(const ReqDev *reqs) 
   }
 }
 
+// Between the two BFGS passes of a group with early stop: K* of every request
+// that stops early, from its complete count of convergences up to K*, and
+// the work counter reset for the second pass.
+__global__ __launch_bounds__(64) void es_finish_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr) {
+  for (int r = threadIdx.x; r < nreq; r += blockDim.x) {
+    const ReqDev &rq = reqs[r];
+    if (rq.ws.es) rq.ws.es[kEsKstar] = es_search(rq.ws.es, rq.iter_bfgs + 1, rq.required_c);
+  }
+  if (threadIdx.x == 0) {
+    hdr->queue = 0ull;
+    hdr->es_pass = 2u;
+  }
+}
+
 // The kernel is persistent: it gets as many blocks as can be resident at once
 // (more would only start once the work counter is spent).
 template <int OBJ, int G, class T>
@@ -107,6 +121,10 @@ hipError_t launch_g(const Group &g, int64_t want, int cus) {
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   const int64_t cap = (int64_t)cus * per_cu;
+  if (g.resident) {
+    *g.resident = cap * (kBfgsBlock / G);
+    return hipSuccess;
+  }
   const int blocks = (int)(want < cap ? want : cap);
   hipLaunchKernelGGL((bfgs_kernel<OBJ, G, T>), dim3(blocks), dim3(kBfgsBlock), lds, g.stream,
                      g.reqs, g.nreq, g.hdr, g.total_starts);
@@ -206,6 +224,11 @@ int wide_cs(int dmax) { return (dmax + 63) / 64 * 64; }
 
 size_t wide_hslot_bytes(int64_t total_starts, int dmax) {
   return sizeof(double) * (size_t)wide_slots(total_starts) * (size_t)dmax * (size_t)wide_cs(dmax);
+}
+
+hipError_t launch_es_finish(const Group &g) {
+  hipLaunchKernelGGL(es_finish_kernel, dim3(1), dim3(64), 0, g.stream, g.reqs, g.nreq, g.hdr);
+  return hipGetLastError();
 }
 
 hipError_t launch_summary(const Group &g) {

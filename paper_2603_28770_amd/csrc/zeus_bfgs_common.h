@@ -17,6 +17,8 @@ struct ReqHot {
   int stop_status;           // status at the iteration budget
   int m_hist;                // L-BFGS pairs kept
   double armijo_c, tol, shrink;
+  int32_t *es;               // early-stop state while a start may stop at its bound
+  int64_t es_c;              // converged starts that stop the request
 };
 constexpr int kHotDoubles = (sizeof(ReqHot) + 7) / 8;
 
@@ -52,8 +54,74 @@ __device__ __forceinline__ int request_of(const ReqDev *reqs, int nreq, int64_t 
   return lo;
 }
 
+// sqrt(gg) < bound, the norm test of a start (gg = g'g), decided exactly as
+// written but without the square root when gg >= 4 bound^2: there the root
+// is at least twice the bound up to a few roundings, so the test fails.
+__device__ __forceinline__ bool norm_below(double gg, double bound) {
+  if (!(gg < (4.0 * bound) * bound)) return false;
+  return sqrt(gg) < bound;
+}
+
+// Relaxed agent-scope access to the early-stop state: its values are only
+// ever bounds (a stale bound is a larger one), so no ordering is needed.
+__device__ __forceinline__ int es_load(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Smallest iteration k at which the counts of the Fenwick tree (nodes
+// 1 .. n, node i for iteration i - 1) reach c convergences at iterations
+// <= k, or -1 when they do not.  With counts read while they still grow the
+// answer can only be too large, never too small.
+__device__ __forceinline__ int es_search(const int32_t *es, int n, int64_t c) {
+  const int32_t *tree = es + kEsTree;
+  int step = 1;
+  while (2 * step <= n) step *= 2;
+  int pos = 0;
+  int64_t rem = c;
+  for (; step > 0; step >>= 1)
+    if (pos + step <= n) {
+      const int64_t t = (uint32_t)es_load(tree + pos + step);
+      if (t < rem) {
+        pos += step;
+        rem -= t;
+      }
+    }
+  return pos < n ? pos : -1;
+}
+
+// A start of a request with early stop has converged at iteration k (one
+// lane per start): count it, and lower the stopping bound to the c-th
+// smallest convergence iteration counted so far.
+__device__ __forceinline__ void es_converged(int32_t *es, int k, int iter_bfgs, int64_t c) {
+  const int n = iter_bfgs + 1;
+  for (int i = k + 1; i <= n; i += i & -i)
+    __hip_atomic_fetch_add(es + kEsTree + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int64_t cnt =
+      (int64_t)(uint32_t)__hip_atomic_fetch_add(es + kEsCount, 1, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT) + 1;
+  if (cnt < c || k >= es_load(es + kEsBound)) return;
+  const int kc = es_search(es, n, c);
+  if (kc >= 0) __hip_atomic_fetch_min(es + kEsBound, kc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Early-stop pass of a launch group (BatchDev::es_pass), read once per kernel.
+__device__ __forceinline__ int es_pass_of(const BatchDev *hdr) {
+  return (int)__hip_atomic_load(&hdr->es_pass, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// In the second pass a claimed start reruns only if its request stops early
+// and the start went past K* in the first pass; every other start keeps the
+// results of the first pass.
+__device__ __forceinline__ bool es_rerun(const ReqDev &rq, int64_t idx) {
+  if (!rq.ws.es) return false;
+  const int ks = es_load(rq.ws.es + kEsKstar);
+  return ks >= 0 && rq.out_iters[idx] > ks;
+}
+
+// The request's scalars for the start a group claimed; in the second
+// early-stop pass the start reruns with K* as its budget and ends STOPPED.
 template <int OBJ>
-__device__ __forceinline__ void load_hot(ReqHot &w, const ReqDev &rq, int ri) {
+__device__ __forceinline__ void load_hot(ReqHot &w, const ReqDev &rq, int ri, int es_pass) {
   w.d = rq.d;
   w.m = Elem<OBJ>::terms(rq.d);
   w.iter_bfgs = rq.iter_bfgs;
@@ -65,8 +133,28 @@ __device__ __forceinline__ void load_hot(ReqHot &w, const ReqDev &rq, int ri) {
   w.armijo_c = rq.armijo_c;
   w.tol = rq.tol;
   w.shrink = rq.shrink;
+  w.es = es_pass == 1 ? rq.ws.es : nullptr;
+  w.es_c = rq.required_c;
+  if (es_pass == 2) {
+    w.iter_bfgs = es_load(rq.ws.es + kEsKstar);
+    w.stop_status = ZEUS_ST_STOPPED;
+  }
 }
 
+// Status of a start at iteration k that is neither non-finite nor converged:
+// the budget, else (first early-stop pass) the stopping bound read at the top
+// of the iteration, else still running (-1).
+__device__ __forceinline__ int budget_status(const ReqHot &q, int k, int bound) {
+  if (k == q.iter_bfgs) return q.stop_status;  // MAXITER, or STOPPED in the rerun
+  if (k >= bound) return ZEUS_ST_STOPPED;
+  return -1;
+}
+
+// Stopping bound of the start's request for this iteration (no bound without
+// early stop).
+__device__ __forceinline__ int es_bound(const ReqHot &q) {
+  return q.es ? es_load(q.es + kEsBound) : 0x7fffffff;
+}
 
 // Line-search trials per round: R trials of G / R lanes each.  64-lane
 // groups take two (d = 50 BFGS 3-7% faster than with four, d = 200 L-BFGS

@@ -99,6 +99,7 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
   int k = 0, ls_trials = 0;
   bool fresh = false, first = true;
   bool hi = !kMixed;  // evaluating in FP64 (always, unless mixed precision)
+  const int es_pass = es_pass_of(hdr);
 
   for (;;) {
     // -- claim a start when idle ------------------------------------------
@@ -117,9 +118,13 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
       if (got >= (unsigned long long)total) break;
       const int ri = request_of(reqs, nreq, (int64_t)got);
       const ReqDev &rq = reqs[ri];
-      idx = (int64_t)got - rq.start_offset;
+      idx = (int64_t)got - rq.start_offset + rq.slice_first;
+      if (es_pass == 2 && !es_rerun(rq, idx)) {  // keeps its first-pass result
+        idx = -1;
+        continue;
+      }
       const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(*sh.q, rq, ri);
+      if (j == 0) load_hot<OBJ>(*sh.q, rq, ri, es_pass);
       own = j < d0;
       fill_step_lengths(sh.al, rq.shrink, j, G);
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
@@ -133,6 +138,9 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
     wave_sync();
     const ReqHot &q = *sh.q;
     const int d = q.d;
+    // the group's stopping bound, read early (its use is at the termination
+    // test) and taken from one lane: the bound falls while the kernel runs
+    const int bound = __shfl(es_bound(q), L.grp * G, 64);
 
     // -- value and gradient at xs (dual numbers, one direction per lane) ----
     double gn, fn;
@@ -174,7 +182,7 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
     // -- termination: non-finite, ||g|| < Theta, budget ---------------------
     const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
     const bool any_bad = L.ballot(bad) != 0ull;
-    if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * q.tol)) {
+    if (kMixed && !hi && (any_bad || norm_below(gg, 10.0 * q.tol))) {
       hi = true;  // escalate: re-evaluate this point in FP64
       fresh = true;
       continue;
@@ -182,13 +190,14 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
     int status = -1;
     if (any_bad)
       status = ZEUS_ST_NONFINITE;
-    else if (sqrt(gg) < q.tol)
+    else if (norm_below(gg, q.tol))
       status = ZEUS_ST_CONVERGED;
-    else if (k == q.iter_bfgs)
-      status = q.stop_status;  // MAXITER, or STOPPED at an early-stop cap
+    else
+      status = budget_status(q, k, bound);
     if (status >= 0) {
       const ReqDev &rq = reqs[q.ri];
       const int tl = q.trace_len;
+      if (status == ZEUS_ST_CONVERGED && q.es && j == 0) es_converged(q.es, k, q.iter_bfgs, q.es_c);
       if (own) rq.out_x[idx * d + j] = xj;
       if (kMixed && !hi) f = group_value<OBJ, G, double>(L, d, sh.xs);  // FP64 value at x
       if (j == 0) {

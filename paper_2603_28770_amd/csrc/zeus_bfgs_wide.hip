@@ -42,6 +42,7 @@ struct WideShm {
   double al[kTabTrials];
   int pass[2][kWaves];       // [phase][wave] line-search outcome
   unsigned long long got;
+  int bound;                 // early-stop bound of this iteration
   ReqHot q;
 };
 
@@ -224,6 +225,7 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
   int64_t idx = -1;
   int k = 0, ls_trials = 0;
   bool have_p = false;  // p = -H g already formed by the update pass
+  const int es_pass = es_pass_of(hdr);
 
   for (;;) {
     if (idx < 0) {
@@ -237,9 +239,13 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
       if (got >= (unsigned long long)total) break;
       const int ri = request_of(reqs, nreq, (int64_t)got);
       const ReqDev &rq = reqs[ri];
-      idx = (int64_t)got - rq.start_offset;
+      idx = (int64_t)got - rq.start_offset + rq.slice_first;
+      if (es_pass == 2 && !es_rerun(rq, idx)) {  // keeps its first-pass result
+        idx = -1;
+        continue;
+      }
       const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(sh.q, rq, ri);
+      if (j == 0) load_hot<OBJ>(sh.q, rq, ri, es_pass);
       fill_step_lengths(sh.al, rq.shrink, j, kWide);
       own = j < d0;
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
@@ -252,9 +258,13 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
       hi = !kMixed;
       have_p = false;
     }
-    __syncthreads();  // xs and the request are visible; earlier reads are done
+    // the stopping bound, read early (its use is at the termination test) by
+    // one thread for the block: the bound falls while the kernel runs
+    if (j == 0) sh.bound = es_bound(sh.q);
+    __syncthreads();  // xs, the request and the bound are visible; earlier reads are done
     const ReqHot &q = sh.q;
     const int d = q.d;
+    const int bound = sh.bound;
 
     // -- value and gradient at xs -------------------------------------------
     double gn, fn;
@@ -320,7 +330,7 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
     const bool bad = (own && !__builtin_isfinite(gj)) || !__builtin_isfinite(f);
     const bool any_bad = __syncthreads_or(bad) != 0;
     const double gg = block_tree_sum(gj * gj, sh, phase);
-    if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * q.tol)) {
+    if (kMixed && !hi && (any_bad || norm_below(gg, 10.0 * q.tol))) {
       hi = true;
       fresh = true;
       continue;
@@ -328,13 +338,14 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
     int status = -1;
     if (any_bad)
       status = ZEUS_ST_NONFINITE;
-    else if (sqrt(gg) < q.tol)
+    else if (norm_below(gg, q.tol))
       status = ZEUS_ST_CONVERGED;
-    else if (k == q.iter_bfgs)
-      status = q.stop_status;  // MAXITER, or STOPPED at an early-stop cap
+    else
+      status = budget_status(q, k, bound);
     if (status >= 0) {
       const ReqDev &rq = reqs[q.ri];
       const int tl = q.trace_len;
+      if (status == ZEUS_ST_CONVERGED && q.es && j == 0) es_converged(q.es, k, q.iter_bfgs, q.es_c);
       if (own) rq.out_x[idx * d + j] = xj;
       if (kMixed && !hi) f = wide_eval<OBJ, double, false>(d, sh.xs, nullptr, sh, phase);
       if (j == 0) {
@@ -399,6 +410,10 @@ hipError_t launch_wide_t(const Group &g, int64_t want, int cus) {
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   int64_t cap = (int64_t)cus * per_cu;
+  if (g.resident) {
+    *g.resident = cap;
+    return hipSuccess;
+  }
   if (cap > g.wide_slots) cap = g.wide_slots;
   const int blocks = (int)(want < cap ? want : cap);
   hipLaunchKernelGGL((bfgs_wide_kernel<OBJ, T>), dim3(blocks), dim3(kWide), 0, g.stream, g.reqs,

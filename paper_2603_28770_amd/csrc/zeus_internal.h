@@ -53,11 +53,31 @@ struct Workspace {
   double *part_x;          // [2][P][dim] its personal-best position
   double *x, *v, *px;      // [n][dim]
   double *pf;              // [n]
+  int32_t *es;             // early-stop state (below), nullptr without early stop
   int pso_blocks;          // P
 };
 
-size_t workspace_bytes(int64_t n, int dim);
-Workspace carve_workspace(void *base, int64_t n, int dim);
+// Early stop (required_converged = c > 0, Alg. 10), read iteration-
+// synchronously: K* is the iteration at which the c-th start converges and
+// every start still running at K* ends there.  The BFGS kernel runs twice.
+// In the first pass a start that converges at iteration k adds itself to a
+// Fenwick tree of convergence counts by iteration, and every start stops at
+// iteration k >= bound, where bound is the c-th smallest convergence
+// iteration among the starts counted so far.  Counts only grow, so bound
+// only falls and never drops below K*.  After the pass the tree is complete
+// up to K*, which gives K* exactly; the second pass reruns from their seeds,
+// capped at K*, the starts that went past it.  The int32 state of a request:
+//   es[kEsBound]          the stopping bound (starts at iter_bfgs)
+//   es[kEsKstar]          K* after the first pass (-1: fewer than c converge)
+//   es[kEsCount]          convergences counted so far
+//   es[kEsTree + i]       Fenwick node i = 1 .. iter_bfgs + 1 (iteration i - 1)
+constexpr int kEsBound = 0, kEsKstar = 1, kEsCount = 2, kEsTree = 3;
+__host__ __device__ constexpr int es_ints(int iter_bfgs) { return kEsTree + iter_bfgs + 2; }
+
+// Device bytes of one request's workspace (swarm state, and es_len ints of
+// early-stop state when es_len > 0), and its pieces at `base`.
+size_t workspace_bytes(int64_t n, int dim, int es_len = 0);
+Workspace carve_workspace(void *base, int64_t n, int dim, int es_len = 0);
 
 // One request of a launch as the kernels see it (a table in device memory).
 // A launch serves requests that share objective, precision and lane counts.
@@ -79,11 +99,16 @@ struct ReqDev {
   int64_t start_offset;      // first start of this request in the BFGS launch
   int block_offset;          // first block of this request in a swarm launch
   int pad1;
+  int64_t required_c;        // early stop at this many converged starts (0: off)
+  int64_t slice_first;       // this entry runs starts slice_first, slice_first + 1, ...
+                             // of its request (a slice of the request's starts)
 };
 
 // Shared counters of one launch group.
 struct BatchDev {
   uint64_t queue;            // next unclaimed BFGS start over all requests
+  uint32_t es_pass;          // 0: no early stop; 1, 2: first, second BFGS pass
+  uint32_t pad;
 };
 
 // Kernels of a user objective, compiled at run time (zeus_user.cpp): the
@@ -117,6 +142,9 @@ struct Group {
   int wide_cs;               // column stride of a slot (max dim rounded up to 64)
   int64_t wide_slot_doubles; // max dim * wide_cs
   const UserKernels *user;   // objective == kUser: its compiled kernels
+  bool early_stop;           // some request has required_converged > 0
+  int64_t *resident;         // non-null: the BFGS launcher only stores here how many
+                             // starts its kernel keeps resident at once (no launch)
 };
 
 // H slots of a wide launch group whose largest dimension is dmax.
@@ -126,6 +154,9 @@ size_t wide_hslot_bytes(int64_t total_starts, int dmax);
 
 // Kernel launchers (return the first HIP error, hipSuccess otherwise).
 hipError_t launch_ws_init(const Group &g);
+// After the first BFGS pass of a group with early stop: K* of every such
+// request, and the work counter reset for the second pass.
+hipError_t launch_es_finish(const Group &g);
 hipError_t launch_pso(const Group &g, int t);
 hipError_t launch_pso_finish(const Group &g);
 hipError_t launch_bfgs(const Group &g);

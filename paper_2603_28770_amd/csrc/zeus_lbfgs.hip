@@ -16,6 +16,10 @@ hipError_t launch_l(const Group &g, int cus) {
   const int64_t per_block = kBfgsBlock / G;
   const int64_t want = (g.total_starts + per_block - 1) / per_block;
   const int64_t cap = (int64_t)cus * per_cu;
+  if (g.resident) {
+    *g.resident = cap * per_block;
+    return hipSuccess;
+  }
   const int blocks = (int)(want < cap ? want : cap);
   hipLaunchKernelGGL((lbfgs_kernel<OBJ, G, CPL, T>), dim3(blocks), dim3(kBfgsBlock), lds, g.stream,
                      g.reqs, g.nreq, g.hdr, g.total_starts);

@@ -181,6 +181,7 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
   bool hi = !kMixed;
 #pragma unroll
   for (int c = 0; c < CPL; ++c) own[c] = false, xj[c] = gj[c] = pj[c] = sj[c] = 0.0;
+  const int es_pass = es_pass_of(hdr);
 
   for (;;) {
     // -- claim a start when idle (as the BFGS kernel) -----------------------
@@ -197,9 +198,13 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
       if (got >= (unsigned long long)total) break;
       const int ri = request_of(reqs, nreq, (int64_t)got);
       const ReqDev &rq = reqs[ri];
-      idx = (int64_t)got - rq.start_offset;
+      idx = (int64_t)got - rq.start_offset + rq.slice_first;
+      if (es_pass == 2 && !es_rerun(rq, idx)) {  // keeps its first-pass result
+        idx = -1;
+        continue;
+      }
       const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(*qh, rq, ri);
+      if (j == 0) load_hot<OBJ>(*qh, rq, ri, es_pass);
       fill_step_lengths(al, rq.shrink, j, G);
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
@@ -217,6 +222,9 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
     wave_sync();
     const ReqHot &q = *qh;
     const int d = q.d;
+    // the group's stopping bound, read early (its use is at the termination
+    // test) and taken from one lane: the bound falls while the kernel runs
+    const int bound = __shfl(es_bound(q), L.grp * G, 64);
 
     // -- value and gradient at xs ---------------------------------------------
     double gn[CPL];
@@ -277,7 +285,7 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
     for (int c = 0; c < CPL; ++c) bad = bad || (own[c] && !__builtin_isfinite(gj[c]));
     const bool any_bad = L.ballot(bad) != 0ull;
     const double gg = slot_dot<G, CPL>(gj, gj);
-    if (kMixed && !hi && (any_bad || sqrt(gg) < 10.0 * q.tol)) {
+    if (kMixed && !hi && (any_bad || norm_below(gg, 10.0 * q.tol))) {
       hi = true;  // escalate: re-evaluate this point in FP64
       fresh = true;
       continue;
@@ -285,13 +293,14 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
     int status = -1;
     if (any_bad)
       status = ZEUS_ST_NONFINITE;
-    else if (sqrt(gg) < q.tol)
+    else if (norm_below(gg, q.tol))
       status = ZEUS_ST_CONVERGED;
-    else if (k == q.iter_bfgs)
-      status = q.stop_status;
+    else
+      status = budget_status(q, k, bound);
     if (status >= 0) {
       const ReqDev &rq = reqs[q.ri];
       const int tl = q.trace_len;
+      if (status == ZEUS_ST_CONVERGED && q.es && j == 0) es_converged(q.es, k, q.iter_bfgs, q.es_c);
 #pragma unroll
       for (int c = 0; c < CPL; ++c)
         if (own[c]) rq.out_x[idx * d + j + G * c] = xj[c];

@@ -16,8 +16,19 @@ __global__ __launch_bounds__(kPsoBlock) void pso_finish_kernel(const ReqDev *req
   global_best_after<kPsoBlock>(a, a.iter_pso, gx_sh, true, a.ws.best, a.ws.gx, s2);
 }
 
-__global__ void ws_init_kernel(BatchDev *hdr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->queue = 0ull;
+// Before a group's launches: the BFGS work counter and the early-stop pass,
+// and (block r) the early-stop state of request r when it stops early.
+__global__ __launch_bounds__(256) void ws_init_kernel(BatchDev *hdr, const ReqDev *reqs,
+                                                      int early_stop) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    hdr->queue = 0ull;
+    hdr->es_pass = early_stop ? 1u : 0u;
+  }
+  const ReqDev &rq = reqs[blockIdx.x];
+  if (!rq.ws.es) return;
+  const int len = es_ints(rq.iter_bfgs);
+  for (int i = threadIdx.x; i < len; i += blockDim.x)
+    rq.ws.es[i] = i == kEsBound ? rq.iter_bfgs : i == kEsKstar ? -1 : 0;
 }
 
 template <int OBJ, int G, int CPL = 1>
@@ -66,7 +77,8 @@ int pso_blocks(int64_t n, int dim) {
 }
 
 hipError_t launch_ws_init(const Group &g) {
-  hipLaunchKernelGGL(ws_init_kernel, dim3(1), dim3(64), 0, g.stream, g.hdr);
+  hipLaunchKernelGGL(ws_init_kernel, dim3(g.nreq), dim3(256), 0, g.stream, g.hdr, g.reqs,
+                     g.early_stop ? 1 : 0);
   return hipGetLastError();
 }
 

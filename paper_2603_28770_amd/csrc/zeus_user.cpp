@@ -183,6 +183,10 @@ hipError_t launch_user_bfgs(const Group &g, int64_t want, int cus) {
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   const int64_t cap = (int64_t)cus * per_cu;
+  if (g.resident) {
+    *g.resident = cap * (kBfgsBlock / g.g_bfgs);
+    return hipSuccess;
+  }
   const unsigned blocks = (unsigned)(want < cap ? want : cap);
   const ReqDev *reqs = g.reqs;
   int nreq = g.nreq;
@@ -208,6 +212,10 @@ hipError_t launch_user_lbfgs(const Group &g, int cus) {
   const int64_t per_block = kBfgsBlock / lanes;
   const int64_t want = (g.total_starts + per_block - 1) / per_block;
   const int64_t cap = (int64_t)cus * per_cu;
+  if (g.resident) {
+    *g.resident = cap * per_block;
+    return hipSuccess;
+  }
   const unsigned blocks = (unsigned)(want < cap ? want : cap);
   const ReqDev *reqs = g.reqs;
   int nreq = g.nreq;

@@ -28,7 +28,7 @@ EXPORTS = ("zeus_abi_version", "zeus_version", "zeus_last_error", "zeus_validate
            "zeus_workspace_bytes", "zeus_context_create", "zeus_context_destroy",
            "zeus_context_set_profiling", "zeus_context_get_profile", "zeus_minimize",
            "zeus_minimize_batch", "zeus_minimize_async", "zeus_minimize_async_static",
-           "zeus_server_create",
+           "zeus_server_create", "zeus_server_create_emulated", "zeus_server_request_bytes",
            "zeus_server_submit", "zeus_server_wait", "zeus_server_cancel", "zeus_server_destroy",
            "zeus_plan_workspace_bytes", "zeus_plan_create", "zeus_plan_launch", "zeus_plan_destroy",
            "zeus_objective_compile", "zeus_objective_check", "zeus_objective_destroy",
@@ -71,6 +71,11 @@ class zeus_request_times(C.Structure):
     _fields_ = [("t_submit_ns", C.c_uint64), ("t_admit_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
 
 
+class zeus_emulation(C.Structure):
+    _fields_ = [("swarm_ns", C.c_uint64), ("step_ns", C.c_uint64), ("start_ns", C.c_uint64),
+                ("finish_ns", C.c_uint64), ("resident_starts", C.c_int64)]
+
+
 class ZeusError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"zeus error {code}: {msg}")
@@ -103,6 +108,8 @@ def _load():
     L.zeus_minimize_async_static.argtypes = [C.c_void_p, P(zeus_problem), P(zeus_result),
                                              C.c_void_p]
     L.zeus_server_create.argtypes = [C.c_void_p, C.c_size_t, P(C.c_void_p)]
+    L.zeus_server_create_emulated.argtypes = [C.c_size_t, P(zeus_emulation), P(C.c_void_p)]
+    L.zeus_server_request_bytes.argtypes = [P(zeus_problem), P(zeus_result), P(C.c_size_t)]
     L.zeus_server_submit.argtypes = [C.c_void_p, P(zeus_problem), P(zeus_result), P(C.c_uint64)]
     L.zeus_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64, P(zeus_request_times)]
     L.zeus_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
@@ -195,7 +202,7 @@ def _np_ptr(a):
 
 def _host_outputs(pb, trace_len, pso_state, ls_trials):
     n, d = pb.n_starts, pb.dim
-    o = {"f": np.empty(n), "x": np.empty((n, d)), "iters": np.empty(n, np.int32),
+    o = {"f": np.full(n, np.nan), "x": np.empty((n, d)), "iters": np.empty(n, np.int32),
          "status": np.empty(n, np.int32)}
     if ls_trials:
         o["ls_trials"] = np.empty(n, np.int32)
@@ -303,10 +310,32 @@ class Server:
     The host arrays of each submitted request are kept here until it is waited
     for."""
 
-    def __init__(self, ctx, budget_bytes: int):
+    def __init__(self, ctx, budget_bytes: int, _emulation=None):
         self.h = C.c_void_p()
-        _check(lib.zeus_server_create(ctx, C.c_size_t(int(budget_bytes)), C.byref(self.h)))
+        if _emulation is None:
+            _check(lib.zeus_server_create(ctx, C.c_size_t(int(budget_bytes)), C.byref(self.h)))
+        else:
+            _check(lib.zeus_server_create_emulated(C.c_size_t(int(budget_bytes)),
+                                                   C.byref(_emulation), C.byref(self.h)))
         self._live = {}
+
+    @classmethod
+    def emulated(cls, budget_bytes: int, *, swarm_ns: int, step_ns: int, start_ns: int,
+                 finish_ns: int, resident_starts: int) -> "Server":
+        """zeus_server_create_emulated: the server's scheduling with no GPU
+        (modelled times, placeholder results)."""
+        emu = zeus_emulation(swarm_ns=swarm_ns, step_ns=step_ns, start_ns=start_ns,
+                             finish_ns=finish_ns, resident_starts=resident_starts)
+        return cls(None, budget_bytes, _emulation=emu)
+
+    @staticmethod
+    def request_bytes(problem, *, trace_len=0, pso_state=False, ls_trials=True) -> int:
+        """zeus_server_request_bytes for a request with these outputs."""
+        pb = problem if isinstance(problem, zeus_problem) else make_problem(problem)
+        _, _, r = _host_outputs(pb, trace_len, pso_state, ls_trials)
+        b = C.c_size_t()
+        _check(lib.zeus_server_request_bytes(C.byref(pb), C.byref(r), C.byref(b)))
+        return b.value
 
     def submit(self, problem, *, trace_len=0, pso_state=False, ls_trials=True) -> int:
         pb = problem if isinstance(problem, zeus_problem) else make_problem(problem)
@@ -324,8 +353,8 @@ class Server:
         code = lib.zeus_server_wait(self.h, C.c_uint64(ticket), C.c_int64(ns), C.byref(tm))
         if code == NOT_READY:
             return None
-        if code != OK:
-            self._live.pop(ticket, None)
+        if code not in (OK, ETIMEOUT):
+            self._live.pop(ticket, None)   # the ticket is released: its arrays are no longer written
         _check(code)
         _, o, s, _ = self._live.pop(ticket)
         o["summary"] = _summary_dict(s)

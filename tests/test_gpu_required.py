@@ -1,7 +1,8 @@
 """Early stop (required_converged = c > 0, Alg. 10) on the GPU against the
 oracle's reading of it (every start still running when the c-th start
-converges stops there), bit for bit; inside a batch and the server; and the
-entry points that cannot run it refuse it."""
+converges stops there), bit for bit: through every entry point (blocking,
+batch, server, asynchronous, allocation-free, graph-captured), with several
+early-stop requests in one launch group, with L-BFGS and at full size."""
 import numpy as np
 import pytest
 
@@ -68,12 +69,61 @@ def test_required_c_in_batch_and_server(Z, ctx):
             assert np.array_equal(a[k], b[k], equal_nan=True) and np.array_equal(a[k], s[k], equal_nan=True)
 
 
-def test_required_c_refused_where_it_cannot_run(Z, ctx):
-    p = dict(CASES[0][0], required_converged=5)
-    ds_ok = Z.DeviceSolve(CASES[0][0])   # buffers sized for the same problem
-    with pytest.raises(Z.ZeusError) as e:
-        Z.zeus_minimize_async(ctx, p, ds_ok.ws_ptr, ds_ok.ws_bytes, ds_ok.result)
-    assert e.value.code == Z.EUNSUPPORTED
-    with pytest.raises(Z.ZeusError) as e:
-        Z.DevicePlan(ctx, [p])
-    assert e.value.code == Z.EUNSUPPORTED
+def test_required_c_on_device_paths(Z, ctx):
+    """The stop is decided on the device, so the asynchronous entry point,
+    its allocation-free form and a graph-captured plan (replayed twice) give
+    the blocking entry point's results bit for bit."""
+    import torch
+    p = dict(CASES[0][0], required_converged=CASES[0][1])
+    print(f"\n[required] async / static / plan paths, {p['name']}", flush=True)
+    ref = Z.zeus_minimize(ctx, p)
+    ds = Z.DeviceSolve(p)
+    ds.enqueue(ctx)
+    torch.cuda.synchronize()
+    a = ds.host()
+    ds2 = Z.DeviceSolve(p)
+    ds2.enqueue_static(ctx)
+    torch.cuda.synchronize()
+    st = ds2.host()
+    plan = Z.DevicePlan(ctx, [p, dict(CASES[1][0], required_converged=CASES[1][1])])
+    reps = []
+    for _ in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        reps.append(plan.host()[0])
+        Z.zeus_minimize(ctx, CASES[2][0])  # other work between the replays
+    plan.close()
+    for out in [a, st] + reps:
+        for k in KEYS:
+            assert np.array_equal(ref[k], out[k], equal_nan=True), k
+        assert out["summary"]["n_converged"] == ref["summary"]["n_converged"]
+
+
+def test_required_c_shared_group_and_lbfgs(Z, ctx, oracle_mod):
+    """Two early-stop requests of one launch group (each with its own K*)
+    beside a request without early stop, and early stop with L-BFGS, against
+    the oracle."""
+    reqs = [dict(CASES[0][0], required_converged=11),
+            dict(CASES[0][0], required_converged=90, request_id=7, seed=9),
+            dict(CASES[0][0], request_id=3),
+            dict(CASES[1][0], lbfgs_m=5, required_converged=30, request_id=2)]
+    print("\n[required] shared group + L-BFGS", flush=True)
+    got = Z.zeus_minimize_batch(ctx, reqs)
+    for p, g in zip(reqs, got):
+        x0 = oracle_mod.pso(p)["x"]
+        c = p.get("required_converged", 0)
+        o = oracle_mod.bfgs_required(p, x0, c)[0] if c else oracle_mod.bfgs(p, x0)
+        for k in KEYS:
+            assert np.array_equal(g[k], o[k], equal_nan=True), (p.get("request_id"), k)
+
+
+def test_required_c_full_size_d10(Z, ctx, oracle_mod):
+    """The d = 10 Rastrigin workload at full size (N = 65,536) with early stop
+    at 100 converged starts, every start against the oracle."""
+    p = dict(W.RASTRIGIN_D10, required_converged=100)
+    print("\n[required] rastrigin d10 full size, c = 100", flush=True)
+    g = Z.zeus_minimize(ctx, p)
+    o, kstar = oracle_mod.bfgs_required(W.RASTRIGIN_D10, oracle_mod.pso(p)["x"], 100)
+    print(f"[required]   K* = {kstar}, stopped {int(np.sum(o['status'] == 2))}", flush=True)
+    for k in KEYS:
+        assert np.array_equal(g[k], o[k], equal_nan=True), k

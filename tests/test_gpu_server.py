@@ -1,6 +1,9 @@
 """The serving path (zeus_server_*) on the GPU: requests submitted from
-several threads while earlier batches run come back bit-identical to solving
-each alone; admission by device-memory footprint; cancel, poll and shutdown."""
+several threads while others run come back bit-identical to solving each
+alone; a short request that arrives during a long one is admitted at once,
+shares the long one's steps on the device and ends first, with the same
+results as alone; admission by device-memory footprint; cancel, poll and
+shutdown."""
 import threading
 import time
 
@@ -84,8 +87,9 @@ def test_served_from_threads_equals_alone(Z, ctx):
 
 def test_tight_budget_queues_and_rejects(Z, ctx):
     reqs = _requests(8, 7, dmax=60, nmin=256, nspan=4.0)
-    need = [Z.zeus_workspace_bytes(Z.make_problem(p)) for p in reqs]
-    budget = max(need) * 2 + (64 << 20)   # room for one or two requests at a time
+    need = [Z.Server.request_bytes(p) for p in reqs]
+    # requests get three quarters of the budget: room for one or two at a time
+    budget = (max(need) * 2 + (1 << 20)) * 4 // 3
     with Z.Server(ctx, budget) as srv:
         tickets = [srv.submit(p) for p in reqs]
         outs = [srv.wait(t, timeout_s=120) for t in tickets]
@@ -125,3 +129,31 @@ def test_cancel_poll_and_shutdown(Z, ctx):
     for k in range(3):
         srv.submit(dict(small, request_id=100 + k))
     srv.close()
+
+
+def test_short_request_during_long(Z, ctx):
+    """Continuous batching at the level of starts: a long request (the d = 50
+    Rosenbrock problem at a quarter of its starts, many steps) is running when
+    a short one of the same kernel class arrives; the short one is admitted
+    at once, takes a share of the next steps beside the long one, ends long
+    before it, and both equal their solves alone bit for bit."""
+    long_ = dict(W.ROSENBROCK_D50, n=32768, request_id=1)
+    short = dict(W.ROSENBROCK_D50, n=512, request_id=2)
+    a_long, a_short = Z.zeus_minimize(ctx, long_), Z.zeus_minimize(ctx, short)
+    with Z.Server(ctx, 8 << 30) as srv:
+        t_long = srv.submit(long_)
+        time.sleep(0.05)
+        t_short = srv.submit(short)
+        o_short = srv.wait(t_short, timeout_s=120)
+        o_long = srv.wait(t_long, timeout_s=120)
+    s, l = o_short["times"], o_long["times"]
+    print(f"\n[server] long admitted..done {(l['t_done_ns'] - l['t_admit_ns']) / 1e6:.1f} ms; "
+          f"short submitted {(s['t_submit_ns'] - l['t_admit_ns']) / 1e6:.1f} ms after it, "
+          f"done after {(s['t_done_ns'] - s['t_submit_ns']) / 1e6:.1f} ms", flush=True)
+    assert l["t_admit_ns"] < s["t_submit_ns"] and s["t_admit_ns"] < l["t_done_ns"]
+    assert s["t_done_ns"] < l["t_done_ns"]
+    _same_keys = ("f", "x", "iters", "status", "ls_trials")
+    for a, o in ((a_long, o_long), (a_short, o_short)):
+        for k in _same_keys:
+            assert np.array_equal(a[k], o[k], equal_nan=True), k
+        assert a["summary"] == o["summary"]
