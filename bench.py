@@ -159,7 +159,10 @@ def main_kernel(p):
     rocprofv3 summary carries under profiles/ (kernel_workload[_mM].md)."""
     if p.get("lbfgs_m", 0):
         return "lbfgs_kernel", f"lbfgs_kernel_{p['name']}_m{p['lbfgs_m']}"
-    kernel = "bfgs_wide_kernel" if p["dim"] > 64 else "bfgs_kernel"
+    if p["dim"] <= 64:
+        kernel = "bfgs_kernel"
+    else:  # one block per start: H in registers up to d = 128, in device memory above
+        kernel = "bfgs_tile_kernel" if p["dim"] <= 128 else "bfgs_wide_kernel"
     return kernel, f"{kernel}_{p['name']}"
 
 

@@ -22,14 +22,13 @@
 //    then an agent-scope work counter.
 // The control flow is uniform across the block (one start per block), so
 // every barrier is reached by all its threads.
-#include "zeus_bfgs_common.h"
+#include "zeus_block.h"
 
 namespace zeus {
 namespace {
 
-constexpr int kWide = kWideLanes;   // lanes (threads) per start
-constexpr int kWaves = kWide / 64;  // wavefronts per start == trials per round
-static_assert(kWaves == 4, "the pairwise combination of wave sums assumes four waves");
+constexpr int kWide = kBlockLanes;   // lanes (threads) per start
+constexpr int kWaves = kBlockWaves;  // wavefronts per start == trials per round
 
 struct WideShm {
   double xs[kWide];  // iterate under evaluation (x, then x_new)
@@ -45,129 +44,6 @@ struct WideShm {
   int bound;                 // early-stop bound of this iteration
   ReqHot q;
 };
-
-// Pairwise sum over the block's 256 lanes of K values per lane.  Alternating
-// phases let one barrier per reduction suffice: a phase's slots are written
-// again only two reductions later, after every thread has passed the barrier
-// of the reduction in between (and so has read them).
-template <int K, class T>
-__device__ __forceinline__ void block_tree_sums(T (&v)[K], WideShm &sh, int &phase) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    v[k] = lane_tree_sum<64, T>(v[k]);
-    if (lane == 0) sh.red[phase][k][w] = (double)v[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double *r = sh.red[phase][k];
-    v[k] = ((T)r[0] + (T)r[1]) + ((T)r[2] + (T)r[3]);
-  }
-  phase ^= 1;
-}
-
-__device__ __forceinline__ double block_tree_sum(double v, WideShm &sh, int &phase) {
-  double a[1] = {v};
-  block_tree_sums<1, double>(a, sh, phase);
-  return a[0];
-}
-
-// Objective value at xs in number type T (every thread returns it); lane j
-// also returns df/dx_j in *gj when `grad` (0 beyond the dimension).
-template <int OBJ, class T, bool kGrad>
-__device__ __forceinline__ double wide_eval(int d, const double *xs, double *gj, WideShm &sh,
-                                            int &phase) {
-  using E = Elem<OBJ>;
-  static_assert(E::W <= 2, "the tangent sum assumes at most two terms per coordinate");
-  const int m = E::terms(d);
-  const int j = threadIdx.x;
-  T tan[E::K], val[E::K];
-#pragma unroll
-  for (int k = 0; k < E::K; ++k) {
-    tan[k] = T(0);
-    val[k] = T(0);
-  }
-  if (kGrad) {
-    if (j < d) {
-#pragma unroll
-      for (int back = E::W - 1; back >= 0; --back) {
-        const int i = j - back;
-        if (i >= 0 && i < m) {
-          dual<T> w[E::W], out[E::K];
-#pragma unroll
-          for (int q = 0; q < E::W; ++q) w[q] = dual<T>{(T)xs[i + q], q == back ? T(1) : T(0)};
-          E::template term<dual<T>>(w, out);
-#pragma unroll
-          for (int k = 0; k < E::K; ++k) tan[k] = tan[k] + out[k].t;
-          if (back == 0)
-#pragma unroll
-            for (int k = 0; k < E::K; ++k) val[k] = out[k].v;
-        }
-      }
-    }
-  } else if (j < m) {
-    T w[E::W];
-#pragma unroll
-    for (int q = 0; q < E::W; ++q) w[q] = (T)xs[j + q];
-    E::template term<T>(w, val);
-  }
-  block_tree_sums<E::K, T>(val, sh, phase);
-  if (!kGrad) return (double)E::template outer<T>(d, val);
-  dual<T> sd[E::K];
-#pragma unroll
-  for (int k = 0; k < E::K; ++k) sd[k] = dual<T>{val[k], tan[k]};
-  const dual<T> r = E::template outer<dual<T>>(d, sd);
-  *gj = (j < d) ? (double)r.t : 0.0;
-  return (double)r.v;
-}
-
-// One Armijo search (Alg. 6) with the objective in number type U: wavefront w
-// evaluates trial base + w of each round; lane c of it takes the term slots
-// 4c .. 4c + 3 and adds them pairwise, the wavefront finishes the pairwise
-// sum.  Returns the index of the first passing trial, or -1.
-template <int OBJ, class U>
-__device__ __forceinline__ int wide_armijo(WideShm &sh, double f, double ddir, int &lsphase) {
-  using E = Elem<OBJ>;
-  constexpr int B = kWide / 64;  // term slots per lane
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const ReqHot &q = sh.q;
-  const int d = q.d, m = q.m;
-  for (int base = 0; base < q.iter_ls; base += kWaves) {
-    const int t = base + w;
-    const double alpha = step_length(sh.al, q.shrink, t);
-    U tv[E::K][B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int i = lane * B + b;
-      U out[E::K];
-#pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) out[kk] = U(0);
-      if (i < m) {
-        U wv[E::W];
-#pragma unroll
-        for (int e = 0; e < E::W; ++e) wv[e] = (U)(sh.xs[i + e] + alpha * sh.ps[i + e]);
-        E::template term<U>(wv, out);
-      }
-#pragma unroll
-      for (int kk = 0; kk < E::K; ++kk) tv[kk][b] = out[kk];
-    }
-    U sums[E::K];
-#pragma unroll
-    for (int kk = 0; kk < E::K; ++kk) sums[kk] = lane_tree_sum<64, U>(reg_tree_sum<B, U>(tv[kk]));
-    const double ft = (double)E::template outer<U>(d, sums);
-    const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
-    if (lane == 0) sh.pass[lsphase][w] = ok ? 1 : 0;
-    __syncthreads();
-    int first = -1;
-#pragma unroll
-    for (int v = kWaves - 1; v >= 0; --v)
-      if (sh.pass[lsphase][v]) first = v;
-    lsphase ^= 1;
-    if (first >= 0) return base + first;
-  }
-  return -1;
-}
 
 // See the narrow kernel for the mixed-precision rules (T = float): FP32
 // evaluation with escalation to FP64 near the minimum, on a non-finite value
@@ -242,6 +118,7 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
       idx = (int64_t)got - rq.start_offset + rq.slice_first;
       if (es_pass == 2 && !es_rerun(rq, idx)) {  // keeps its first-pass result
         idx = -1;
+        __syncthreads();  // every thread has read sh.got before the next claim writes it
         continue;
       }
       const int d0 = rq.d;
@@ -269,9 +146,9 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
     // -- value and gradient at xs -------------------------------------------
     double gn, fn;
     if (hi)
-      fn = wide_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase);
+      fn = block_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase);
     else
-      fn = wide_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase);
+      fn = block_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase);
 
     // -- after a step: y, u = H y, the rank-2 update and p = -H_new g_new ----
     have_p = false;
@@ -347,7 +224,7 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
       const int tl = q.trace_len;
       if (status == ZEUS_ST_CONVERGED && q.es && j == 0) es_converged(q.es, k, q.iter_bfgs, q.es_c);
       if (own) rq.out_x[idx * d + j] = xj;
-      if (kMixed && !hi) f = wide_eval<OBJ, double, false>(d, sh.xs, nullptr, sh, phase);
+      if (kMixed && !hi) f = block_eval<OBJ, double, false>(d, sh.xs, nullptr, sh, phase);
       if (j == 0) {
         rq.out_f[idx] = f;
         rq.out_iters[idx] = k;
@@ -379,9 +256,9 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
     // -- Armijo backtracking -----------------------------------------------------
     int taken;
     if (hi) {
-      taken = wide_armijo<OBJ, double>(sh, f, ddir, lsphase);
+      taken = block_armijo<OBJ, double, kWide>(sh, f, ddir, lsphase);
     } else {
-      taken = wide_armijo<OBJ, T>(sh, f, ddir, lsphase);
+      taken = block_armijo<OBJ, T, kWide>(sh, f, ddir, lsphase);
       if (taken < 0) {
         ls_trials += q.iter_ls;
         hi = true;

@@ -193,6 +193,17 @@ struct Tile {
       for (int k = 0; k < C; ++k) h[t * C + k] = row(j, t) == col(j, k) ? 1.0 : 0.0;
   }
 
+  // The same for a tile that holds the block of a larger matrix whose first
+  // row is r0 and first column c0 (the identity's block there: its ones lie
+  // on the diagonal of the larger matrix).
+  __device__ __forceinline__ void identity_at(int j, int r0, int c0) {
+    j = opaque(j);
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+#pragma unroll
+      for (int k = 0; k < C; ++k) h[t * C + k] = r0 + row(j, t) == c0 + col(j, k) ? 1.0 : 0.0;
+  }
+
   // Puts the padding (row or column >= d) back to the identity's.
   __device__ __forceinline__ void restore_padding(int j, int d) {
     j = opaque(j);
@@ -201,6 +212,17 @@ struct Tile {
 #pragma unroll
       for (int k = 0; k < C; ++k)
         if (row(j, t) >= d || col(j, k) >= d) h[t * C + k] = row(j, t) == col(j, k) ? 1.0 : 0.0;
+  }
+
+  __device__ __forceinline__ void restore_padding_at(int j, int d, int r0, int c0) {
+    j = opaque(j);
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        const int r = r0 + row(j, t), c = c0 + col(j, k);
+        if (r >= d || c >= d) h[t * C + k] = r == c ? 1.0 : 0.0;
+      }
   }
 
   // (H v)_j for lane j; v in the padded layout (vpos).  For G > 16 the rows
@@ -242,12 +264,21 @@ struct Tile {
   // (then the padding must be restored).
   __device__ __forceinline__ bool rank2(double rho, double beta, const double *us, const double *ss,
                                         int j, double sj, double uj) {
+    return rank2_rc(rho, beta, us, ss, us, ss, j, sj, uj);
+  }
+
+  // The update of a tile that holds a block of a larger matrix: the rows'
+  // entries of u and s are read from ur_v and sr_v, the columns' from us and
+  // ss (each in the padded layout, from the block's first row or column).
+  __device__ __forceinline__ bool rank2_rc(double rho, double beta, const double *ur_v,
+                                           const double *sr_v, const double *us,
+                                           const double *ss, int j, double sj, double uj) {
     double a[R], e[R];
     bool fin = true;
 #pragma unroll
     for (int t = 0; t < R; ++t) {
-      const double sr = R == 1 ? sj : ss[vpos<G>(row(j, t))];
-      const double ur = R == 1 ? uj : us[vpos<G>(row(j, t))];
+      const double sr = R == 1 ? sj : sr_v[vpos<G>(row(j, t))];
+      const double ur = R == 1 ? uj : ur_v[vpos<G>(row(j, t))];
       a[t] = -rho * sr;
       e[t] = beta * sr - rho * ur;
       fin = fin && __builtin_isfinite(a[t]) && __builtin_isfinite(e[t]);

@@ -17,6 +17,8 @@ and are still checked so that a loss of exactness reports how far off it is:
     for starts without a near-tie; success rates (f - f* < 1e-4) within 0.01
     over all starts.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -167,9 +169,10 @@ def test_rosenbrock_d64_max_dim(Z, ctx, oracle_mod):
     _check_bfgs(g, o, p)
 
 
-# Above 64 dimensions a start runs on a block of 256 lanes with its inverse
-# Hessian in device memory: just over the narrow limit, unaligned and aligned
-# sizes, and the largest dimension of the build.
+# Above 64 dimensions a start runs on a block of 256 lanes: up to 128 with its
+# inverse Hessian in the registers of its four wavefronts, above that in
+# device memory.  Just over the narrow limit, unaligned and aligned sizes,
+# both sides of 128, and the largest dimension of the build.
 WIDE_CASES = [
     W.problem(name="rosenbrock_d65", objective="rosenbrock", dim=65, n=70, lower=-2.0, upper=2.0,
               iter_pso=2, iter_bfgs=300, seed=12),
@@ -192,15 +195,36 @@ def test_parity_wide(Z, ctx, oracle_mod, p):
     _check_summary(g)
 
 
-def test_wide_more_starts_than_slots(Z, ctx, oracle_mod):
-    """2300 starts on at most 2048 resident blocks: the later starts come from
-    the work counter and reuse H slots of finished starts (sampled)."""
+@pytest.mark.parametrize("lanes", [None, 256], ids=["on_chip", "device_memory"])
+def test_wide_more_starts_than_slots(Z, ctx, oracle_mod, lanes):
+    """2300 starts on at most 2048 resident blocks (device memory: H slots) or
+    the resident blocks of the on-chip kernel: the later starts come from the
+    work counter and reuse the blocks (and H slots) of finished starts
+    (sampled)."""
     p = W.problem(name="rosenbrock_d70_n2300", objective="rosenbrock", dim=70, n=2300, lower=-2.0,
                   upper=2.0, iter_pso=1, iter_bfgs=60, seed=21)
     idx = np.concatenate([np.arange(0, 40), np.arange(2048, 2300, 7)])
-    g, sw, o = _run_both(Z, ctx, oracle_mod, p, idx=idx)
+    if lanes:
+        os.environ["ZEUS_TILE_LANES"] = str(lanes)
+    try:
+        g, sw, o = _run_both(Z, ctx, oracle_mod, p, idx=idx)
+    finally:
+        os.environ.pop("ZEUS_TILE_LANES", None)
     _check_pso(g, sw)
     _check_bfgs(g, o, p, idx=idx)
+    _check_summary(g)
+
+
+# The device-memory block at dimensions the on-chip block also covers.
+@pytest.mark.parametrize("p", WIDE_CASES[:3], ids=[c["name"] for c in WIDE_CASES[:3]])
+def test_parity_device_memory_block(Z, ctx, oracle_mod, p):
+    os.environ["ZEUS_TILE_LANES"] = "256"
+    try:
+        g, sw, o = _run_both(Z, ctx, oracle_mod, p)
+    finally:
+        del os.environ["ZEUS_TILE_LANES"]
+    _check_pso(g, sw)
+    _check_bfgs(g, o, p)
     _check_summary(g)
 
 

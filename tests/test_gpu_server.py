@@ -133,16 +133,17 @@ def test_cancel_poll_and_shutdown(Z, ctx):
 
 def test_short_request_during_long(Z, ctx):
     """Continuous batching at the level of starts: a long request (the d = 50
-    Rosenbrock problem at a quarter of its starts, many steps) is running when
-    a short one of the same kernel class arrives; the short one is admitted
-    at once, takes a share of the next steps beside the long one, ends long
-    before it, and both equal their solves alone bit for bit."""
-    long_ = dict(W.ROSENBROCK_D50, n=32768, request_id=1)
+    Rosenbrock problem with all its 131,072 starts, many steps, about 60 ms of
+    BFGS) is running when a short one of the same kernel class arrives 5 ms
+    later; the short one is admitted at once, takes a share of the next steps
+    beside the long one, ends long before it, and both equal their solves
+    alone bit for bit."""
+    long_ = dict(W.ROSENBROCK_D50, request_id=1)
     short = dict(W.ROSENBROCK_D50, n=512, request_id=2)
     a_long, a_short = Z.zeus_minimize(ctx, long_), Z.zeus_minimize(ctx, short)
     with Z.Server(ctx, 8 << 30) as srv:
         t_long = srv.submit(long_)
-        time.sleep(0.05)
+        time.sleep(0.005)
         t_short = srv.submit(short)
         o_short = srv.wait(t_short, timeout_s=120)
         o_long = srv.wait(t_long, timeout_s=120)

@@ -1,6 +1,7 @@
 """Every tiling of the BFGS phase (2..64 lanes per start, or one 256-lane
-block per start) returns bit-identical results: they evaluate the same
-pairwise sums.  Forced through ZEUS_TILE_LANES."""
+block per start with H in its registers up to d = 128 or in device memory)
+returns bit-identical results: they evaluate the same pairwise sums.  Forced
+through ZEUS_TILE_LANES."""
 import os
 
 import numpy as np
@@ -34,6 +35,10 @@ CASES = [
               iter_pso=2, iter_bfgs=400, seed=4),
     W.problem(name="ack40_mixed", objective="ackley", dim=40, n=200, lower=-5.0, upper=5.0,
               iter_pso=2, iter_bfgs=300, seed=5, precision="mixed", grad_tol=1e-4),
+    W.problem(name="ros90", objective="rosenbrock", dim=90, n=60, lower=-2.0, upper=2.0,
+              iter_pso=2, iter_bfgs=250, seed=6),
+    W.problem(name="rast120_mixed", objective="rastrigin", dim=120, n=40, lower=-5.12, upper=5.12,
+              iter_pso=2, iter_bfgs=200, seed=7, precision="mixed", grad_tol=1e-4),
 ]
 
 
@@ -46,7 +51,9 @@ def test_all_tilings_agree(Z, ctx, p):
     while g <= 64:
         tilings.append(g)
         g *= 2
-    tilings.append(256)
+    if p["dim"] <= 128:
+        tilings.append(128)  # one block per start, H in its wavefronts' registers
+    tilings.append(256)      # one block per start, H in device memory
     ref = None
     for lanes in tilings:
         print(f"\n[tiling] {p['name']} lanes={lanes}", flush=True)
