@@ -161,8 +161,10 @@ def main_kernel(p):
         return "lbfgs_kernel", f"lbfgs_kernel_{p['name']}_m{p['lbfgs_m']}"
     if p["dim"] <= 64:
         kernel = "bfgs_kernel"
-    else:  # one block per start: H in registers up to d = 128, in device memory above
-        kernel = "bfgs_tile_kernel" if p["dim"] <= 128 else "bfgs_wide_kernel"
+    else:  # one block per start: H in registers up to d = 128, in registers and LDS
+        # up to 208, in device memory above
+        kernel = ("bfgs_tile_kernel" if p["dim"] <= 128 else
+                  "bfgs_hybrid_kernel" if p["dim"] <= 208 else "bfgs_wide_kernel")
     return kernel, f"{kernel}_{p['name']}"
 
 

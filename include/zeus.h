@@ -175,9 +175,10 @@ zeus_err zeus_validate(const zeus_problem *problem);
 
 /* Device workspace that zeus_minimize_async needs for this problem, in bytes.
  * Swarm state x, v, px ([N][dim] doubles each) and pf [N], plus reduction
- * scratch.  Up to 128 dimensions the inverse Hessians never leave the chip;
- * BFGS above 128 dimensions adds one inverse-Hessian slot per resident block
- * (at most 2048 slots) of dim x (dim rounded up to 64) doubles. */
+ * scratch.  Up to 208 dimensions the inverse Hessians never leave the chip
+ * (registers, and above 128 dimensions registers and LDS); BFGS above 208
+ * dimensions adds one inverse-Hessian slot per resident block (at most 2048
+ * slots) of dim x (dim rounded up to 64) doubles. */
 zeus_err zeus_workspace_bytes(const zeus_problem *problem, size_t *bytes);
 
 /* Creates a context on HIP device `device` with its own stream (default
@@ -292,7 +293,7 @@ zeus_err zeus_plan_destroy(zeus_plan *plan);
 /* (its stop depends on all its starts).  A request's results are bit-      */
 /* identical to solving it alone with zeus_minimize.  A quarter of the      */
 /* budget (at most 2 GiB) is kept for the two steps' request tables and the */
-/* H slots of problems above 128 dimensions.                                */
+/* H slots of problems above 208 dimensions.                                */
 /* All server calls are thread-safe.                                        */
 /* ------------------------------------------------------------------------ */
 typedef struct zeus_server zeus_server;

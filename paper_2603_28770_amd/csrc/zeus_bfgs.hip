@@ -162,13 +162,14 @@ hipError_t launch_prec(const Group &g, int64_t want, int cus) {
 
 // Tiling: lanes per start (2..64, a power of two >= dim: one group per start,
 // H in registers), kTileBlockDim (one block of four wavefronts per start, H in
-// their registers, dim <= 128) or kWideLanes (one block per start, H in
-// device memory).
+// their registers, dim <= 128), kHybridDim (one block of eight wavefronts per
+// start, H in their registers and LDS, dim <= 208) or kWideLanes (one block
+// per start, H in device memory).
 // Every tiling computes the same pairwise trees, so results do not depend on
 // it; only speed does.  The rules come from the autotuner's table; a start
 // no rule covers gets the smallest power of two >= max(dim, 4), or above 64
-// dimensions the block with H on chip (up to 128; the device-memory block
-// above).  A user objective up to 8 dimensions gets 32 lanes:
+// dimensions the block with H on chip (in registers up to 128, in registers
+// and LDS up to 208; the device-memory block above).  A user objective up to 8 dimensions gets 32 lanes:
 // evaluated as a whole it tries one step length per lane in a line-search
 // round, and on four user sources (d = 2..5, 1.9 to 12 trials per iteration)
 // 32 lanes took 0.71 of the time of the smallest group in geometric mean.
@@ -180,6 +181,7 @@ namespace {
 bool tiling_valid(int lanes, int dim) {
   if (lanes == kWideLanes) return dim <= kMaxDim;
   if (lanes == kTileBlockDim) return dim <= kTileBlockDim;
+  if (lanes == kHybridDim) return dim <= kHybridDim;
   return lanes >= 2 && lanes <= kMaxNarrowDim && (lanes & (lanes - 1)) == 0 && lanes >= dim;
 }
 }  // namespace
@@ -189,7 +191,8 @@ int group_lanes(int objective, int precision, int dim) {
     const int v = atoi(e);
     if (v > 0 && tiling_valid(v, dim)) return v;
   }
-  if (dim > kMaxNarrowDim) return dim <= kTileBlockDim ? kTileBlockDim : kWideLanes;
+  if (dim > kMaxNarrowDim)
+    return dim <= kTileBlockDim ? kTileBlockDim : dim <= kHybridDim ? kHybridDim : kWideLanes;
   for (const TileRule &r : kTileRules)
     if (r.objective == objective && r.precision == precision && dim >= r.dmin && dim <= r.dmax &&
         tiling_valid(r.lanes, dim))
@@ -212,9 +215,9 @@ hipError_t launch_bfgs(const Group &g) {
   if (cus <= 0) cus = 256;
   if (g.method == 1) return launch_lbfgs(g, cus);
   if (g.g_bfgs == kWideLanes) return launch_bfgs_wide(g, cus);
-  if (g.g_bfgs == kTileBlockDim) {
+  if (g.g_bfgs == kTileBlockDim || g.g_bfgs == kHybridDim) {
     if (g.objective == kUser) return hipErrorInvalidValue;
-    return launch_bfgs_tile(g, cus);
+    return g.g_bfgs == kTileBlockDim ? launch_bfgs_tile(g, cus) : launch_bfgs_hybrid(g, cus);
   }
   if (g.g_bfgs > kMaxNarrowDim) return hipErrorInvalidValue;
   const int64_t starts_per_block = (int64_t)(kBfgsBlock / g.g_bfgs);

@@ -1,25 +1,34 @@
-// zeus_block.h -- pieces shared by the two block-per-start BFGS kernels
-// (64 < d): one block of kBlockLanes lanes (four wavefronts) runs a start.
+// zeus_block.h -- pieces shared by the block-per-start BFGS kernels (64 < d):
+// one block of four or eight wavefronts runs a start.
 // Lane j owns coordinate j; the block exchanges vectors through its LDS
 // struct (a type with the members these helpers name: xs, ps, red, pass, al
-// and q) and finishes every sum across its four wavefronts there.
+// and q) and finishes every sum across its wavefronts there.
 #pragma once
 
 #include "zeus_bfgs_common.h"
 
 namespace zeus {
 
-constexpr int kBlockLanes = kWideLanes;     // lanes (threads) per start
+constexpr int kBlockLanes = kWideLanes;     // lanes (threads) per start (four wavefronts)
 constexpr int kBlockWaves = kBlockLanes / 64;  // wavefronts per start == trials per round
-static_assert(kBlockWaves == 4, "the pairwise combination of wave sums assumes four waves");
+static_assert(kBlockWaves == 4, "the device-memory and on-chip blocks have four wavefronts");
 
-// Pairwise sum over the block's 256 lanes of K values per lane: a butterfly
-// inside each wavefront, then the four wavefront sums added pairwise through
-// LDS.  Alternating phases let one barrier per reduction suffice: a phase's
-// slots are written again only two reductions later, after every thread has
-// passed the barrier of the reduction in between (and so has read them).
+// The wavefronts of the block (4 or 8), from the LDS struct's sum slots.
+template <class Shm>
+constexpr int shm_waves() {
+  return (int)(sizeof(Shm::red[0][0]) / sizeof(double));
+}
+
+// Pairwise sum over the block's lanes (NW wavefronts of 64) of K values per
+// lane: a butterfly inside each wavefront, then the NW wavefront sums added
+// pairwise through LDS.  Alternating phases let one barrier per reduction
+// suffice: a phase's slots are written again only two reductions later, after
+// every thread has passed the barrier of the reduction in between (and so has
+// read them).
 template <int K, class T, class Shm>
 __device__ __forceinline__ void block_tree_sums(T (&v)[K], Shm &sh, int &phase) {
+  constexpr int NW = shm_waves<Shm>();
+  static_assert(NW == 4 || NW == 8, "blocks of four or eight wavefronts");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -30,7 +39,12 @@ __device__ __forceinline__ void block_tree_sums(T (&v)[K], Shm &sh, int &phase) 
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double *r = sh.red[phase][k];
-    v[k] = ((T)r[0] + (T)r[1]) + ((T)r[2] + (T)r[3]);
+    const T lo = ((T)r[0] + (T)r[1]) + ((T)r[2] + (T)r[3]);
+    if constexpr (NW == 4) {
+      v[k] = lo;
+    } else {
+      v[k] = lo + (((T)r[4] + (T)r[5]) + ((T)r[6] + (T)r[7]));
+    }
   }
   phase ^= 1;
 }
@@ -95,19 +109,20 @@ __device__ __forceinline__ double block_eval(int d, const double *xs, double *gj
 
 // One Armijo search (Alg. 6) with the objective in number type U over SLOTS
 // term slots (SLOTS a multiple of 64, at least the number of terms):
-// wavefront w evaluates trial base + w of each round; lane c of it takes the
-// term slots B c .. B c + B - 1 (B = SLOTS / 64) and adds them pairwise, the
-// wavefront finishes the pairwise sum.  Returns the index of the first
-// passing trial, or -1.
+// wavefront w of the NW evaluates trial base + w of each round; lane c of it
+// takes the term slots B c .. B c + B - 1 (B = SLOTS / 64) and adds them
+// pairwise, the wavefront finishes the pairwise sum.  Returns the index of the
+// first passing trial, or -1.
 template <int OBJ, class U, int SLOTS, class Shm>
 __device__ __forceinline__ int block_armijo(Shm &sh, double f, double ddir, int &lsphase) {
   using E = Elem<OBJ>;
   static_assert(SLOTS % 64 == 0, "term slots come in whole wavefronts");
   constexpr int B = SLOTS / 64;  // term slots per lane
+  constexpr int NW = shm_waves<Shm>();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const ReqHot &q = sh.q;
   const int d = q.d, m = q.m;
-  for (int base = 0; base < q.iter_ls; base += kBlockWaves) {
+  for (int base = 0; base < q.iter_ls; base += NW) {
     const int t = base + w;
     const double alpha = step_length(sh.al, q.shrink, t);
     U tv[E::K][B];
@@ -135,7 +150,7 @@ __device__ __forceinline__ int block_armijo(Shm &sh, double f, double ddir, int 
     __syncthreads();
     int first = -1;
 #pragma unroll
-    for (int v = kBlockWaves - 1; v >= 0; --v)
+    for (int v = NW - 1; v >= 0; --v)
       if (sh.pass[lsphase][v]) first = v;
     lsphase ^= 1;
     if (first >= 0) return base + first;

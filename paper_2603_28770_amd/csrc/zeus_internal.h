@@ -14,12 +14,16 @@ namespace zeus {
 // 64-lane wavefront runs a start with the inverse Hessian in its registers;
 // up to kTileBlockDim a block of kWideLanes lanes (four wavefronts) runs a
 // start with H in the registers of its wavefronts, a 64 x 64 quarter each;
-// above that a block of kWideLanes lanes runs a start with the rows in a
-// device-memory slot of the block.  As a tiling (lanes per start, below),
-// kTileBlockDim names the on-chip block and kWideLanes the device-memory one.
+// up to kHybridDim a block of eight wavefronts runs a start with eight 64 x 64
+// tiles of H in its registers and the rest in LDS; above that a block of
+// kWideLanes lanes runs a start with the rows in a device-memory slot of the
+// block.  As a tiling (lanes per start, below), kTileBlockDim names the
+// on-chip four-wavefront block, kHybridDim the register-and-LDS block and
+// kWideLanes the device-memory one.
 constexpr int kMaxDim = 256;
 constexpr int kMaxNarrowDim = 64;
 constexpr int kTileBlockDim = 128;
+constexpr int kHybridDim = 208;
 constexpr int kWideLanes = 256;
 // Most H slots (resident wide blocks) a launch group uses.
 constexpr int kWideMaxSlots = 2048;
@@ -166,6 +170,7 @@ hipError_t launch_pso_finish(const Group &g);
 hipError_t launch_bfgs(const Group &g);
 hipError_t launch_bfgs_wide(const Group &g, int cus);
 hipError_t launch_bfgs_tile(const Group &g, int cus);
+hipError_t launch_bfgs_hybrid(const Group &g, int cus);
 hipError_t launch_lbfgs(const Group &g, int cus);
 // Coordinate slots per L-BFGS start (power of two >= max(dim, 4); one
 // wavefront covers up to 256).
@@ -181,9 +186,10 @@ size_t bfgs_lds_bytes(int lanes);
 size_t lbfgs_lds_bytes(int slots);
 
 // Lanes per start of the BFGS kernels for a problem (power of two >= dim, at
-// most 64; kTileBlockDim for one block per start with H on chip, d <= 128;
-// kWideLanes for one block per start with H in device memory), from the
-// tiling table.
+// most 64; kTileBlockDim for one block per start with H in registers,
+// d <= 128; kHybridDim for one block per start with H in registers and LDS,
+// d <= 208; kWideLanes for one block per start with H in device memory), from
+// the tiling table.
 int group_lanes(int objective, int precision, int dim);
 
 // One rule of the tiling table: problems of this objective and precision

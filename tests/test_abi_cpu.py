@@ -109,13 +109,15 @@ def test_workspace_bytes(Z):
         Z.zeus_workspace_bytes(Z.make_problem(_p(dim=0)))
 
 
-@pytest.mark.parametrize("n,d", [(100, 65), (700, 128), (5000, 200), (3000, 256)])
+@pytest.mark.parametrize("n,d", [(100, 65), (700, 128), (5000, 200), (900, 208), (3000, 209),
+                                 (3000, 256)])
 def test_workspace_bytes_wide(Z, n, d):
-    """Above 128 dimensions the workspace also holds one inverse-Hessian slot
+    """Above 208 dimensions the workspace also holds one inverse-Hessian slot
     per resident block (at most 2048), d columns of the dimension rounded up to
-    64; up to 128 the inverse Hessians stay in registers."""
+    64; up to 208 the inverse Hessians stay on chip (registers, then registers
+    and LDS)."""
     b = Z.zeus_workspace_bytes(Z.make_problem(_p(n=n, dim=d)))
-    slots = min(n, 2048) if d > 128 else 0
+    slots = min(n, 2048) if d > 208 else 0
     hs = 8 * slots * d * ((d + 63) // 64 * 64)
     swarm = 3 * 8 * n * d + 8 * n
     assert swarm + hs <= b <= swarm + hs + 2 * 1024 * (d + 3) * 8 + 64 * 1024

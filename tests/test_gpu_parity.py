@@ -169,10 +169,11 @@ def test_rosenbrock_d64_max_dim(Z, ctx, oracle_mod):
     _check_bfgs(g, o, p)
 
 
-# Above 64 dimensions a start runs on a block of 256 lanes: up to 128 with its
-# inverse Hessian in the registers of its four wavefronts, above that in
-# device memory.  Just over the narrow limit, unaligned and aligned sizes,
-# both sides of 128, and the largest dimension of the build.
+# Above 64 dimensions a start runs on a block: up to 128 with its inverse
+# Hessian in the registers of four wavefronts, up to 208 in the registers of
+# eight wavefronts and LDS, above that in device memory.  Just over the
+# narrow limit, unaligned and aligned sizes, both sides of 128 and 208, and
+# the largest dimension of the build.
 WIDE_CASES = [
     W.problem(name="rosenbrock_d65", objective="rosenbrock", dim=65, n=70, lower=-2.0, upper=2.0,
               iter_pso=2, iter_bfgs=300, seed=12),
@@ -180,8 +181,14 @@ WIDE_CASES = [
               upper=5.12, iter_pso=3, iter_bfgs=300, seed=1, request_id=3),
     W.problem(name="styblinski_d128", objective="styblinski_tang", dim=128, n=33, lower=-5.0,
               upper=5.0, iter_pso=2, iter_bfgs=200, seed=3),
+    W.problem(name="rosenbrock_d129", objective="rosenbrock", dim=129, n=24, lower=-2.0, upper=2.0,
+              iter_pso=2, iter_bfgs=300, seed=13),
     W.problem(name="ackley_d200", objective="ackley", dim=200, n=20, lower=-5.0, upper=5.0,
               iter_pso=2, iter_bfgs=200, seed=2),
+    W.problem(name="styblinski_d208", objective="styblinski_tang", dim=208, n=16, lower=-5.0,
+              upper=5.0, iter_pso=2, iter_bfgs=150, seed=5),
+    W.problem(name="rosenbrock_d209", objective="rosenbrock", dim=209, n=12, lower=-2.0, upper=2.0,
+              iter_pso=1, iter_bfgs=120, seed=6),
     W.problem(name="sphere_d256", objective="sphere", dim=256, n=9, lower=-3.0, upper=3.0,
               iter_pso=1, iter_bfgs=30, seed=4),
 ]
@@ -215,8 +222,11 @@ def test_wide_more_starts_than_slots(Z, ctx, oracle_mod, lanes):
     _check_summary(g)
 
 
-# The device-memory block at dimensions the on-chip block also covers.
-@pytest.mark.parametrize("p", WIDE_CASES[:3], ids=[c["name"] for c in WIDE_CASES[:3]])
+# The device-memory block at dimensions the on-chip blocks also cover.
+_DM = [c for c in WIDE_CASES if c["dim"] in (65, 100, 128, 200)]
+
+
+@pytest.mark.parametrize("p", _DM, ids=[c["name"] for c in _DM])
 def test_parity_device_memory_block(Z, ctx, oracle_mod, p):
     os.environ["ZEUS_TILE_LANES"] = "256"
     try:

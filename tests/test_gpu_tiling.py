@@ -1,7 +1,7 @@
-"""Every tiling of the BFGS phase (2..64 lanes per start, or one 256-lane
-block per start with H in its registers up to d = 128 or in device memory)
-returns bit-identical results: they evaluate the same pairwise sums.  Forced
-through ZEUS_TILE_LANES."""
+"""Every tiling of the BFGS phase (2..64 lanes per start, or one block per
+start with H in its registers up to d = 128, in its registers and LDS up to
+d = 208, or in device memory) returns bit-identical results: they evaluate the
+same pairwise sums.  Forced through ZEUS_TILE_LANES."""
 import os
 
 import numpy as np
@@ -39,6 +39,10 @@ CASES = [
               iter_pso=2, iter_bfgs=250, seed=6),
     W.problem(name="rast120_mixed", objective="rastrigin", dim=120, n=40, lower=-5.12, upper=5.12,
               iter_pso=2, iter_bfgs=200, seed=7, precision="mixed", grad_tol=1e-4),
+    W.problem(name="ros150", objective="rosenbrock", dim=150, n=24, lower=-2.0, upper=2.0,
+              iter_pso=2, iter_bfgs=200, seed=8),
+    W.problem(name="ack170_mixed", objective="ackley", dim=170, n=16, lower=-5.0, upper=5.0,
+              iter_pso=2, iter_bfgs=150, seed=9, precision="mixed", grad_tol=1e-4),
 ]
 
 
@@ -53,6 +57,8 @@ def test_all_tilings_agree(Z, ctx, p):
         g *= 2
     if p["dim"] <= 128:
         tilings.append(128)  # one block per start, H in its wavefronts' registers
+    if p["dim"] <= 208:
+        tilings.append(208)  # one block per start, H in its registers and LDS
     tilings.append(256)      # one block per start, H in device memory
     ref = None
     for lanes in tilings:
