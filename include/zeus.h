@@ -378,8 +378,10 @@ zeus_err zeus_server_create_emulated(size_t hbm_budget_bytes, const zeus_emulati
 /* structure the kernels evaluate the whole function: a value is one call,  */
 /* lane j of a start computes df/dx_j by one call on dual numbers seeded    */
 /* with e_j (Alg. 5 as written), and a line-search round tries one step     */
-/* length per lane.  Built for FP64: BFGS up to dim 64, L-BFGS (lbfgs_m > 0, */
-/* a lane then owns up to four coordinates) up to dim 256.                  */
+/* length per lane (one block per start above dim 64: a trial per lane).   */
+/* Built for FP64: BFGS up to dim 208 (H in registers, and above dim 128   */
+/* in registers and LDS), L-BFGS (lbfgs_m > 0, a lane then owns up to four */
+/* coordinates) up to dim 256.                                              */
 /* ------------------------------------------------------------------------ */
 typedef struct zeus_user_objective zeus_user_objective;
 
@@ -398,7 +400,7 @@ zeus_err zeus_objective_destroy(zeus_user_objective *obj);
 
 /* Blocking solve of n >= 1 problems of the user objective `obj`, as
  * zeus_minimize_batch: every problem has objective ZEUS_USER (else
- * ZEUS_EINVAL), precision ZEUS_FP64, and dim <= 64 with lbfgs_m 0 or
+ * ZEUS_EINVAL), precision ZEUS_FP64, and dim <= 208 with lbfgs_m 0 or
  * dim <= 256 with lbfgs_m 1..8 (else ZEUS_EUNSUPPORTED); required_converged
  * works as for zeus_minimize.  The other entry points refuse ZEUS_USER. */
 zeus_err zeus_minimize_user(zeus_context *ctx, const zeus_user_objective *obj,

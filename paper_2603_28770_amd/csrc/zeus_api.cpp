@@ -47,8 +47,8 @@ zeus_err check_problem(const zeus_problem *p, bool user) {
   if (user) {
     if (p->objective != ZEUS_USER) return fail(ZEUS_EINVAL, "objective must be ZEUS_USER");
     if (p->precision != ZEUS_FP64) return fail(ZEUS_EUNSUPPORTED, "user objectives run in FP64");
-    if (p->lbfgs_m == 0 && p->dim > zeus::kMaxNarrowDim)
-      return fail(ZEUS_EUNSUPPORTED, "user objectives need dim <= 64 with BFGS (L-BFGS: <= 256)");
+    if (p->lbfgs_m == 0 && p->dim > zeus::kHybridDim)
+      return fail(ZEUS_EUNSUPPORTED, "user objectives need dim <= 208 with BFGS (L-BFGS: <= 256)");
   } else if (p->objective == ZEUS_USER) {
     return fail(ZEUS_EINVAL, "ZEUS_USER problems run through zeus_minimize_user");
   } else if (p->objective < ZEUS_ROSENBROCK || p->objective > ZEUS_QUARTIC) {

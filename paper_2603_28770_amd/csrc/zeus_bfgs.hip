@@ -216,7 +216,7 @@ hipError_t launch_bfgs(const Group &g) {
   if (g.method == 1) return launch_lbfgs(g, cus);
   if (g.g_bfgs == kWideLanes) return launch_bfgs_wide(g, cus);
   if (g.g_bfgs == kTileBlockDim || g.g_bfgs == kHybridDim) {
-    if (g.objective == kUser) return hipErrorInvalidValue;
+    if (g.objective == kUser) return launch_user_bfgs(g, g.total_starts, cus);
     return g.g_bfgs == kTileBlockDim ? launch_bfgs_tile(g, cus) : launch_bfgs_hybrid(g, cus);
   }
   if (g.g_bfgs > kMaxNarrowDim) return hipErrorInvalidValue;

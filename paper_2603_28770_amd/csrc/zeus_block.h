@@ -29,6 +29,8 @@ template <int K, class T, class Shm>
 __device__ __forceinline__ void block_tree_sums(T (&v)[K], Shm &sh, int &phase) {
   constexpr int NW = shm_waves<Shm>();
   static_assert(NW == 4 || NW == 8, "blocks of four or eight wavefronts");
+  static_assert(K <= (int)(sizeof(Shm::red[0]) / sizeof(Shm::red[0][0])),
+                "more sums than the LDS struct has slots for");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -64,6 +66,17 @@ template <int OBJ, class T, bool kGrad, class Shm>
 __device__ __forceinline__ double block_eval(int d, const double *xs, double *gj, Shm &sh,
                                              int &phase) {
   using E = Elem<OBJ>;
+  if constexpr (whole_form<E>::value) {
+    // no term structure: Alg. 5 as written, lane j < d evaluating the whole
+    // function on dual numbers seeded with e_j (pass j); the primal part is
+    // the same on every lane
+    const int j = threadIdx.x;
+    if (!kGrad) return E::value(xs, d);
+    double g;
+    const double f = E::value_grad(xs, d, j < d ? j : -1, &g);
+    *gj = j < d ? g : 0.0;
+    return f;
+  } else {
   static_assert(E::W <= 2, "the tangent sum assumes at most two terms per coordinate");
   const int m = E::terms(d);
   const int j = threadIdx.x;
@@ -105,6 +118,7 @@ __device__ __forceinline__ double block_eval(int d, const double *xs, double *gj
   const dual<T> r = E::template outer<dual<T>>(d, sd);
   *gj = (j < d) ? (double)r.t : 0.0;
   return (double)r.v;
+  }
 }
 
 // One Armijo search (Alg. 6) with the objective in number type U over SLOTS
@@ -122,6 +136,28 @@ __device__ __forceinline__ int block_armijo(Shm &sh, double f, double ddir, int 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const ReqHot &q = sh.q;
   const int d = q.d, m = q.m;
+  if constexpr (whole_form<E>::value) {
+    // no term structure: one trial per lane, trials base .. base + 64 NW - 1
+    // in a round; wavefront w reports its first passing lane
+    for (int base = 0; base < q.iter_ls; base += 64 * NW) {
+      const int t = base + (int)threadIdx.x;
+      bool ok = false;
+      if (t < q.iter_ls) {
+        const double alpha = step_length(sh.al, q.shrink, t);
+        ok = E::trial(sh.xs, sh.ps, alpha, d) <= f + (q.armijo_c * alpha) * ddir;
+      }
+      const uint64_t hit = __ballot(ok);
+      if (lane == 0) sh.pass[lsphase][w] = hit ? __ffsll((unsigned long long)hit) : 0;
+      __syncthreads();
+      int first = -1;
+#pragma unroll
+      for (int v = NW - 1; v >= 0; --v)
+        if (sh.pass[lsphase][v]) first = 64 * v + sh.pass[lsphase][v] - 1;
+      lsphase ^= 1;
+      if (first >= 0) return base + first;
+    }
+    return -1;
+  } else {
   for (int base = 0; base < q.iter_ls; base += NW) {
     const int t = base + w;
     const double alpha = step_length(sh.al, q.shrink, t);
@@ -156,6 +192,7 @@ __device__ __forceinline__ int block_armijo(Shm &sh, double f, double ddir, int 
     if (first >= 0) return base + first;
   }
   return -1;
+  }
 }
 
 }  // namespace zeus

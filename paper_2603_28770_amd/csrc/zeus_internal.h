@@ -121,13 +121,15 @@ struct BatchDev {
 
 // Kernels of a user objective, compiled at run time (zeus_user.cpp): the
 // module, its swarm kernels by log2 of the coordinate slots per particle
-// (2..256), its BFGS kernels by log2 of the lanes per start (4..64) and its
-// L-BFGS kernels by log2 of the coordinate slots per start (4..256)
-// (hipModule_t and hipFunction_t handles).
+// (2..256), its BFGS kernels by log2 of the lanes per start (4..64), its
+// block BFGS kernels (H in registers up to d = 128, in registers and LDS up
+// to 208) and its L-BFGS kernels by log2 of the coordinate slots per start
+// (4..256) (hipModule_t and hipFunction_t handles).
 struct UserKernels {
   void *module;
   void *pso[9];
   void *bfgs[7];
+  void *bfgs_tile, *bfgs_hybrid;
   void *lbfgs[9];
 };
 

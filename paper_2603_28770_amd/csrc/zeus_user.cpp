@@ -4,8 +4,9 @@
 // The program is zeus_user.h, the user's source, zeus_user_elem.h and the
 // swarm, BFGS and L-BFGS kernel templates, instantiated for kUser at every
 // size (swarm: 2..256 coordinate slots per particle, one per lane up to 64
-// lanes and 2 or 4 per lane beyond; BFGS: 4..64 lanes per start; L-BFGS:
-// 4..256 coordinate slots per start; FP64).  The
+// lanes and 2 or 4 per lane beyond; BFGS: 4..64 lanes per start, and the two
+// on-chip block kernels for 64 < d <= 128 and <= 208; L-BFGS: 4..256
+// coordinate slots per start; FP64).  The
 // headers are compiled into the library as text (zeus_rtc_headers.inc,
 // generated from the sources by the build), so the same template code runs
 // for built-in and user objectives.  The build's code-generation flags are
@@ -63,7 +64,8 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
   prog += "#line 1 \"objective\"\n";
   prog += source;
   prog += "\n#include \"zeus_user_elem.h\"\n#include \"zeus_pso_kernels.h\"\n"
-          "#include \"zeus_bfgs_kernels.h\"\n#include \"zeus_lbfgs_kernels.h\"\n";
+          "#include \"zeus_bfgs_kernels.h\"\n#include \"zeus_lbfgs_kernels.h\"\n"
+          "#include \"zeus_bfgs_tile_kernels.h\"\n#include \"zeus_bfgs_hybrid_kernels.h\"\n";
   std::vector<const char *> names, texts;
   for (int i = 0; i < kRtcHeaderCount; ++i) {
     names.push_back(kRtcHeaders[i].name);
@@ -97,6 +99,9 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
     lbfgs_expr.push_back("&zeus::lbfgs_kernel<7, " + split(l) + ", double>");
     hiprtcAddNameExpression(p, lbfgs_expr.back().c_str());
   }
+  const std::vector<std::string> block_expr = {"&zeus::bfgs_tile_kernel<7, double>",
+                                               "&zeus::bfgs_hybrid_kernel<7, double>"};
+  for (const std::string &e : block_expr) hiprtcAddNameExpression(p, e.c_str());
   const std::string arch_opt = std::string("--offload-arch=") + arch;
   const char *opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
                         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
@@ -124,7 +129,7 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
     return out_names;
   };
   const std::vector<std::string> pso_names = lowered(pso_expr), bfgs_names = lowered(bfgs_expr),
-                                 lbfgs_names = lowered(lbfgs_expr);
+                                 lbfgs_names = lowered(lbfgs_expr), block_names = lowered(block_expr);
   hiprtcDestroyProgram(&p);
   if (!load) return 0;
   hipModule_t mod;
@@ -148,6 +153,11 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
     hipFunction_t f;
     if ((he = hipModuleGetFunction(&f, mod, lbfgs_names[l - 2].c_str())) != hipSuccess) break;
     out->lbfgs[l] = f;
+  }
+  for (int b = 0; he == hipSuccess && b < 2; ++b) {
+    hipFunction_t f;
+    if ((he = hipModuleGetFunction(&f, mod, block_names[b].c_str())) != hipSuccess) break;
+    (b == 0 ? out->bfgs_tile : out->bfgs_hybrid) = f;
   }
   if (he != hipSuccess) {
     *log = std::string("hipModuleGetFunction: ") + hipGetErrorString(he);
@@ -174,6 +184,29 @@ hipError_t launch_user_pso(const Group &g, int t) {
 }
 
 hipError_t launch_user_bfgs(const Group &g, int64_t want, int cus) {
+  if (g.g_bfgs == kTileBlockDim || g.g_bfgs == kHybridDim) {
+    // one block per start, as many as can be resident (static LDS only)
+    void *fn = g.user ? (g.g_bfgs == kTileBlockDim ? g.user->bfgs_tile : g.user->bfgs_hybrid) : nullptr;
+    if (!fn) return hipErrorInvalidValue;
+    hipFunction_t f = static_cast<hipFunction_t>(fn);
+    const int threads = g.g_bfgs == kTileBlockDim ? kWideLanes : 2 * kWideLanes;
+    int per_cu = 0;
+    hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, threads, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const int64_t cap = (int64_t)cus * per_cu;
+    if (g.resident) {
+      *g.resident = cap;
+      return hipSuccess;
+    }
+    const unsigned blocks = (unsigned)(g.total_starts < cap ? g.total_starts : cap);
+    const ReqDev *reqs = g.reqs;
+    int nreq = g.nreq;
+    BatchDev *hdr = g.hdr;
+    int64_t total = g.total_starts;
+    void *args[] = {&reqs, &nreq, &hdr, &total};
+    return hipModuleLaunchKernel(f, blocks, 1, 1, (unsigned)threads, 1, 1, 0, g.stream, args, nullptr);
+  }
   const int l = log2_of(g.g_bfgs);
   if (!g.user || l < 2 || l > 6 || !g.user->bfgs[l]) return hipErrorInvalidValue;
   hipFunction_t f = static_cast<hipFunction_t>(g.user->bfgs[l]);

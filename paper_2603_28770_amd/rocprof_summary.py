@@ -42,9 +42,9 @@ KERNEL_SOURCES = {
                    "csrc/zeus_internal.h"],
     "lbfgs_kernel": ["csrc/zeus_lbfgs_kernels.h", "csrc/zeus_bfgs_common.h", "csrc/zeus_group.h",
                      "csrc/zeus_device.h", "csrc/zeus_internal.h"],
-    "bfgs_tile_kernel": ["csrc/zeus_bfgs_tile.hip", "csrc/zeus_block.h", "csrc/zeus_bfgs_common.h",
+    "bfgs_tile_kernel": ["csrc/zeus_bfgs_tile_kernels.h", "csrc/zeus_block.h", "csrc/zeus_bfgs_common.h",
                          "csrc/zeus_group.h", "csrc/zeus_device.h", "csrc/zeus_internal.h"],
-    "bfgs_hybrid_kernel": ["csrc/zeus_bfgs_hybrid.hip", "csrc/zeus_block.h", "csrc/zeus_bfgs_common.h",
+    "bfgs_hybrid_kernel": ["csrc/zeus_bfgs_hybrid_kernels.h", "csrc/zeus_block.h", "csrc/zeus_bfgs_common.h",
                            "csrc/zeus_group.h", "csrc/zeus_device.h", "csrc/zeus_internal.h"],
     "bfgs_wide_kernel": ["csrc/zeus_bfgs_wide.hip", "csrc/zeus_block.h", "csrc/zeus_bfgs_common.h",
                          "csrc/zeus_group.h", "csrc/zeus_device.h", "csrc/zeus_internal.h"],

@@ -3,8 +3,9 @@ against the oracle running the same source compiled for the CPU: swarm seeds
 and every start's f, x, iterations, status and line-search trials bit for
 bit, for one to four requests per call (a Goldstein-Price batch), every lane
 count from 4 to 64, trigonometric, logarithmic and exponential user code
-(a binned Poisson likelihood fit), L-BFGS from d = 5 to d = 200 (one, two and
-four coordinates per lane), and early stop; plus the refusals."""
+(a binned Poisson likelihood fit), BFGS on the on-chip block kernels at
+d = 100 and 150, L-BFGS from d = 5 to d = 200 (one, two and four coordinates
+per lane), and early stop; plus the refusals."""
 import numpy as np
 import pytest
 
@@ -53,6 +54,10 @@ CASES = [
     ("chain_log_d100_lbfgs", UO.CHAIN_LOG, [_p(100, 96, -2.0, 2.0, 13, lbfgs_m=6, iter_bfgs=150)]),
     ("rosenbrock_d200_lbfgs", UO.ROSENBROCK,
      [_p(200, 64, -2.0, 2.0, 14, iter_pso=2, lbfgs_m=8, iter_bfgs=150)]),
+    # BFGS above 64 dimensions: one block per start, H in registers (d <= 128),
+    # then in registers and LDS (d <= 208)
+    ("chain_log_d100", UO.CHAIN_LOG, [_p(100, 48, -2.0, 2.0, 15, iter_pso=2, iter_bfgs=120)]),
+    ("rosenbrock_d150", UO.ROSENBROCK, [_p(150, 32, -2.0, 2.0, 16, iter_pso=2, iter_bfgs=150)]),
 ]
 
 
@@ -133,7 +138,7 @@ def test_poisson_fit_recovers_the_spectrum(Z, ctx, compiled, oracle_mod):
 
 def test_user_refusals(Z, ctx, compiled):
     obj = compiled(UO.ROSENBROCK)
-    for bad, code in ((dict(dim=65), Z.EUNSUPPORTED), (dict(precision="mixed"), Z.EUNSUPPORTED),
+    for bad, code in ((dict(dim=209), Z.EUNSUPPORTED), (dict(precision="mixed"), Z.EUNSUPPORTED),
                       (dict(dim=257, lbfgs_m=4), Z.EUNSUPPORTED), (dict(lbfgs_m=9), Z.EUNSUPPORTED),
                       (dict(objective="rosenbrock"), Z.EINVAL)):
         with pytest.raises(Z.ZeusError) as e:
