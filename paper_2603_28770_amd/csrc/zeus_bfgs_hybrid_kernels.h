@@ -114,7 +114,7 @@ __device__ __forceinline__ double hybrid_row(const HybridShm &sh, int i) {
 // (other lanes 0).
 __device__ __forceinline__ double hybrid_matvec(const Tile<64> &H, const double *vec, HybridShm &sh,
                                                 int t, int lane, int w, int c0, int d) {
-  sh.tpart[w][lane] = H.matvec(vec + vpos<256>(c0), lane);
+  sh.tpart[w][lane] = H.matvec_bcast(vec[vpos<256>(c0 + lane)]);
   for (int q = t; q < kQ; q += kHLanes) {
     double acc = 0.0;
     if (chain_live(q, d)) {
@@ -251,8 +251,8 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
         const double beta = (rho * rho) * yu + rho;
         // H+ = H - rho (s u' + u s') + beta s s'   (u = H y); inf * 0 would
         // have reached the padding when a coefficient is not finite
-        if (!H.rank2_rc(rho, beta, sh.us + vpos<256>(r0), sh.ss + vpos<256>(r0),
-                        sh.us + vpos<256>(c0), sh.ss + vpos<256>(c0), lane, 0.0, 0.0))
+        if (!H.rank2_bcast(rho, beta, sh.us + vpos<256>(r0), sh.ss + vpos<256>(r0),
+                           sh.us[vpos<256>(c0 + lane)], sh.ss[vpos<256>(c0 + lane)], lane, 0.0, 0.0))
           H.restore_padding_at(lane, d, r0, c0);
         chains_rank2(sh, j, d, rho, beta);
       }

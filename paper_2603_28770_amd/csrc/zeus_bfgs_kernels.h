@@ -159,18 +159,32 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
     if (!fresh) {
       if (sy > 0.0) {  // curvature condition; skip the update otherwise
         const double rho = 1.0 / sy;
-        sh.vs[vpos<G>(j)] = yj;
-        wave_sync();
-        double uj = H.matvec(sh.vs, j);  // every lane: the tile sums cross lanes
+        // every lane: the tile sums cross lanes.  From 16 lanes on the tiles
+        // take the vector by row broadcasts from the lanes' own entries.
+        double uj;
+        if constexpr (kTileCols<G> == 16) {
+          uj = H.matvec_bcast(yj);
+        } else {
+          sh.vs[vpos<G>(j)] = yj;
+          wave_sync();
+          uj = H.matvec(sh.vs, j);
+        }
         uj = own ? uj : 0.0;
         const double yu = lane_tree_sum<G, double>(yj * uj);
-        sh.us[vpos<G>(j)] = uj;
-        sh.ss[vpos<G>(j)] = sj;
-        wave_sync();
+        if constexpr (kTileRows<G> > 1 || kTileCols<G> < 16) {  // rows of other lanes
+          sh.us[vpos<G>(j)] = uj;
+          sh.ss[vpos<G>(j)] = sj;
+          wave_sync();
+        }
         const double beta = (rho * rho) * yu + rho;
         // H+ = H - rho (s u' + u s') + beta s s'   (u = H y); inf * 0 would
         // have reached the padding when a coefficient is not finite
-        if (!H.rank2(rho, beta, sh.us, sh.ss, j, sj, uj)) H.restore_padding(j, d);
+        bool fin;
+        if constexpr (kTileCols<G> == 16)
+          fin = H.rank2_bcast(rho, beta, sh.us, sh.ss, uj, sj, j, sj, uj);
+        else
+          fin = H.rank2(rho, beta, sh.us, sh.ss, j, sj, uj);
+        if (!fin) H.restore_padding(j, d);
       }
       ++k;
     }
@@ -214,9 +228,14 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
     }
 
     // -- search direction p = -H g (reset to -g if not a descent direction) -
-    sh.vs[vpos<G>(j)] = gj;
-    wave_sync();
-    const double hg = H.matvec(sh.vs, j);  // every lane: the tile sums cross lanes
+    double hg;  // every lane: the tile sums cross lanes
+    if constexpr (kTileCols<G> == 16) {
+      hg = H.matvec_bcast(gj);
+    } else {
+      sh.vs[vpos<G>(j)] = gj;
+      wave_sync();
+      hg = H.matvec(sh.vs, j);
+    }
     pj = own ? -hg : 0.0;
     double ddir = lane_tree_sum<G, double>(gj * pj);
     if (!(ddir < 0.0)) {

@@ -59,7 +59,7 @@ struct TileShm {
 // (the same bits in wavefronts w and w ^ 2: IEEE addition commutes).
 __device__ __forceinline__ double tile_block_matvec(const Tile<64> &H, const double *v, TileShm &sh,
                                                     int lane, int w, int c0) {
-  const double mine = H.matvec(v + vpos<kTDim>(c0), lane);
+  const double mine = H.matvec_bcast(v[vpos<kTDim>(c0 + lane)]);
   sh.part[w][lane] = mine;
   __syncthreads();
   return mine + sh.part[w ^ 2][lane];
@@ -156,8 +156,9 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
         const double beta = (rho * rho) * yu + rho;
         // H+ = H - rho (s u' + u s') + beta s s'   (u = H y); inf * 0 would
         // have reached the padding when a coefficient is not finite
-        if (!H.rank2_rc(rho, beta, sh.us + vpos<kTDim>(r0), sh.ss + vpos<kTDim>(r0),
-                        sh.us + vpos<kTDim>(c0), sh.ss + vpos<kTDim>(c0), lane, 0.0, 0.0))
+        if (!H.rank2_bcast(rho, beta, sh.us + vpos<kTDim>(r0), sh.ss + vpos<kTDim>(r0),
+                           sh.us[vpos<kTDim>(c0 + lane)], sh.ss[vpos<kTDim>(c0 + lane)], lane, 0.0,
+                           0.0))
           H.restore_padding_at(lane, d, r0, c0);
       }
       ++k;

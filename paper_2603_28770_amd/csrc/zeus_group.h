@@ -156,6 +156,97 @@ __device__ __forceinline__ void lds_load(double (&b)[N], const double *v) {
   for (int c = 0; c < N; ++c) b[c] = v[c];
 }
 
+// Row broadcasts for the tiles: v_fmac_f64 with DPP row_newbcast:K on its
+// first operand multiplies by the value of lane K of the lane's row of 16
+// lanes.  In a tile with 16 columns per row, the lane at position K of a row
+// holds entry K of the row's 16-column block of a vector, which is what
+// every lane of the row needs for its column K, so the products and the
+// update read their vector operands from registers, not LDS.  Each asm
+// statement starts with s_nop 1: a DPP read needs two wait states after a
+// VALU write of its source.  Wait states and operand order are the only
+// difference from __builtin_fma: fma(a, b, c) == fma(b, a, c) bit for bit.
+template <int K>
+struct IntK {
+  static constexpr int value = K;
+};
+template <int K, int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (K < N) {
+    f(IntK<K>{});
+    static_for<K + 1, N>(f);
+  }
+}
+
+// acc_t += bcast_K(v) * h_t for the R = 1, 2 or 4 rows of a tile column
+template <int K>
+__device__ __forceinline__ void fmac_bcast(double &a0, double v, double h0) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(a0)
+      : "v"(v), "v"(h0), "n"(K));
+}
+template <int K>
+__device__ __forceinline__ void fmac_bcast(double &a0, double &a1, double v, double h0, double h1) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %2, %3 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %2, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf"
+      : "+v"(a0), "+v"(a1)
+      : "v"(v), "v"(h0), "v"(h1), "n"(K));
+}
+template <int K>
+__device__ __forceinline__ void fmac_bcast(double &a0, double &a1, double &a2, double &a3, double v,
+                                           double h0, double h1, double h2, double h3) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, %5 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %4, %6 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %4, %7 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %4, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf"
+      : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
+      : "v"(v), "v"(h0), "v"(h1), "v"(h2), "v"(h3), "n"(K));
+}
+// x_t = fma(e_t, bcast_K(s), fma(a_t, bcast_K(u), x_t)) for the rows of a tile column
+template <int K>
+__device__ __forceinline__ void upd_bcast(double &x0, double u, double s, double a0, double e0) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %1, %3 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %2, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf"
+      : "+v"(x0)
+      : "v"(u), "v"(s), "v"(a0), "v"(e0), "n"(K));
+}
+template <int K>
+__device__ __forceinline__ void upd_bcast(double &x0, double &x1, double u, double s, double a0,
+                                          double a1, double e0, double e1) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %2, %4 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %2, %5 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %3, %6 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %3, %7 row_newbcast:%8 row_mask:0xf bank_mask:0xf"
+      : "+v"(x0), "+v"(x1)
+      : "v"(u), "v"(s), "v"(a0), "v"(a1), "v"(e0), "v"(e1), "n"(K));
+}
+template <int K>
+__device__ __forceinline__ void upd_bcast(double &x0, double &x1, double &x2, double &x3, double u,
+                                          double s, const double (&a)[4], const double (&e)[4]) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %4, %7 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %4, %8 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %4, %9 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %5, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %5, %11 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %5, %12 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %5, %13 row_newbcast:%14 row_mask:0xf bank_mask:0xf"
+      : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3)
+      : "v"(u), "v"(s), "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(e[0]), "v"(e[1]),
+        "v"(e[2]), "v"(e[3]), "n"(K));
+}
+
 template <int G>
 constexpr int kTileCols = G < 16 ? G : 16;
 template <int G>
@@ -257,6 +348,36 @@ struct Tile {
     }
   }
 
+  // The same product with the vector's entry of column col(j, k) taken from
+  // lane k of the lane's row of 16 (row broadcasts): vc is the vector's entry
+  // of column col(j, 0) + (j mod 16), i.e. of this lane's position in its
+  // block (for a tile of the whole matrix, lane j's own entry).  Needs 16
+  // columns per tile row (G >= 16).
+  __device__ __forceinline__ double matvec_bcast(double vc) const {
+    static_assert(C == 16, "row broadcasts need 16 columns per tile row");
+    double part[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) part[t] = 0.0;
+    static_for<0, C>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      if constexpr (R == 4)
+        fmac_bcast<k>(part[0], part[1], part[2], part[3], vc, h[k], h[C + k], h[2 * C + k], h[3 * C + k]);
+      else if constexpr (R == 2)
+        fmac_bcast<k>(part[0], part[1], vc, h[k], h[C + k]);
+      else
+        fmac_bcast<k>(part[0], vc, h[k]);
+    });
+    if constexpr (R == 1) {
+      return part[0];
+    } else if constexpr (R == 2) {
+      return half_pair_sum<16>(part[0], part[1]);
+    } else {
+      const double q0 = half_pair_sum<16>(part[0], part[1]);
+      const double q1 = half_pair_sum<16>(part[2], part[3]);
+      return half_pair_sum<32>(q0, q1);
+    }
+  }
+
   // H <- H - rho (s u' + u s') + beta s s', element (r, c) by
   // fma(e_r, s_c, fma(a_r, u_c, H_rc)) with a_r = -rho s_r and
   // e_r = beta s_r - rho u_r; u and s in the padded layout, sj and uj this
@@ -265,6 +386,36 @@ struct Tile {
   __device__ __forceinline__ bool rank2(double rho, double beta, const double *us, const double *ss,
                                         int j, double sj, double uj) {
     return rank2_rc(rho, beta, us, ss, us, ss, j, sj, uj);
+  }
+
+  // The update with the columns' entries of u and s taken by row broadcasts
+  // (uc, sc: the entries of this lane's position in its block, as for
+  // matvec_bcast); the rows' entries are read from ur_v and sr_v (padded
+  // layout, from the tile's first row) when R > 1, else they are uj and sj.
+  __device__ __forceinline__ bool rank2_bcast(double rho, double beta, const double *ur_v,
+                                              const double *sr_v, double uc, double sc, int j,
+                                              double sj, double uj) {
+    static_assert(C == 16, "row broadcasts need 16 columns per tile row");
+    double a[R], e[R];
+    bool fin = true;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const double sr = R == 1 ? sj : sr_v[vpos<G>(row(j, t))];
+      const double ur = R == 1 ? uj : ur_v[vpos<G>(row(j, t))];
+      a[t] = -rho * sr;
+      e[t] = beta * sr - rho * ur;
+      fin = fin && __builtin_isfinite(a[t]) && __builtin_isfinite(e[t]);
+    }
+    static_for<0, C>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      if constexpr (R == 4)
+        upd_bcast<k>(h[k], h[C + k], h[2 * C + k], h[3 * C + k], uc, sc, a, e);
+      else if constexpr (R == 2)
+        upd_bcast<k>(h[k], h[C + k], uc, sc, a[0], a[1], e[0], e[1]);
+      else
+        upd_bcast<k>(h[k], uc, sc, a[0], e[0]);
+    });
+    return fin;
   }
 
   // The update of a tile that holds a block of a larger matrix: the rows'
