@@ -42,6 +42,18 @@ __device__ __forceinline__ void fill_step_lengths(double *al, double shrink, int
   }
 }
 
+// In the second early-stop pass almost every claimed start keeps its
+// first-pass result, so a claim is mostly a skip and the agent-scope work
+// counter would serialise the pass (one same-address atomic per start).
+// There a worker (group or block) `self` of `workers` takes the starts
+// self, self + workers, self + 2 workers, ... instead: the reruns are short
+// and alike, so a static split balances them.  Returns the worker's n-th
+// start (n >= 1) in that split.
+__device__ __forceinline__ unsigned long long strided_claim(unsigned long long self,
+                                                            unsigned long long workers, int n) {
+  return self + (unsigned long long)n * workers;
+}
+
 // The request of a launch group that holds global start `got` (the start
 // offsets of the table ascend from 0).
 __device__ __forceinline__ int request_of(const ReqDev *reqs, int nreq, int64_t got) {

@@ -12,7 +12,8 @@
 //    column strip (rows 0 .. 191, columns 192 .. 207) and the row strip (rows
 //    192 .. 207, all columns) -- is held in LDS as chains of 16 consecutive
 //    columns of one row, 656 chains, element k of chain q at hl[k][q] so that
-//    the lanes of a wavefront read consecutive addresses;
+//    the lanes of a wavefront read consecutive addresses; lane t owns chain t
+//    and lanes 256 .. 399 one more (the wavefronts without gradient work);
 //  * a row's product with a vector is a fused multiply-add chain over each
 //    block of 16 consecutive columns, the block sums added pairwise over the
 //    13 blocks (the order of every other kernel): a register tile's four
@@ -78,6 +79,18 @@ __device__ __forceinline__ int chain_block(int q) {
   return q < kQT ? 8 + (q >> 6) : q < kQT + kQC ? kHB - 1 : (q - kQT - kQC) >> 4;
 }
 
+// The chains of lane t: chain t, and for lanes 256 .. 399 (wavefronts that
+// take no part in the gradient, which only lanes below the dimension
+// evaluate) one of the 144 chains past 512.
+// (A loop, not unrolled: two inlined copies of a chain's work would keep
+// both chains' loads in flight and spill.)
+template <class F>
+__device__ __forceinline__ void for_lane_chains(int t, F &&f) {
+  const int n = (t >= kHLanes / 2 && kHLanes + (t - kHLanes / 2) < kQ) ? 2 : 1;
+#pragma unroll 1
+  for (int i = 0; i < n; ++i) f(i == 0 ? t : kHLanes + (t - kHLanes / 2));
+}
+
 // A chain with no row or no column below the dimension lies in the padding.
 __device__ __forceinline__ bool chain_live(int q, int d) {
   return chain_row(q) < d && 16 * chain_block(q) < d;
@@ -85,11 +98,11 @@ __device__ __forceinline__ bool chain_live(int q, int d) {
 
 // Identity entries of the LDS part (all chains).
 __device__ __forceinline__ void chains_identity(HybridShm &sh, int t) {
-  for (int q = t; q < kQ; q += kHLanes) {
+  for_lane_chains(t, [&](int q) {
     const int r = chain_row(q), c0 = 16 * chain_block(q);
 #pragma unroll
     for (int k = 0; k < 16; ++k) sh.hl[k][q] = r == c0 + k ? 1.0 : 0.0;
-  }
+  });
 }
 
 // Row i of H v (lane i < kHD) from the register tiles' products (tpart) and
@@ -115,7 +128,7 @@ __device__ __forceinline__ double hybrid_row(const HybridShm &sh, int i) {
 __device__ __forceinline__ double hybrid_matvec(const Tile<64> &H, const double *vec, HybridShm &sh,
                                                 int t, int lane, int w, int c0, int d) {
   sh.tpart[w][lane] = H.matvec_bcast(vec[vpos<256>(c0 + lane)]);
-  for (int q = t; q < kQ; q += kHLanes) {
+  for_lane_chains(t, [&](int q) {
     double acc = 0.0;
     if (chain_live(q, d)) {
       const double *v = vec + vpos<256>(16 * chain_block(q));  // 16 consecutive entries
@@ -129,7 +142,7 @@ __device__ __forceinline__ double hybrid_matvec(const Tile<64> &H, const double 
       }
     }
     sh.cpart[q] = acc;
-  }
+  });
   __syncthreads();
   return t < kHD ? hybrid_row(sh, t) : 0.0;
 }
@@ -139,8 +152,8 @@ __device__ __forceinline__ double hybrid_matvec(const Tile<64> &H, const double 
 // e_r = beta s_r - rho u_r; a chain whose coefficients are not finite gets
 // its padding back.
 __device__ __forceinline__ void chains_rank2(HybridShm &sh, int t, int d, double rho, double beta) {
-  for (int q = t; q < kQ; q += kHLanes) {
-    if (!chain_live(q, d)) continue;
+  for_lane_chains(t, [&](int q) {
+    if (!chain_live(q, d)) return;
     const int r = chain_row(q), c0 = 16 * chain_block(q);
     const double sr = sh.ss[vpos<256>(r)], ur = sh.us[vpos<256>(r)];
     const double a = -rho * sr;
@@ -157,7 +170,7 @@ __device__ __forceinline__ void chains_rank2(HybridShm &sh, int t, int d, double
 #pragma unroll
       for (int k = 0; k < 16; ++k)
         if (c0 + k >= d) sh.hl[k][q] = r == c0 + k ? 1.0 : 0.0;
-  }
+  });
 }
 
 // See the narrow kernel for the mixed-precision rules (T = float).
@@ -177,12 +190,14 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
   int64_t idx = -1;
   int k = 0, ls_trials = 0;
   const int es_pass = es_pass_of(hdr);
+  int claims = 0;  // starts claimed after the first (second early-stop pass; thread 0)
 
   for (;;) {
     if (idx < 0) {
       if (j == 0) {
-        sh.got = first ? (unsigned long long)blockIdx.x
-                       : gridDim.x + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
+        sh.got = first           ? (unsigned long long)blockIdx.x
+                 : es_pass == 2 ? strided_claim(blockIdx.x, gridDim.x, ++claims)
+                                : gridDim.x + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
       }
       first = false;
       __syncthreads();

@@ -100,6 +100,8 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
   bool fresh = false, first = true;
   bool hi = !kMixed;  // evaluating in FP64 (always, unless mixed precision)
   const int es_pass = es_pass_of(hdr);
+  int claims = 0;  // starts claimed after the first (second early-stop pass)
+  int cur_ri = -1;  // the request whose scalars and step lengths the group's LDS holds
 
   for (;;) {
     // -- claim a start when idle ------------------------------------------
@@ -107,10 +109,14 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
       // the first start of a group is its own index; later ones come from
       // the counter, after the starts taken that way
       const unsigned long long groups = (unsigned long long)gridDim.x * (kBfgsBlock / G);
+      const unsigned long long self =
+          (unsigned long long)blockIdx.x * (kBfgsBlock / G) + (threadIdx.x >> 6) * S + L.grp;
       unsigned long long got = 0;
       if (first) {
-        got = (unsigned long long)blockIdx.x * (kBfgsBlock / G) + (threadIdx.x >> 6) * S + L.grp;
+        got = self;
         first = false;
+      } else if (es_pass == 2) {
+        got = strided_claim(self, groups, ++claims);
       } else {
         if (j == 0) got = groups + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
         got = __shfl(got, L.grp * G, 64);
@@ -124,9 +130,12 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
         continue;
       }
       const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(*sh.q, rq, ri, es_pass);
+      if (ri != cur_ri) {  // the LDS slice still holds the previous start's request
+        if (j == 0) load_hot<OBJ>(*sh.q, rq, ri, es_pass);
+        fill_step_lengths(sh.al, rq.shrink, j, G);
+        cur_ri = ri;
+      }
       own = j < d0;
-      fill_step_lengths(sh.al, rq.shrink, j, G);
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
       sh.xs[j] = xj;
       H.identity(j);  // H <- I

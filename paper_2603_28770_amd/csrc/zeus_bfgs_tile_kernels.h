@@ -83,12 +83,14 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
   int64_t idx = -1;
   int k = 0, ls_trials = 0;
   const int es_pass = es_pass_of(hdr);
+  int claims = 0;  // starts claimed after the first (second early-stop pass; thread 0)
 
   for (;;) {
     if (idx < 0) {
       if (j == 0) {
-        sh.got = first ? (unsigned long long)blockIdx.x
-                       : gridDim.x + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
+        sh.got = first           ? (unsigned long long)blockIdx.x
+                 : es_pass == 2 ? strided_claim(blockIdx.x, gridDim.x, ++claims)
+                                : gridDim.x + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
       }
       first = false;
       __syncthreads();

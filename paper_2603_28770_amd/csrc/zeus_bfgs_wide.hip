@@ -102,12 +102,14 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
   int k = 0, ls_trials = 0;
   bool have_p = false;  // p = -H g already formed by the update pass
   const int es_pass = es_pass_of(hdr);
+  int claims = 0;  // starts claimed after the first (second early-stop pass; thread 0)
 
   for (;;) {
     if (idx < 0) {
       if (j == 0) {
-        sh.got = first ? (unsigned long long)blockIdx.x
-                       : gridDim.x + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
+        sh.got = first           ? (unsigned long long)blockIdx.x
+                 : es_pass == 2 ? strided_claim(blockIdx.x, gridDim.x, ++claims)
+                                : gridDim.x + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
       }
       first = false;
       __syncthreads();

@@ -182,15 +182,21 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
 #pragma unroll
   for (int c = 0; c < CPL; ++c) own[c] = false, xj[c] = gj[c] = pj[c] = sj[c] = 0.0;
   const int es_pass = es_pass_of(hdr);
+  int claims = 0;  // starts claimed after the first (second early-stop pass)
+  int cur_ri = -1;  // the request whose scalars and step lengths the group's LDS holds
 
   for (;;) {
     // -- claim a start when idle (as the BFGS kernel) -----------------------
     if (idx < 0) {
       const unsigned long long groups = (unsigned long long)gridDim.x * (kBfgsBlock / G);
+      const unsigned long long self =
+          (unsigned long long)blockIdx.x * (kBfgsBlock / G) + (threadIdx.x >> 6) * S + L.grp;
       unsigned long long got = 0;
       if (first) {
-        got = (unsigned long long)blockIdx.x * (kBfgsBlock / G) + (threadIdx.x >> 6) * S + L.grp;
+        got = self;
         first = false;
+      } else if (es_pass == 2) {
+        got = strided_claim(self, groups, ++claims);
       } else {
         if (j == 0) got = groups + atomicAdd((unsigned long long *)&hdr->queue, 1ull);
         got = __shfl(got, L.grp * G, 64);
@@ -204,8 +210,11 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
         continue;
       }
       const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(*qh, rq, ri, es_pass);
-      fill_step_lengths(al, rq.shrink, j, G);
+      if (ri != cur_ri) {  // the LDS slice still holds the previous start's request
+        if (j == 0) load_hot<OBJ>(*qh, rq, ri, es_pass);
+        fill_step_lengths(al, rq.shrink, j, G);
+        cur_ri = ri;
+      }
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
         const int jj = j + G * c;

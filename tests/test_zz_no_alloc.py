@@ -3,8 +3,9 @@ ordinary asynchronous one (zeus_minimize_async with a caller workspace),
 through the C ABI: the same kernels run either way, so every output must be
 bit-identical.  Two calls in a row on the same stream, the second with a
 smaller problem (the static workspace keeps the first call's contents), then
-a problem whose inverse Hessians live in the workspace (dim > 64), and the
-clear error for a problem larger than the static workspace."""
+the block kernels (inverse Hessians on chip up to dim 208, in the workspace
+above), and the clear error for a problem larger than the static
+workspace."""
 import numpy as np
 import pytest
 
@@ -64,11 +65,15 @@ def test_static_workspace_two_calls_then_smaller(Z, ctx):
         _same(ra, rb)
 
 
-def test_static_workspace_with_inverse_hessian_slots(Z, ctx):
+@pytest.mark.parametrize("dim", [100, 150, 220], ids=["registers", "registers_lds", "slots"])
+def test_static_workspace_with_inverse_hessian_slots(Z, ctx, dim):
+    """The block kernels: H in registers (d = 100), in registers and LDS
+    (d = 150) and in device-memory slots carved from the workspace (d = 220)."""
     import torch
     s = torch.cuda.Stream()
-    p = W.problem(name="styblinski_d100", objective="styblinski_tang", dim=100, n=40,
+    p = W.problem(name=f"styblinski_d{dim}", objective="styblinski_tang", dim=dim, n=40,
                   lower=-5.0, upper=5.0, iter_pso=2, iter_bfgs=150, seed=3)
+    assert Z.zeus_workspace_bytes(Z.make_problem(p)) <= Z.STATIC_WORKSPACE_BYTES
     print(f"\n[static] {p['name']}", flush=True)
     ra, rb = _both(Z, ctx, p, s)
     _same(ra, rb)
