@@ -13,7 +13,7 @@
 //    192 .. 207, all columns) -- is held in LDS as chains of 16 consecutive
 //    columns of one row, 656 chains, element k of chain q at hl[k][q] so that
 //    the lanes of a wavefront read consecutive addresses; lane t owns chain t
-//    and lanes 256 .. 399 one more (the wavefronts without gradient work);
+//    and lanes 0 .. 143 chain t + 512 as well;
 //  * a row's product with a vector is a fused multiply-add chain over each
 //    block of 16 consecutive columns, the block sums added pairwise over the
 //    13 blocks (the order of every other kernel): a register tile's four
@@ -79,16 +79,17 @@ __device__ __forceinline__ int chain_block(int q) {
   return q < kQT ? 8 + (q >> 6) : q < kQT + kQC ? kHB - 1 : (q - kQT - kQC) >> 4;
 }
 
-// The chains of lane t: chain t, and for lanes 256 .. 399 (wavefronts that
-// take no part in the gradient, which only lanes below the dimension
-// evaluate) one of the 144 chains past 512.
+// The chains of lane t: t and t + 512, so lanes 0 .. 143 hold two.  The
+// wavefronts with the extra chains are the block's first ones: issue favours
+// a SIMD's older wavefronts, so there the longer path between two barriers is
+// served first.  Given instead to the wavefronts without gradient work (lanes
+// 256 .. 399) the same chains made the d = 200 solve 12% slower.
 // (A loop, not unrolled: two inlined copies of a chain's work would keep
 // both chains' loads in flight and spill.)
 template <class F>
 __device__ __forceinline__ void for_lane_chains(int t, F &&f) {
-  const int n = (t >= kHLanes / 2 && kHLanes + (t - kHLanes / 2) < kQ) ? 2 : 1;
 #pragma unroll 1
-  for (int i = 0; i < n; ++i) f(i == 0 ? t : kHLanes + (t - kHLanes / 2));
+  for (int q = t; q < kQ; q += kHLanes) f(q);
 }
 
 // A chain with no row or no column below the dimension lies in the padding.
