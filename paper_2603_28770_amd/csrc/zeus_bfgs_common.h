@@ -22,6 +22,9 @@ struct ReqHot {
 };
 constexpr int kHotDoubles = (sizeof(ReqHot) + 7) / 8;
 
+// Term sums an objective's outer function combines (Ackley has two).
+constexpr int kMaxSums = 2;
+
 // Step lengths alpha_t = shrink^t of the first kTabTrials trials, each the
 // product of the previous one and shrink, as Alg. 6 forms them.
 constexpr int kTabTrials = 32;
@@ -185,11 +188,13 @@ constexpr int kRound = G == 64 ? 2 : (G < 4 ? G : 4);
 // the last term): a lane adds its slots pairwise and the trial's lanes finish
 // the pairwise sum with a butterfly.  The first trial that passes is the step
 // Alg. 6 returns.  Returns its index, or -1 when none of the iter_ls trials
-// passes.
+// passes.  When acc (the group's LDS) is given and a trial passes, the
+// trial's first lane writes its k-th term sum to acc[k] (objectives with a
+// term structure); the group sees it after its next wave_sync.
 template <int OBJ, int G, int SLOTS, class U>
 __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const double *xs,
                                              const double *ps, const double *al, const ReqHot &q,
-                                             double f, double ddir) {
+                                             double f, double ddir, double *acc = nullptr) {
   using E = Elem<OBJ>;
   constexpr int R = kRound<G>, TP = G / R, B = SLOTS / TP;
   constexpr uint64_t leaders = [] {  // bit r * TP for every trial r of a round
@@ -250,7 +255,14 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const doubl
     const double ft = (double)E::template outer<U>(d, sums);
     const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
     const uint64_t hit = L.ballot(ok) & leaders;
-    if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1) / TP;
+    if (hit != 0ull) {
+      const int r = (__ffsll((unsigned long long)hit) - 1) / TP;  // the passing trial's slot
+      static_assert(E::K <= kMaxSums, "more term sums than the slots kept for them");
+      if (acc && L.j == r * TP)
+#pragma unroll
+        for (int kk = 0; kk < E::K; ++kk) acc[kk] = (double)sums[kk];
+      return base + r;
+    }
   }
   return -1;
   }

@@ -61,6 +61,7 @@ struct HybridShm {
   double tpart[kHW][64];         // each wavefront's products over its register tile
   double cpart[kQ];              // the chains' products
   double red[2][3][kHW];         // [phase][sum][wave] partial sums
+  double tsum[2 * kHW][kMaxSums];     // [phase * waves + wave][sum] line-search trials' term sums
   double al[kTabTrials];
   int pass[2][kHW];              // [phase][wave] line-search outcome
   unsigned long long got;
@@ -186,6 +187,7 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
   const bool coord = j < kHD;
   Tile<64> H;
   int phase = 0, lsphase = 0;
+  int acc = -1;  // slot of sh.tsum with the accepted trial's term sums (block_armijo), or -1
   bool own = false, first = true, fresh = false, hi = !kMixed;
   double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
   int64_t idx = -1;
@@ -235,9 +237,10 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
     // -- value and gradient at xs -------------------------------------------
     double gn, fn;
     if (hi)
-      fn = block_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase);
+      fn = block_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase, acc);
     else
-      fn = block_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase);
+      fn = block_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase, acc);
+    acc = -1;
 
     // y's, g'g and the non-finite test in one reduction, whose barrier also
     // publishes y and g for the products below; right after a claim or an
@@ -330,9 +333,9 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
     // -- Armijo backtracking (Alg. 6) ---------------------------------------
     int taken;
     if (hi) {
-      taken = block_armijo<OBJ, double, kHSlots>(sh, f, ddir, lsphase);
+      taken = block_armijo<OBJ, double, kHSlots>(sh, f, ddir, lsphase, &acc);
     } else {
-      taken = block_armijo<OBJ, T, kHSlots>(sh, f, ddir, lsphase);
+      taken = block_armijo<OBJ, T, kHSlots>(sh, f, ddir, lsphase, &acc);
       if (taken < 0) {
         ls_trials += q.iter_ls;
         hi = true;  // escalate: FP32 cannot resolve this decrease

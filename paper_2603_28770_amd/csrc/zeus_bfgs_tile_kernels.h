@@ -47,6 +47,7 @@ struct TileShm {
   double us[kTVec];  // u = H y, padded layout
   double part[kBlockWaves][kQuarter];  // each wavefront's products over its quarter
   double red[2][3][kBlockWaves];       // [phase][sum][wave] partial sums
+  double tsum[2 * kBlockWaves][kMaxSums];   // [phase * waves + wave][sum] line-search trials' term sums
   double al[kTabTrials];
   int pass[2][kBlockWaves];            // [phase][wave] line-search outcome
   unsigned long long got;
@@ -78,6 +79,7 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
   const int ci = j & (kTDim - 1);  // row whose products this lane receives
   Tile<64> H;
   int phase = 0, lsphase = 0;
+  int acc = -1;  // slot of sh.tsum with the accepted trial's term sums (block_armijo), or -1
   bool own = false, first = true, fresh = false, hi = !kMixed;
   double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
   int64_t idx = -1;
@@ -126,9 +128,10 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
     // -- value and gradient at xs -------------------------------------------
     double gn, fn;
     if (hi)
-      fn = block_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase);
+      fn = block_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase, acc);
     else
-      fn = block_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase);
+      fn = block_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase, acc);
+    acc = -1;
 
     // y's, g'g and the non-finite test in one reduction, whose barrier also
     // publishes y and g for the products below; right after a claim or an
@@ -220,9 +223,9 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
     // -- Armijo backtracking (Alg. 6) ---------------------------------------
     int taken;
     if (hi) {
-      taken = block_armijo<OBJ, double, kTDim>(sh, f, ddir, lsphase);
+      taken = block_armijo<OBJ, double, kTDim>(sh, f, ddir, lsphase, &acc);
     } else {
-      taken = block_armijo<OBJ, T, kTDim>(sh, f, ddir, lsphase);
+      taken = block_armijo<OBJ, T, kTDim>(sh, f, ddir, lsphase, &acc);
       if (taken < 0) {
         ls_trials += q.iter_ls;
         hi = true;  // escalate: FP32 cannot resolve this decrease

@@ -38,6 +38,7 @@ struct WideShm {
   double ss[kWide];  // s = x_new - x
   double us[kWide];  // u = H y
   double red[2][2][kWaves];  // [phase][sum][wave] partial sums
+  double tsum[2 * kWaves][kMaxSums];  // [phase * waves + wave][sum] line-search trials' term sums
   double al[kTabTrials];
   int pass[2][kWaves];       // [phase][wave] line-search outcome
   unsigned long long got;
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
   const int j = threadIdx.x;
   double *H = hslots + (int64_t)blockIdx.x * slot;  // column c of row j at H[c * cs + j]
   int phase = 0, lsphase = 0;
+  int acc = -1;  // slot of sh.tsum with the accepted trial's term sums (block_armijo), or -1
   bool own = false, first = true, fresh = false, hi = !kMixed;
   double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
   int64_t idx = -1;
@@ -148,9 +150,10 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
     // -- value and gradient at xs -------------------------------------------
     double gn, fn;
     if (hi)
-      fn = block_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase);
+      fn = block_eval<OBJ, double, true>(d, sh.xs, &gn, sh, phase, acc);
     else
-      fn = block_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase);
+      fn = block_eval<OBJ, T, true>(d, sh.xs, &gn, sh, phase, acc);
+    acc = -1;
 
     // -- after a step: y, u = H y, the rank-2 update and p = -H_new g_new ----
     have_p = false;
@@ -258,9 +261,9 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
     // -- Armijo backtracking -----------------------------------------------------
     int taken;
     if (hi) {
-      taken = block_armijo<OBJ, double, kWide>(sh, f, ddir, lsphase);
+      taken = block_armijo<OBJ, double, kWide>(sh, f, ddir, lsphase, &acc);
     } else {
-      taken = block_armijo<OBJ, T, kWide>(sh, f, ddir, lsphase);
+      taken = block_armijo<OBJ, T, kWide>(sh, f, ddir, lsphase, &acc);
       if (taken < 0) {
         ls_trials += q.iter_ls;
         hi = true;
