@@ -601,10 +601,17 @@ zeus_err enqueue_batch(zeus_context *ctx, const BatchPlan &b, const zeus_problem
                        const std::vector<hipStream_t> &streams) {
   char *R = static_cast<char *>(res_base), *Wb = static_cast<char *>(ws_base);
   zeus_err e;
-  for (size_t gi = 0; gi < b.order.size(); ++gi) {
-    hipStream_t s = streams[gi % streams.size()];
+  const size_t ng = b.order.size();
+  std::vector<std::vector<Planned>> plans(ng);
+  std::vector<GroupRun> runs(ng);
+  // Every group's request table first, all on the first stream: an upload
+  // from pageable host memory holds the host until its stream has finished
+  // the work queued before it, so an upload behind another group's kernels
+  // would keep the host from queueing anything else meanwhile.
+  for (size_t gi = 0; gi < ng; ++gi) {
     const std::vector<int32_t> &members = b.groups.at(b.order[gi]);
-    std::vector<Planned> plan(members.size());
+    std::vector<Planned> &plan = plans[gi];
+    plan.resize(members.size());
     for (size_t k = 0; k < members.size(); ++k) {
       const int32_t r = members[k];
       plan[k].pb = &problems[r];
@@ -612,9 +619,25 @@ zeus_err enqueue_batch(zeus_context *ctx, const BatchPlan &b, const zeus_problem
       plan[k].ws = carve_request_ws(Wb + b.ws_off[r], problems[r]);
     }
     void *hs = b.h_off[gi] == SIZE_MAX ? nullptr : Wb + b.h_off[gi];
-    if ((e = enqueue_group(ctx, plan, Wb + b.tab_off[gi], hs, s)) != ZEUS_OK) return e;
+    if ((e = build_group(plan, Wb + b.tab_off[gi], hs, streams[gi % streams.size()], &runs[gi])) !=
+        ZEUS_OK)
+      return e;
+    if ((e = upload_group(runs[gi], streams[0])) != ZEUS_OK) return e;
+  }
+  hipError_t he = hipStreamSynchronize(streams[0]);
+  if (he != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
+  for (size_t gi = 0; gi < ng; ++gi)
+    if ((e = launch_group(ctx, runs[gi], plans[gi], true)) != ZEUS_OK) return e;
+  // Then the copies, after every group's kernels: a copy into pageable host
+  // memory also holds the host until its stream gets there.  Issued between
+  // groups, the copies and uploads kept the next groups' kernels from being
+  // queued, so the persistent kernels of different groups never overlapped
+  // (the full uneven batch spent a fifth of its time with the device idle).
+  for (size_t gi = 0; gi < ng; ++gi) {
+    hipStream_t s = streams[gi % streams.size()];
+    const std::vector<int32_t> &members = b.groups.at(b.order[gi]);
     for (size_t k = 0; k < members.size(); ++k)
-      if ((e = copy_back(problems[members[k]], outs[members[k]], plan[k].dev, s)) != ZEUS_OK)
+      if ((e = copy_back(problems[members[k]], outs[members[k]], plans[gi][k].dev, s)) != ZEUS_OK)
         return e;
   }
   return ZEUS_OK;
