@@ -907,7 +907,12 @@ zeus_err minimize_batch(zeus_context *ctx, const zeus_problem *problems, int32_t
   ctx->active_user = user ? &user->k : nullptr;
   e = enqueue_batch(ctx, plan, problems, outs, ctx->res, ctx->ws, streams);
   ctx->active_user = nullptr;
-  if (e != ZEUS_OK) return e;
+  if (e != ZEUS_OK) {
+    // groups queued before the failure may still be running: let them end
+    // before the caller reuses (or the next call reallocates) the buffers
+    for (hipStream_t st : streams) (void)hipStreamSynchronize(st);
+    return e;
+  }
   hipError_t he;
   for (hipStream_t st : streams)
     if ((he = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
