@@ -37,6 +37,9 @@ CASES = [
               iter_pso=2, iter_bfgs=400, seed=3, lbfgs_m=8),
     W.problem(name="st100_m4", objective="styblinski_tang", dim=100, n=60, lower=-5.0, upper=5.0,
               iter_pso=2, iter_bfgs=300, seed=5, lbfgs_m=4),
+    # two term sums over two coordinates per lane
+    W.problem(name="ack120_m5", objective="ackley", dim=120, n=40, lower=-5.0, upper=5.0,
+              iter_pso=2, iter_bfgs=300, seed=15, lbfgs_m=5),
     W.problem(name="ros200_m6", objective="rosenbrock", dim=200, n=24, lower=-2.0, upper=2.0,
               iter_pso=1, iter_bfgs=1500, seed=9, lbfgs_m=6),
     W.problem(name="sphere256_m3", objective="sphere", dim=256, n=9, lower=-3.0, upper=3.0,

@@ -179,6 +179,10 @@ WIDE_CASES = [
               iter_pso=2, iter_bfgs=300, seed=12),
     W.problem(name="rastrigin_d100", objective="rastrigin", dim=100, n=40, lower=-5.12,
               upper=5.12, iter_pso=3, iter_bfgs=300, seed=1, request_id=3),
+    # two term sums (K = 2) on the four-wavefront block, whose next value
+    # takes both sums of the accepted line-search trial
+    W.problem(name="ackley_d90", objective="ackley", dim=90, n=30, lower=-5.0, upper=5.0,
+              iter_pso=2, iter_bfgs=200, seed=14),
     W.problem(name="styblinski_d128", objective="styblinski_tang", dim=128, n=33, lower=-5.0,
               upper=5.0, iter_pso=2, iter_bfgs=200, seed=3),
     W.problem(name="rosenbrock_d129", objective="rosenbrock", dim=129, n=24, lower=-2.0, upper=2.0,
