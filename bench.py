@@ -111,7 +111,7 @@ def algorithmic_flops_split(obj, d, n_starts, total_iters, total_ls_trials, lbfg
 #   Ackley           F_p = 6d + d (cos) + 2 (exp) + 1 (sqrt)   F_t = 6d
 #   Styblinski-Tang  F_p = 7d            F_t = 6d
 # (the test-only and user objectives take this file's own counts above).
-def _survey_counts(obj, d):
+def _method_counts(obj, d):
     if obj == "rosenbrock":
         return 8 * (d - 1), 10 * (d - 1)
     if obj == "rastrigin":
@@ -132,13 +132,13 @@ _SPARSE_TANGENT = {"rosenbrock": 20, "rastrigin": 5, "ackley": 14, "styblinski_t
                    "sphere": 2, "quartic": 3}
 
 
-def survey_flops(obj, d, total_iters, total_ls_trials, lbfgs_m=0):
-    """The method's algorithmic work as the survey defines it, per start-
-    iteration W_H + W_grad + W_LS: W_H = 6 d^2 (one matrix-vector product and
-    the rank-2 update; with L-BFGS the two-loop recursion 8 m d + 3 d),
-    W_grad = F_p + d F_t (one primal and d dense tangent sweeps), and per
-    line-search trial F_p + 2 d."""
-    fp, ft = _survey_counts(obj, d)
+def method_flops(obj, d, total_iters, total_ls_trials, lbfgs_m=0):
+    """The method's algorithmic work, per start-iteration W_H + W_grad + W_LS:
+    W_H = 6 d^2 (one matrix-vector product and the rank-2 update; with L-BFGS
+    the two-loop recursion 8 m d + 3 d), W_grad = F_p + d F_t (one primal and
+    the d dense tangent sweeps of Alg. 5), and per line-search trial
+    F_p + 2 d."""
+    fp, ft = _method_counts(obj, d)
     h_work = 8 * lbfgs_m * d + 3 * d if lbfgs_m else 6 * d * d
     return total_iters * (h_work + fp + d * ft) + total_ls_trials * (fp + 2 * d)
 
@@ -147,7 +147,7 @@ def sparse_flops(obj, d, total_iters, total_ls_trials, lbfgs_m=0):
     """The same work with each gradient direction sweeping only the terms
     that hold its coordinate (what a term-parallel evaluation needs); for
     objectives without a term structure the dense count."""
-    fp, ft = _survey_counts(obj, d)
+    fp, ft = _method_counts(obj, d)
     tan = _SPARSE_TANGENT.get(obj)
     grad = fp + d * (min(tan, ft) if tan is not None else ft)
     h_work = 8 * lbfgs_m * d + 3 * d if lbfgs_m else 6 * d * d
@@ -651,7 +651,7 @@ def measure_single(args, Z, ctx, stream, p, name):
     bfgs_ms = prof["bfgs_ms"] / max(1, prof["bfgs_launches"])
     lm = p.get("lbfgs_m", 0)
     trials = s["total_ls_trials"]
-    flops = survey_flops(p["objective"], p["dim"], iters, trials, lm)
+    flops = method_flops(p["objective"], p["dim"], iters, trials, lm)
     sparse = sparse_flops(p["objective"], p["dim"], iters, trials, lm)
     kernel, stem = main_kernel(p)
     achieved = flops / (bfgs_ms * 1e-3) / 1e12

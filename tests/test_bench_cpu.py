@@ -85,17 +85,17 @@ def test_missing_profile_is_not_used():
     assert bench.profiled_traffic("no_such_workload") is None
 
 
-def test_survey_count_hand_computed():
+def test_method_count_hand_computed():
     # Rosenbrock d = 50: F_p = 392, F_t = 490; per iteration 6 * 2500 + 392 + 50 * 490;
     # per trial 392 + 100
-    assert bench.survey_flops("rosenbrock", 50, 1, 0) == 15000 + 392 + 24500
-    assert bench.survey_flops("rosenbrock", 50, 0, 1) == 492
+    assert bench.method_flops("rosenbrock", 50, 1, 0) == 15000 + 392 + 24500
+    assert bench.method_flops("rosenbrock", 50, 0, 1) == 492
     # Rastrigin d = 10: F_p = 60, F_t = 50
-    assert bench.survey_flops("rastrigin", 10, 3, 7) == 3 * (600 + 60 + 500) + 7 * (60 + 20)
+    assert bench.method_flops("rastrigin", 10, 3, 7) == 3 * (600 + 60 + 500) + 7 * (60 + 20)
     # Ackley d = 50: F_p = 353, F_t = 300
-    assert bench.survey_flops("ackley", 50, 1, 1) == 15000 + 353 + 15000 + 353 + 100
+    assert bench.method_flops("ackley", 50, 1, 1) == 15000 + 353 + 15000 + 353 + 100
     # L-BFGS m = 8 at d = 200: the two-loop recursion in place of 6 d^2
-    assert bench.survey_flops("rosenbrock", 200, 1, 0, lbfgs_m=8) == (
+    assert bench.method_flops("rosenbrock", 200, 1, 0, lbfgs_m=8) == (
         8 * 8 * 200 + 600 + 8 * 199 + 200 * 10 * 199)
 
 
@@ -103,4 +103,4 @@ def test_sparse_count_is_below_the_dense_one():
     assert bench.sparse_flops("rosenbrock", 50, 1, 0) == 15000 + 392 + 50 * 20
     for obj in ("rosenbrock", "rastrigin", "ackley", "styblinski_tang"):
         for d in (2, 10, 50, 200):
-            assert bench.sparse_flops(obj, d, 100, 150) <= bench.survey_flops(obj, d, 100, 150)
+            assert bench.sparse_flops(obj, d, 100, 150) <= bench.method_flops(obj, d, 100, 150)
