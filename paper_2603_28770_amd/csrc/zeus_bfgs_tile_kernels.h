@@ -17,8 +17,9 @@
 //    lane i of wavefronts w and w + 2 both end with row 64 (w & 1) + i;
 //  * lanes 0 .. 127 own the coordinates (x, g, p, s, y); the vectors the
 //    tiles read (y, g, u, s) go through LDS in the padded layout, written
-//    before a reduction whose barrier publishes them (eight barriers per
-//    iteration with an update, plus one per line-search round);
+//    before a reduction whose barrier publishes them (six barriers per
+//    iteration with an update, plus one per line-search round: the value at
+//    a new iterate takes the accepted trial's term sums, block_eval);
 //  * gradient, sums, line search (four trials per round, one per wavefront),
 //    termination and retirement are those of the device-memory block kernel
 //    (zeus_block.h), with the term slots cut to 128;

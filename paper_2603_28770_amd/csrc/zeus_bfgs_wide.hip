@@ -1,6 +1,9 @@
-// zeus_bfgs_wide.hip -- the BFGS phase for 64 < d <= 256 (Alg. 4 / Alg. 10
-// with the dual-number gradient of Alg. 5 and the Armijo search of Alg. 6):
-// one block of 256 lanes per start.
+// zeus_bfgs_wide.hip -- the BFGS phase with the inverse Hessian in device
+// memory (Alg. 4 / Alg. 10 with the dual-number gradient of Alg. 5 and the
+// Armijo search of Alg. 6): one block of 256 lanes per start.  It runs
+// 208 < d <= 256, where H no longer fits on chip, and any d > 64 when the
+// tiling is forced (ZEUS_TILE_LANES=256), which the tests use to compare it
+// with the on-chip kernels.
 //
 //  * lane i owns coordinate i and row i of the inverse Hessian H;
 //  * a row of up to 256 doubles does not fit in registers, so H lives in a
