@@ -424,15 +424,19 @@ zeus_err launch_group(zeus_context *ctx, const GroupRun &run, const std::vector<
   if (prof) (void)hipEventRecord(pend.ev[0], stream);
   if ((e = zeus::launch_ws_init(g)) != hipSuccess) return hip_fail(e, "counter reset launch");
   if (with_swarm) {
+    TraceRange tr("zeus.swarm");
     for (int t = 0; t <= g.max_iter_pso; ++t)
       if ((e = zeus::launch_pso(g, t)) != hipSuccess) return hip_fail(e, "swarm launch");
     if ((e = zeus::launch_pso_finish(g)) != hipSuccess) return hip_fail(e, "swarm best launch");
   }
   if (prof) (void)hipEventRecord(pend.ev[1], stream);
-  if ((e = zeus::launch_bfgs(g)) != hipSuccess) return hip_fail(e, "BFGS launch");
-  if (g.early_stop) {  // K*, then the rerun of the starts that went past it
-    if ((e = zeus::launch_es_finish(g)) != hipSuccess) return hip_fail(e, "early-stop launch");
+  {
+    TraceRange tr("zeus.bfgs");
     if ((e = zeus::launch_bfgs(g)) != hipSuccess) return hip_fail(e, "BFGS launch");
+    if (g.early_stop) {  // K*, then the rerun of the starts that went past it
+      if ((e = zeus::launch_es_finish(g)) != hipSuccess) return hip_fail(e, "early-stop launch");
+      if ((e = zeus::launch_bfgs(g)) != hipSuccess) return hip_fail(e, "BFGS launch");
+    }
   }
   if (prof) (void)hipEventRecord(pend.ev[2], stream);
   if ((e = zeus::launch_summary(g)) != hipSuccess) return hip_fail(e, "summary launch");
@@ -834,6 +838,7 @@ zeus_err enqueue_async(zeus_context *ctx, const zeus_problem &pb, void *workspac
 
 zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, void *workspace,
                              size_t workspace_bytes, const zeus_result *out, void *stream) {
+  TraceRange tr("zeus_minimize_async");
   g_last_error.clear();
   size_t need = 0;
   zeus_err e = check_async(ctx, problem, out, &need);
@@ -852,6 +857,7 @@ zeus_err zeus_minimize_async(zeus_context *ctx, const zeus_problem *problem, voi
 
 zeus_err zeus_minimize_async_static(zeus_context *ctx, const zeus_problem *problem,
                                     const zeus_result *out, void *stream) {
+  TraceRange tr("zeus_minimize_async_static");
   g_last_error.clear();
   size_t need = 0;
   zeus_err e = check_async(ctx, problem, out, &need);
@@ -877,6 +883,7 @@ namespace {
 // zeus_minimize_batch, and zeus_minimize_user with `user` set.
 zeus_err minimize_batch(zeus_context *ctx, const zeus_problem *problems, int32_t n,
                         const zeus_result *outs, const zeus_user_objective *user) {
+  TraceRange tr(user ? "zeus_minimize_user" : "zeus_minimize_batch");
   g_last_error.clear();
   if (!ctx) return fail(ZEUS_EINVAL, "ctx is NULL");
   if (n < 1 || !problems || !outs) return fail(ZEUS_EINVAL, "need n >= 1 problems and results");
@@ -997,6 +1004,7 @@ zeus_err zeus_plan_workspace_bytes(const zeus_problem *problems, int32_t n, size
 zeus_err zeus_plan_create(zeus_context *ctx, const zeus_problem *problems, int32_t n,
                           void *workspace, size_t workspace_bytes, const zeus_result *outs,
                           zeus_plan **out) {
+  TraceRange tr("zeus_plan_create");
   g_last_error.clear();
   if (!ctx || !out) return fail(ZEUS_EINVAL, "NULL argument");
   *out = nullptr;
@@ -1094,6 +1102,7 @@ zeus_err zeus_plan_create(zeus_context *ctx, const zeus_problem *problems, int32
 }
 
 zeus_err zeus_plan_launch(zeus_plan *plan, void *stream) {
+  TraceRange tr("zeus_plan_launch");
   g_last_error.clear();
   if (!plan) return fail(ZEUS_EINVAL, "plan is NULL");
   DeviceGuard dg(plan->device);

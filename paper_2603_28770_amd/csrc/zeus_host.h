@@ -5,6 +5,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -24,6 +25,18 @@ extern thread_local std::string g_last_error;
 
 zeus_err fail(zeus_err e, const std::string &msg);
 zeus_err hip_fail(hipError_t e, const char *what);
+
+// roctx ranges and markers on the host timeline (rocprofv3 --marker-trace):
+// a range around each entry point and each launch phase, markers where the
+// server admits and retires a request.  Without a profiler attached they
+// cost a call each.
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
+inline void trace_mark(const char *what) { roctxMarkA(what); }
 
 // Device memory pieces are 256-byte aligned.
 constexpr size_t kAlign = 256;

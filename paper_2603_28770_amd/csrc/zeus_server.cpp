@@ -167,6 +167,7 @@ class HipDevice : public Device {
   // Table upload, counter reset, swarm sweeps, swarm best and the optional
   // swarm-state copies of one admitted request, on the swarm stream.
   zeus_err swarm(Req &r, char *block) override {
+    TraceRange tr("zeus.server.swarm");
     hipStream_t s = streams_[kSwarmStream];
     char *res = block, *ws = block + align_up(r.rl.total);
     char *tab = ws + align_up(request_ws_bytes(r.pb));
@@ -188,6 +189,7 @@ class HipDevice : public Device {
   // One BFGS launch over the step's slices (two passes for a request with
   // early stop) on the stream of its buffer.
   zeus_err step(Step &st, int b, char *buf, size_t bytes) override {
+    TraceRange tr("zeus.server.step");
     hipStream_t s = streams_[b == 0 ? kStepStream0 : kStepStream1];
     std::vector<zeus_problem> pbs(st.slices.size());
     std::vector<Planned> planned(st.slices.size());
@@ -222,6 +224,7 @@ class HipDevice : public Device {
 
   // Best-of-N and the copies into the caller's arrays, on the finish stream.
   zeus_err finish(Req &r) override {
+    TraceRange tr("zeus.server.finish");
     hipStream_t s = streams_[kFinishStream];
     zeus::Group g = r.own.g;
     g.stream = s;
@@ -380,6 +383,7 @@ struct zeus_server {
   }
 
   void end_req(Req &r, State st) {
+    trace_mark("zeus.server.retire");
     r.state = st;
     r.times.t_done_ns = now_ns();
     pool.release(r.off, r.bytes);
@@ -446,6 +450,7 @@ struct zeus_server {
       size_t off = 0;
       if (!pool.alloc(q.bytes, &off)) break;
       queue.pop_front();
+      trace_mark("zeus.server.admit");
       q.off = off;
       q.state = kSwarm;
       q.times.t_admit_ns = now_ns();

@@ -34,6 +34,20 @@ def test_exports_every_declared_symbol(Z):
     assert set(Z.EXPORTS) == set(names)
 
 
+def test_trace_ranges_are_linked(Z):
+    """The entry points and launch phases mark roctx ranges (rocprofv3
+    --marker-trace): the library takes the roctx calls from ROCm's roctx
+    library, and the range names are in its code."""
+    und = subprocess.run(["nm", "-D", "--undefined-only", Z.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for sym in ("roctxRangePushA", "roctxRangePop", "roctxMarkA"):
+        assert sym in und, sym
+    data = open(Z.LIB_PATH, "rb").read()
+    for name in (b"zeus_minimize_batch", b"zeus.swarm", b"zeus.bfgs", b"zeus.server.step",
+                 b"zeus.server.admit", b"zeus.server.retire", b"zeus_plan_launch"):
+        assert name + b"\0" in data, name
+
+
 def test_struct_layouts_match_header(Z, tmp_path):
     import ctypes as C
     prog = tmp_path / "layout.c"

@@ -82,14 +82,16 @@ def test_short_request_finishes_inside_a_long_one(Z):
 def test_equal_requests_share_the_steps(Z):
     """Two equal requests admitted together progress together (each step gives
     both an equal slice), so they end close together rather than one after
-    the other (the first may lead by the steps built before the second's swarm
-    ended)."""
+    the other.  Run one after the other, the first would end halfway through
+    the span; the bound leaves room for the steps built before the second's
+    swarm ended and for a scheduling thread slowed by a loaded host (the
+    emulated device's operations are host time)."""
     with server(Z, 1 << 30) as srv:
         ts = [srv.submit(req(64 * 512, r)) for r in (1, 2)]
         outs = [srv.wait(t, timeout_s=60) for t in ts]
     d = [o["times"]["t_done_ns"] for o in outs]
     span = max(d) - min(o["times"]["t_admit_ns"] for o in outs)
-    assert abs(d[0] - d[1]) < 0.15 * span
+    assert abs(d[0] - d[1]) < 0.3 * span
 
 
 def test_cancel_queued_and_running(Z):
