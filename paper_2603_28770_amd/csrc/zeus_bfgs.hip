@@ -213,6 +213,13 @@ hipError_t launch_bfgs(const Group &g) {
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
+  // ZEUS_BFGS_CUS sizes the persistent grid for fewer compute units: the
+  // tests use it to show that results do not depend on how many groups or
+  // blocks share the starts (nor on which of them runs which start)
+  if (const char *e = getenv("ZEUS_BFGS_CUS")) {
+    const int v = atoi(e);
+    if (v > 0 && v < cus) cus = v;
+  }
   if (g.method == 1) return launch_lbfgs(g, cus);
   if (g.g_bfgs == kWideLanes) return launch_bfgs_wide(g, cus);
   if (g.g_bfgs == kTileBlockDim || g.g_bfgs == kHybridDim) {
