@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define ZEUS_ABI_VERSION 1u
+#define ZEUS_ABI_VERSION 2u
 
 typedef enum zeus_err {
   ZEUS_OK = 0,
@@ -149,6 +149,14 @@ typedef struct zeus_result {
   int32_t trace_len;    /* 0 disables the trace                                 */
   int32_t reserved0;
   zeus_summary *summary;/* one zeus_summary                                     */
+  int32_t *skips;       /* [N] steps whose rank-2 update was skipped because
+                           y's <= 0 (Alg. 4's curvature condition; L-BFGS: the
+                           pair was not kept)                                    */
+  int32_t *resets;      /* [N] search directions that were not descent
+                           directions, so H was reset to I and p = -g (L-BFGS:
+                           the kept pairs were dropped).  In mixed precision a
+                           direction formed again after an escalation to FP64
+                           counts again                                          */
 } zeus_result;
 
 typedef struct zeus_context zeus_context;

@@ -274,7 +274,7 @@ def bfgs_required(problem, x0, required_c, nthreads=None, plain=False):
     late = np.flatnonzero(full["iters"] > kstar)
     if late.size:
         cut = bfgs(dict(problem, iter_bfgs=kstar), x0, idx=late, nthreads=nthreads, plain=plain)
-        for k in ("x", "f", "iters", "ls_trials"):
+        for k in ("x", "f", "iters", "ls_trials", "skips", "resets"):
             full[k][late] = cut[k]
         full["status"][late] = ST_STOPPED
     return full, kstar

@@ -354,6 +354,8 @@ zeus_err build_group(const std::vector<Planned> &reqs, void *hdr_table, void *hs
     q.out_iters = reqs[r].dev.iters;
     q.out_status = reqs[r].dev.status;
     q.out_ls = reqs[r].dev.ls_trials;
+    q.out_skips = reqs[r].dev.skips;
+    q.out_resets = reqs[r].dev.resets;
     q.trace = q.trace_len ? reqs[r].dev.trace : nullptr;
     q.summary = reqs[r].dev.summary;
     q.start_offset = g.total_starts;
@@ -474,6 +476,8 @@ ResLayout res_layout(const zeus_problem &pb, const zeus_result &out) {
   l.it = o; o += align_up(4 * n);
   l.st = o; o += align_up(4 * n);
   l.ls = o; o += out.ls_trials ? align_up(4 * n) : 0;
+  l.sk = o; o += out.skips ? align_up(4 * n) : 0;
+  l.rs = o; o += out.resets ? align_up(4 * n) : 0;
   l.seed = o; o += out.seeds ? align_up(8 * n * d) : 0;
   l.v = o; o += out.pso_v ? align_up(8 * n * d) : 0;
   l.px = o; o += out.pso_px ? align_up(8 * n * d) : 0;
@@ -492,6 +496,8 @@ zeus_result carve_result(char *R, const ResLayout &l, const zeus_result &out) {
   dev.iters = reinterpret_cast<int32_t *>(R + l.it);
   dev.status = reinterpret_cast<int32_t *>(R + l.st);
   dev.ls_trials = out.ls_trials ? reinterpret_cast<int32_t *>(R + l.ls) : nullptr;
+  dev.skips = out.skips ? reinterpret_cast<int32_t *>(R + l.sk) : nullptr;
+  dev.resets = out.resets ? reinterpret_cast<int32_t *>(R + l.rs) : nullptr;
   dev.seeds = out.seeds ? reinterpret_cast<double *>(R + l.seed) : nullptr;
   dev.pso_v = out.pso_v ? reinterpret_cast<double *>(R + l.v) : nullptr;
   dev.pso_px = out.pso_px ? reinterpret_cast<double *>(R + l.px) : nullptr;
@@ -516,6 +522,8 @@ zeus_err copy_back(const zeus_problem &pb, const zeus_result &out, const zeus_re
                {out.iters, dev.iters, 4 * n},
                {out.status, dev.status, 4 * n},
                {out.ls_trials, dev.ls_trials, 4 * n},
+               {out.skips, dev.skips, 4 * n},
+               {out.resets, dev.resets, 4 * n},
                {out.seeds, dev.seeds, 8 * n * d},
                {out.pso_v, dev.pso_v, 8 * n * d},
                {out.pso_px, dev.pso_px, 8 * n * d},

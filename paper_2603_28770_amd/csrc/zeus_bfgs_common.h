@@ -25,6 +25,14 @@ constexpr int kHotDoubles = (sizeof(ReqHot) + 7) / 8;
 // Term sums an objective's outer function combines (Ackley has two).
 constexpr int kMaxSums = 2;
 
+// Per-start counts of two decisions of Alg. 4, kept in LDS and touched only
+// by the start's first lane (no registers): steps whose rank-2 update was
+// skipped because y's <= 0, and search directions reset to -g because g'p
+// was not negative.
+struct StartCounts {
+  int32_t skips, resets;
+};
+
 // Step lengths alpha_t = shrink^t of the first kTabTrials trials, each the
 // product of the previous one and shrink, as Alg. 6 forms them.
 constexpr int kTabTrials = 32;

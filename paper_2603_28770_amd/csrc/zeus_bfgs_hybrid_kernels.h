@@ -64,6 +64,8 @@ struct HybridShm {
   double tsum[2 * kHW][kMaxSums];     // [phase * waves + wave][sum] line-search trials' term sums
   double al[kTabTrials];
   int pass[2][kHW];              // [phase][wave] line-search outcome
+  StartCounts cnt;               // update skips and direction resets (thread 0)
+  int pad_hl[2];                 // places hl (below)
   unsigned long long got;
   int bound;                     // early-stop bound of this iteration
   ReqHot q;
@@ -71,6 +73,9 @@ struct HybridShm {
   // instructions from one base, which keeps their addresses out of registers
   double hl[16][kQ];             // the LDS part of H, element k of chain q at hl[k][q]
 };
+// The chain array 8 bytes past a 16-byte boundary: 16-byte aligned, the
+// d = 200 solve took 2% longer (230.4 against 225.7 ms).
+static_assert(__builtin_offsetof(HybridShm, hl) % 16 == 8, "the chain array's placement in LDS");
 
 // Row and column block of chain q.
 __device__ __forceinline__ int chain_row(int q) {
@@ -215,7 +220,10 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
         continue;
       }
       const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(sh.q, rq, ri, es_pass);
+      if (j == 0) {
+        load_hot<OBJ>(sh.q, rq, ri, es_pass);
+        sh.cnt = StartCounts{0, 0};
+      }
       fill_step_lengths(sh.al, rq.shrink, j, kHLanes);
       own = j < d0;
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
@@ -274,6 +282,8 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
                            sh.us[vpos<256>(c0 + lane)], sh.ss[vpos<256>(c0 + lane)], lane, 0.0, 0.0))
           H.restore_padding_at(lane, d, r0, c0);
         chains_rank2(sh, j, d, rho, beta);
+      } else if (j == 0) {
+        ++sh.cnt.skips;
       }
       ++k;
     }
@@ -306,6 +316,8 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
         rq.out_iters[idx] = k;
         rq.out_status[idx] = status;
         if (rq.out_ls) rq.out_ls[idx] = ls_trials;
+        if (rq.out_skips) rq.out_skips[idx] = sh.cnt.skips;
+        if (rq.out_resets) rq.out_resets[idx] = sh.cnt.resets;
       }
       if (tl && own)
         for (int kk = k + 1; kk < tl; ++kk) rq.trace[(idx * tl + kk) * d + j] = __builtin_nan("");
@@ -323,6 +335,7 @@ void bfgs_hybrid_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t tot
     if (coord) sh.ps[j] = pj;  // published by the barrier of the next reduction
     double ddir = block_tree_sum(gj * pj, sh, phase);
     if (!(ddir < 0.0)) {
+      if (j == 0) ++sh.cnt.resets;
       H.identity_at(lane, r0, c0);
       chains_identity(sh, j);
       pj = own ? -gj : 0.0;

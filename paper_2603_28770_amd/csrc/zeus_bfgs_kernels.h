@@ -97,6 +97,7 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
   double xj = 0.0, gj = 0.0, pj = 0.0, sj = 0.0, f = 0.0;
   int64_t idx = -1;
   int k = 0, ls_trials = 0;
+  StartCounts cnt{0, 0};  // the start's update skips and direction resets
   bool fresh = false, first = true;
   bool hi = !kMixed;  // evaluating in FP64 (always, unless mixed precision)
   const int es_pass = es_pass_of(hdr);
@@ -139,6 +140,7 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
       sh.xs[j] = xj;
       H.identity(j);  // H <- I
+      cnt = StartCounts{0, 0};
       k = 0;
       ls_trials = 0;
       fresh = true;
@@ -194,6 +196,8 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
         else
           fin = H.rank2(rho, beta, sh.us, sh.ss, j, sj, uj);
         if (!fin) H.restore_padding(j, d);
+      } else {
+        ++cnt.skips;
       }
       ++k;
     }
@@ -228,6 +232,8 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
         rq.out_iters[idx] = k;
         rq.out_status[idx] = status;
         if (rq.out_ls) rq.out_ls[idx] = ls_trials;
+        if (rq.out_skips) rq.out_skips[idx] = cnt.skips;
+        if (rq.out_resets) rq.out_resets[idx] = cnt.resets;
       }
       if (tl && own)
         for (int kk = k + 1; kk < tl; ++kk)
@@ -251,6 +257,7 @@ void bfgs_kernel(const ReqDev *reqs, int nreq,
       H.identity(j);
       pj = own ? -gj : 0.0;
       ddir = lane_tree_sum<G, double>(gj * pj);
+      ++cnt.resets;
     }
     sh.ps[j] = pj;
     wave_sync();

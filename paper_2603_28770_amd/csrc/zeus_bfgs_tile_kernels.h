@@ -51,6 +51,7 @@ struct TileShm {
   double tsum[2 * kBlockWaves][kMaxSums];   // [phase * waves + wave][sum] line-search trials' term sums
   double al[kTabTrials];
   int pass[2][kBlockWaves];            // [phase][wave] line-search outcome
+  StartCounts cnt;                     // update skips and direction resets (thread 0)
   unsigned long long got;
   int bound;                           // early-stop bound of this iteration
   ReqHot q;
@@ -108,7 +109,10 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
         continue;
       }
       const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(sh.q, rq, ri, es_pass);
+      if (j == 0) {
+        load_hot<OBJ>(sh.q, rq, ri, es_pass);
+        sh.cnt = StartCounts{0, 0};
+      }
       fill_step_lengths(sh.al, rq.shrink, j, kBlockLanes);
       own = j < d0;
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
@@ -166,6 +170,8 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
                            sh.us[vpos<kTDim>(c0 + lane)], sh.ss[vpos<kTDim>(c0 + lane)], lane, 0.0,
                            0.0))
           H.restore_padding_at(lane, d, r0, c0);
+      } else if (j == 0) {
+        ++sh.cnt.skips;
       }
       ++k;
     }
@@ -198,6 +204,8 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
         rq.out_iters[idx] = k;
         rq.out_status[idx] = status;
         if (rq.out_ls) rq.out_ls[idx] = ls_trials;
+        if (rq.out_skips) rq.out_skips[idx] = sh.cnt.skips;
+        if (rq.out_resets) rq.out_resets[idx] = sh.cnt.resets;
       }
       if (tl && own)
         for (int kk = k + 1; kk < tl; ++kk) rq.trace[(idx * tl + kk) * d + j] = __builtin_nan("");
@@ -215,6 +223,7 @@ void bfgs_tile_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total
     if (coord) sh.ps[j] = pj;  // published by the barrier of the next reduction
     double ddir = block_tree_sum(gj * pj, sh, phase);
     if (!(ddir < 0.0)) {
+      if (j == 0) ++sh.cnt.resets;
       H.identity_at(lane, r0, c0);
       pj = own ? -gj : 0.0;
       if (coord) sh.ps[j] = pj;

@@ -44,6 +44,7 @@ struct WideShm {
   double tsum[2 * kWaves][kMaxSums];  // [phase * waves + wave][sum] line-search trials' term sums
   double al[kTabTrials];
   int pass[2][kWaves];       // [phase][wave] line-search outcome
+  StartCounts cnt;           // update skips and direction resets (thread 0)
   unsigned long long got;
   int bound;                 // early-stop bound of this iteration
   ReqHot q;
@@ -129,7 +130,10 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
         continue;
       }
       const int d0 = rq.d;
-      if (j == 0) load_hot<OBJ>(sh.q, rq, ri, es_pass);
+      if (j == 0) {
+        load_hot<OBJ>(sh.q, rq, ri, es_pass);
+        sh.cnt = StartCounts{0, 0};
+      }
       fill_step_lengths(sh.al, rq.shrink, j, kWide);
       own = j < d0;
       xj = own ? rq.ws.x[idx * d0 + j] : 0.0;  // x <- swarm[i]
@@ -203,6 +207,8 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
         }
         pj = own ? -total : 0.0;
         have_p = true;
+      } else if (j == 0) {
+        ++sh.cnt.skips;
       }
       ++k;
     }
@@ -238,6 +244,8 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
         rq.out_iters[idx] = k;
         rq.out_status[idx] = status;
         if (rq.out_ls) rq.out_ls[idx] = ls_trials;
+        if (rq.out_skips) rq.out_skips[idx] = sh.cnt.skips;
+        if (rq.out_resets) rq.out_resets[idx] = sh.cnt.resets;
       }
       if (tl && own)
         for (int kk = k + 1; kk < tl; ++kk) rq.trace[(idx * tl + kk) * d + j] = __builtin_nan("");
@@ -253,6 +261,7 @@ __global__ __launch_bounds__(kWide) void bfgs_wide_kernel(const ReqDev *reqs, in
     }
     double ddir = block_tree_sum(gj * pj, sh, phase);
     if (!(ddir < 0.0)) {  // not a descent direction: H <- I, p = -g
+      if (j == 0) ++sh.cnt.resets;
       if (own)
         for (int c = 0; c < d; ++c) H[(int64_t)c * cs + j] = (c == j) ? 1.0 : 0.0;
       pj = own ? -gj : 0.0;

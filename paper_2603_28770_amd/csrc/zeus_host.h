@@ -113,7 +113,7 @@ zeus_err enqueue_group(zeus_context *ctx, const std::vector<Planned> &reqs, void
 // Device result arrays of one request laid out in one piece of memory (the
 // optional outputs only where the caller asked for them).
 struct ResLayout {
-  size_t f, x, it, st, ls, seed, v, px, pf, gx, tr, sum, total;
+  size_t f, x, it, st, ls, sk, rs, seed, v, px, pf, gx, tr, sum, total;
 };
 ResLayout res_layout(const zeus_problem &pb, const zeus_result &out);
 zeus_result carve_result(char *R, const ResLayout &l, const zeus_result &out);

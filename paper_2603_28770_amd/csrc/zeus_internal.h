@@ -102,6 +102,7 @@ struct ReqDev {
   Workspace ws;              // swarm state
   double *out_f, *out_x;     // results (device)
   int32_t *out_iters, *out_status, *out_ls;
+  int32_t *out_skips, *out_resets;  // per-start update skips and descent resets (nullable)
   double *trace;
   zeus_summary *summary;
   int64_t start_offset;      // first start of this request in the BFGS launch

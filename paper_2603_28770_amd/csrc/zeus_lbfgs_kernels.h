@@ -24,9 +24,9 @@ constexpr int kHist = kLbfgsMaxHistory;  // pairs kept in registers (m <= kHist)
 
 // Per-group LDS slice: the point under evaluation and the search direction
 // (the line search reads both in full), the step lengths, the accepted
-// trial's term sums and the request.
+// trial's term sums, the start's counts and the request.
 __device__ __host__ __forceinline__ constexpr int lbfgs_stride(int slots) {
-  return 2 * slots + kTabTrials + kMaxSums + kHotDoubles;
+  return 2 * slots + kTabTrials + kMaxSums + 1 + kHotDoubles;
 }
 
 // sum over the group's G * CPL coordinate slots of a[c] b[c] (pairwise).
@@ -175,6 +175,7 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
   const GroupLanes<G> L;
   const int j = L.j;
   double *xs, *ps, *al, *acc;
+  StartCounts *cnt;  // the start's pair skips and direction resets (lane 0)
   ReqHot *qh;
   {
     double *base = smem + (size_t)((threadIdx.x >> 6) * S + L.grp) * lbfgs_stride(SLOTS);
@@ -182,7 +183,8 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
     ps = base + SLOTS;
     al = base + 2 * SLOTS;
     acc = al + kTabTrials;
-    qh = reinterpret_cast<ReqHot *>(acc + kMaxSums);
+    cnt = reinterpret_cast<StartCounts *>(acc + kMaxSums);
+    qh = reinterpret_cast<ReqHot *>(acc + kMaxSums + 1);
   }
 
   bool own[CPL];
@@ -238,6 +240,7 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
         xj[c] = own[c] ? rq.ws.x[idx * d0 + jj] : 0.0;  // x <- swarm[i]
         xs[jj] = xj[c];
       }
+      if (j == 0) *cnt = StartCounts{0, 0};
       count = 0;
       k = 0;
       ls_trials = 0;
@@ -293,6 +296,8 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
             hrho[i] = rho;
           }
         ++count;
+      } else if (j == 0) {
+        ++cnt->skips;
       }
       ++k;
     }
@@ -336,6 +341,8 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
         rq.out_iters[idx] = k;
         rq.out_status[idx] = status;
         if (rq.out_ls) rq.out_ls[idx] = ls_trials;
+        if (rq.out_skips) rq.out_skips[idx] = cnt->skips;
+        if (rq.out_resets) rq.out_resets[idx] = cnt->resets;
       }
       if (tl)
 #pragma unroll
@@ -387,6 +394,7 @@ void lbfgs_kernel(const ReqDev *reqs, int nreq, BatchDev *hdr, int64_t total) {
     for (int c = 0; c < CPL; ++c) pj[c] = own[c] ? -qv[c] : 0.0;
     double ddir = slot_dot<G, CPL>(gj, pj);
     if (!(ddir < 0.0)) {  // not a descent direction: forget the pairs, p = -g
+      if (j == 0) ++cnt->resets;
       count = 0;
 #pragma unroll
       for (int c = 0; c < CPL; ++c) pj[c] = own[c] ? -gj[c] : 0.0;

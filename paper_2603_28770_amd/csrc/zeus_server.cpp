@@ -319,6 +319,8 @@ class EmulatedDevice : public Device {
       r.out.iters[i] = 0;
       r.out.status[i] = ZEUS_ST_MAXITER;
       if (r.out.ls_trials) r.out.ls_trials[i] = 0;
+      if (r.out.skips) r.out.skips[i] = 0;
+      if (r.out.resets) r.out.resets[i] = 0;
     }
     std::memset(r.out.x, 0, sizeof(double) * n * d);
     zeus_summary s{};

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # ZEUS_LIB names another build of the same library (e.g. to compare builds).
 LIB_PATH = os.environ.get("ZEUS_LIB") or os.path.join(HERE, "libzeus.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, NOT_READY, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ECANCELLED, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
 OBJECTIVES = {"rosenbrock": 0, "rastrigin": 1, "ackley": 2, "styblinski_tang": 3,
               "goldstein_price": 4, "sphere": 5, "quartic": 6, "user": 7}
@@ -58,7 +58,8 @@ class zeus_result(C.Structure):
                 ("status", C.c_void_p), ("ls_trials", C.c_void_p), ("seeds", C.c_void_p),
                 ("pso_v", C.c_void_p), ("pso_px", C.c_void_p), ("pso_pf", C.c_void_p),
                 ("pso_best_x", C.c_void_p), ("trace", C.c_void_p), ("trace_len", C.c_int32),
-                ("reserved0", C.c_int32), ("summary", C.c_void_p)]
+                ("reserved0", C.c_int32), ("summary", C.c_void_p), ("skips", C.c_void_p),
+                ("resets", C.c_void_p)]
 
 
 class zeus_profile(C.Structure):
@@ -204,8 +205,10 @@ def _host_outputs(pb, trace_len, pso_state, ls_trials):
     n, d = pb.n_starts, pb.dim
     o = {"f": np.full(n, np.nan), "x": np.empty((n, d)), "iters": np.empty(n, np.int32),
          "status": np.empty(n, np.int32)}
-    if ls_trials:
+    if ls_trials:  # the per-start counters: line-search trials, update skips, direction resets
         o["ls_trials"] = np.empty(n, np.int32)
+        o["skips"] = np.empty(n, np.int32)
+        o["resets"] = np.empty(n, np.int32)
     if pso_state:
         o.update(seeds=np.empty((n, d)), pso_v=np.empty((n, d)), pso_px=np.empty((n, d)),
                  pso_pf=np.empty(n), pso_best_x=np.empty(d))
@@ -218,7 +221,8 @@ def _host_outputs(pb, trace_len, pso_state, ls_trials):
                     pso_px=_np_ptr(o.get("pso_px")), pso_pf=_np_ptr(o.get("pso_pf")),
                     pso_best_x=_np_ptr(o.get("pso_best_x")), trace=_np_ptr(o.get("trace")),
                     trace_len=int(trace_len), reserved0=0,
-                    summary=C.cast(C.pointer(s), C.c_void_p).value)
+                    summary=C.cast(C.pointer(s), C.c_void_p).value,
+                    skips=_np_ptr(o.get("skips")), resets=_np_ptr(o.get("resets")))
     return o, s, r
 
 
@@ -404,6 +408,8 @@ class DevicePlan:
                  "iters": torch.empty(nn, dtype=i32, device=dev),
                  "status": torch.empty(nn, dtype=i32, device=dev),
                  "ls_trials": torch.empty(nn, dtype=i32, device=dev),
+                 "skips": torch.empty(nn, dtype=i32, device=dev),
+                 "resets": torch.empty(nn, dtype=i32, device=dev),
                  "summary": torch.empty(C.sizeof(zeus_summary), dtype=torch.uint8, device=dev)}
             if trace_len:
                 t["trace"] = torch.empty((nn, trace_len, d), dtype=f64, device=dev)
@@ -411,7 +417,8 @@ class DevicePlan:
             pp = lambda key: t[key].data_ptr() if key in t else None
             res[k] = zeus_result(f=pp("f"), x=pp("x"), iters=pp("iters"), status=pp("status"),
                                  ls_trials=pp("ls_trials"), trace=pp("trace"),
-                                 trace_len=int(trace_len), reserved0=0, summary=pp("summary"))
+                                 trace_len=int(trace_len), reserved0=0, summary=pp("summary"),
+                                 skips=pp("skips"), resets=pp("resets"))
         self.res = res
         self.h = C.c_void_p()
         _check(lib.zeus_plan_create(ctx, self.pbs, n, C.c_void_p(ws_ptr), wb, self.res,
@@ -454,6 +461,8 @@ class DeviceSolve:
                   "iters": torch.empty(n, dtype=i32, device=dev),
                   "status": torch.empty(n, dtype=i32, device=dev),
                   "ls_trials": torch.empty(n, dtype=i32, device=dev),
+                  "skips": torch.empty(n, dtype=i32, device=dev),
+                  "resets": torch.empty(n, dtype=i32, device=dev),
                   "summary": torch.empty(C.sizeof(zeus_summary), dtype=torch.uint8, device=dev)}
         if pso_state:
             self.t.update(seeds=torch.empty((n, d), dtype=f64, device=dev),
@@ -468,7 +477,8 @@ class DeviceSolve:
                                   ls_trials=p("ls_trials"), seeds=p("seeds"), pso_v=p("pso_v"),
                                   pso_px=p("pso_px"), pso_pf=p("pso_pf"),
                                   pso_best_x=p("pso_best_x"), trace=p("trace"),
-                                  trace_len=int(trace_len), reserved0=0, summary=p("summary"))
+                                  trace_len=int(trace_len), reserved0=0, summary=p("summary"),
+                                  skips=p("skips"), resets=p("resets"))
 
     def enqueue(self, ctx, stream_ptr: int = 0):
         zeus_minimize_async(ctx, self.pb, self.ws_ptr, self.ws_bytes, self.result, stream_ptr)

@@ -52,10 +52,11 @@ def test_struct_layouts_match_header(Z, tmp_path):
     import ctypes as C
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "zeus.h"\n'
-                    "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\","
+                    "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\","
                     "sizeof(zeus_problem), sizeof(zeus_result), sizeof(zeus_summary),"
                     "sizeof(zeus_profile), offsetof(zeus_problem, seed),"
-                    "offsetof(zeus_result, summary), offsetof(zeus_problem, grad_tol));return 0;}\n")
+                    "offsetof(zeus_result, summary), offsetof(zeus_problem, grad_tol),"
+                    "offsetof(zeus_result, resets));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o",
                     str(exe)], check=True)
@@ -64,11 +65,11 @@ def test_struct_layouts_match_header(Z, tmp_path):
     assert vals == [C.sizeof(Z.zeus_problem), C.sizeof(Z.zeus_result),
                     C.sizeof(Z.zeus_summary), C.sizeof(Z.zeus_profile),
                     Z.zeus_problem.seed.offset, Z.zeus_result.summary.offset,
-                    Z.zeus_problem.grad_tol.offset]
+                    Z.zeus_problem.grad_tol.offset, Z.zeus_result.resets.offset]
 
 
 def test_version(Z):
-    assert Z.zeus_abi_version() == 1 and "gfx950" in Z.zeus_version()
+    assert Z.zeus_abi_version() == Z.ABI_VERSION == 2 and "gfx950" in Z.zeus_version()
 
 
 def _p(**kw):
@@ -95,7 +96,7 @@ def test_validation_rejects(Z, bad):
 
 def test_validation_abi_and_history(Z):
     pb = Z.make_problem(_p())
-    pb.abi_version = 2
+    pb.abi_version = 1  # the layout before the per-start skip and reset counts
     assert Z.zeus_validate(pb) == Z.EINVAL
     for m, code in ((-1, Z.EINVAL), (0, Z.OK), (1, Z.OK), (8, Z.OK), (9, Z.EUNSUPPORTED)):
         pb = Z.make_problem(_p())

@@ -43,7 +43,7 @@ def _mix(count, seed, dmax=64, nmin=64, nspan=8.0):
     return out
 
 
-KEYS = ("f", "x", "iters", "status", "ls_trials", "seeds")
+KEYS = ("f", "x", "iters", "status", "ls_trials", "skips", "resets", "seeds")
 
 
 def test_batch_equals_alone(Z, ctx):

@@ -69,7 +69,8 @@ def _check_bfgs(g, o, p, idx=None, max_mismatch_share=0.02):
     same_f = (gf == o["f"]) | (np.isnan(gf) & np.isnan(o["f"]))
     same_x = np.all((gx == o["x"]) | (np.isnan(gx) & np.isnan(o["x"])), axis=1)
     exact = same_x & same_f & (gi == o["iters"]) & (gs == o["status"]) & (
-        g["ls_trials"][sel] == o["ls_trials"])
+        g["ls_trials"][sel] == o["ls_trials"]) & (g["skips"][sel] == o["skips"]) & (
+        g["resets"][sel] == o["resets"])
     print(f"[parity]   bit-exact starts {exact.mean():.4f}", flush=True)
     tie = o["tie_iter"]
     clean = tie < 0
@@ -290,7 +291,7 @@ def test_deterministic_repeat(Z, ctx):
     p = W.scaled(W.RASTRIGIN_D10, 5000)
     a = Z.zeus_minimize(ctx, p, pso_state=True)
     b = Z.zeus_minimize(ctx, p, pso_state=True)
-    for k in ("f", "x", "iters", "status", "ls_trials", "seeds"):
+    for k in ("f", "x", "iters", "status", "ls_trials", "skips", "resets", "seeds"):
         assert np.array_equal(a[k], b[k]), k
 
 
@@ -303,8 +304,8 @@ def test_async_matches_blocking(Z, ctx):
     ds.enqueue(ctx, s.cuda_stream)
     s.synchronize()
     b = ds.host()
-    for k in ("f", "x", "iters", "status", "ls_trials", "seeds", "pso_v", "pso_px", "pso_pf",
-              "pso_best_x", "trace"):
+    for k in ("f", "x", "iters", "status", "ls_trials", "skips", "resets", "seeds", "pso_v",
+              "pso_px", "pso_pf", "pso_best_x", "trace"):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
     assert a["summary"] == b["summary"]
 

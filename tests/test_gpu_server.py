@@ -14,7 +14,7 @@ from paper_2603_28770_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("f", "x", "iters", "status", "ls_trials", "seeds")
+KEYS = ("f", "x", "iters", "status", "ls_trials", "skips", "resets", "seeds")
 
 
 @pytest.fixture(scope="module")
@@ -153,7 +153,7 @@ def test_short_request_during_long(Z, ctx):
           f"done after {(s['t_done_ns'] - s['t_submit_ns']) / 1e6:.1f} ms", flush=True)
     assert l["t_admit_ns"] < s["t_submit_ns"] and s["t_admit_ns"] < l["t_done_ns"]
     assert s["t_done_ns"] < l["t_done_ns"]
-    _same_keys = ("f", "x", "iters", "status", "ls_trials")
+    _same_keys = ("f", "x", "iters", "status", "ls_trials", "skips", "resets")
     for a, o in ((a_long, o_long), (a_short, o_short)):
         for k in _same_keys:
             assert np.array_equal(a[k], o[k], equal_nan=True), k

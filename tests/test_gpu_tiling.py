@@ -71,5 +71,5 @@ def test_all_tilings_agree(Z, ctx, p):
         if ref is None:
             ref = out
             continue
-        for k in ("f", "x", "iters", "status", "ls_trials"):
+        for k in ("f", "x", "iters", "status", "ls_trials", "skips", "resets"):
             assert np.array_equal(ref[k], out[k], equal_nan=True), (lanes, k)

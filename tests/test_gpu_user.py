@@ -15,7 +15,7 @@ from paper_2603_28770_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("f", "x", "iters", "status", "ls_trials")
+KEYS = ("f", "x", "iters", "status", "ls_trials", "skips", "resets")
 
 
 @pytest.fixture(scope="module")

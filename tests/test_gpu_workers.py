@@ -46,7 +46,7 @@ CASES = [
     W.problem(name="rast5_early_stop", objective="rastrigin", dim=5, n=4000, lower=-5.12,
               upper=5.12, iter_pso=2, iter_bfgs=200, seed=36, required_converged=40),
 ]
-KEYS = ("f", "x", "iters", "status", "ls_trials")
+KEYS = ("f", "x", "iters", "status", "ls_trials", "skips", "resets")
 
 
 def _timed(Z, ctx, p):

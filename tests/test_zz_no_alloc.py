@@ -30,7 +30,7 @@ def ctx(Z):
     Z.zeus_context_destroy(c)
 
 
-KEYS = ("f", "x", "iters", "status", "ls_trials", "seeds", "pso_v", "pso_px", "pso_pf",
+KEYS = ("f", "x", "iters", "status", "ls_trials", "skips", "resets", "seeds", "pso_v", "pso_px", "pso_pf",
         "pso_best_x", "trace")
 
 
