@@ -13,9 +13,12 @@ update of one start).  Converged starts per second and the p50/p99 latency of
 one solve are reported beside it.
 
 roofline: the dominant kernel (the BFGS kernel) against the FP64 vector-ALU
-peak of MI355X; its algorithmic flops per launch come from the per-unit
-counts of ``algorithmic_flops`` and its launch duration from HIP events on the
-stream it runs on.
+peak of MI355X; its algorithmic flops per launch come from the method's
+per-unit counts (``method_flops``: H work, one primal and d dense tangent
+sweeps per iteration, one primal per line-search trial) and its launch
+duration from HIP events on the stream it runs on.  ``algorithmic_flops``
+recounts the same work from this code's own operation counts; the mixed-
+precision line splits it into FP64 and FP32 work.
 
 cpu_baseline: the CPU oracle (plain C, OpenMP over starts) timed on this
 host on the same workload.
@@ -406,7 +409,7 @@ def run_user(args, Z, ctx):
     iters = s["total_iters"]
     bfgs_ms = prof["bfgs_ms"] / max(1, prof["bfgs_launches"])
     lm = p.get("lbfgs_m", 0)
-    flops = algorithmic_flops(model, p["dim"], p["n"], iters, s["total_ls_trials"], lm)
+    flops = method_flops(model, p["dim"], iters, s["total_ls_trials"], lm)
     achieved = flops / (bfgs_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC, "value": iters / (ms / 1e3), "unit": "start-iters/s", "n_gpus": 1,
@@ -423,6 +426,10 @@ def run_user(args, Z, ctx):
         "n_converged": s["n_converged"], "best_f": s["best_f"],
         "kernel_ms": {"pso": prof["pso_ms"] / args.steps, "bfgs": bfgs_ms,
                       "reduce": prof["reduce_ms"] / args.steps},
+        # swarm particle-iterations (initialisation + iter_pso sweeps) per
+        # second of the swarm kernels
+        "pso_particle_iters_per_s": p["n"] * (p["iter_pso"] + 1)
+                                    / max(1e-9, prof["pso_ms"] / args.steps * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
                      "traffic": None,
@@ -670,6 +677,10 @@ def measure_single(args, Z, ctx, stream, p, name):
         "n_converged": s["n_converged"], "best_f": s["best_f"], "success_rate": success,
         "kernel_ms": {"pso": prof["pso_ms"] / args.steps, "bfgs": bfgs_ms,
                       "reduce": prof["reduce_ms"] / args.steps},
+        # swarm particle-iterations (initialisation + iter_pso sweeps) per
+        # second of the swarm kernels
+        "pso_particle_iters_per_s": p["n"] * (p["iter_pso"] + 1)
+                                    / max(1e-9, prof["pso_ms"] / args.steps * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
                      "traffic": profiled_traffic(name, kernel, stem), "kernel": kernel,
