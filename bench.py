@@ -238,6 +238,7 @@ def _user_source(name):
 # user-code workloads: problem, the objective its source restates (for the
 # flop counts), the source
 USER_WORKLOADS = {"user_rosenbrock_d50_n131072": (W.USER_ROSENBROCK_D50, "rosenbrock"),
+                  "user_rosenbrock_d50_n131072_mixed": (W.USER_ROSENBROCK_D50_MIXED, "rosenbrock"),
                   "user_rosenbrock_d200_n8192_lbfgs8": (W.USER_ROSENBROCK_D200_LBFGS, "rosenbrock"),
                   "user_poisson_fit_n65536": (W.USER_POISSON_FIT, "poisson_fit")}
 
@@ -437,6 +438,18 @@ def run_user(args, Z, ctx):
                      "flops_per_launch": flops},
         "note": "blocking entry point: ms_per_step includes copying the results to host memory",
     }
+    if p.get("precision") == "mixed":
+        # t_ideal = W64 / FP64 peak + W32 / FP32 peak; the peak is this mix's
+        # blend of the two, so that frac = achieved / peak = t_ideal / t
+        w64, w32 = algorithmic_flops_split(model, p["dim"], p["n"], iters, s["total_ls_trials"], lm)
+        t_ideal = w64 / (FP64_VALU_PEAK_TFLOPS * 1e12) + w32 / (FP32_VALU_PEAK_TFLOPS * 1e12)
+        blend = (w64 + w32) / t_ideal / 1e12
+        line["dtype"] = "f32+f64 (mixed)"
+        line["config"]["precision"] = "mixed"
+        line["roofline"].update(achieved=(w64 + w32) / (bfgs_ms * 1e-3) / 1e12, peak=blend,
+                                frac=t_ideal * 1e3 / bfgs_ms, w64_flops=w64, w32_flops=w32,
+                                flops_per_launch=w64 + w32)
+        line["note"] += "; the CPU baseline is the oracle, which computes in FP64"
     if model in W.BOXES:  # a restated built-in objective: the built-in beside it
         pb = dict(p, objective=model)
         bms, bprof, bout = timed(lambda: Z.zeus_minimize(ctx, pb))

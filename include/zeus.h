@@ -373,23 +373,26 @@ zeus_err zeus_server_create_emulated(size_t hbm_budget_bytes, const zeus_emulati
 /* ------------------------------------------------------------------------ */
 /* User-defined objectives.                                                 */
 /*                                                                          */
-/* The paper's f is user code: a function of the point written once over a */
+/* The paper's f is user code: a function of the point written once over a  */
 /* number type, so that it gives values and, on dual numbers, directional   */
 /* derivatives (Sec. III-C, Alg. 5).  Here it is C++ source compiled at run */
 /* time (hipRTC) together with the library's kernel templates.  The source  */
 /* defines                                                                  */
 /*     template <class T, class X> ZEUS_FN T objective(const X &x, int d);  */
 /* where x[i], i < d, is the point's coordinate i as a T; T is double or    */
-/* zeus::Dual; +, -, *, / work between Ts and doubles, and zsin, zcos,      */
-/* zexp, zlog and zsqrt are provided for both; helpers are ZEUS_FN too and  */
-/* data may sit in namespace-scope constexpr arrays.  Without a term        */
-/* structure the kernels evaluate the whole function: a value is one call,  */
-/* lane j of a start computes df/dx_j by one call on dual numbers seeded    */
-/* with e_j (Alg. 5 as written), and a line-search round tries one step     */
-/* length per lane (one block per start above dim 64: a trial per lane).   */
-/* Built for FP64: BFGS up to dim 208 (H in registers, and above dim 128   */
-/* in registers and LDS), L-BFGS (lbfgs_m > 0, a lane then owns up to four */
-/* coordinates) up to dim 256.                                              */
+/* zeus::Dual, and for the float evaluations of ZEUS_MIXED zeus::F32 or     */
+/* zeus::DualF (the coordinate rounded to float; every operation in float,  */
+/* a double operand rounded to float first); +, -, *, / work between Ts and */
+/* doubles, and zsin, zcos, zexp, zlog and zsqrt are provided for all four. */
+/* All four are compiled, so the source is generic over T; helpers are      */
+/* ZEUS_FN too and data may sit in namespace-scope constexpr arrays.        */
+/* Without a term structure the kernels evaluate the whole function: a      */
+/* value is one call, lane j of a start computes df/dx_j by one call on     */
+/* dual numbers seeded with e_j (Alg. 5 as written), and a line-search      */
+/* round tries one step length per lane (one block per start above dim 64:  */
+/* a trial per lane).  Built in FP64 and in mixed precision: BFGS up to dim */
+/* 208 (H in registers, and above dim 128 in registers and LDS), L-BFGS     */
+/* (lbfgs_m > 0, a lane then owns up to four coordinates) up to dim 256.    */
 /* ------------------------------------------------------------------------ */
 typedef struct zeus_user_objective zeus_user_objective;
 
@@ -408,9 +411,10 @@ zeus_err zeus_objective_destroy(zeus_user_objective *obj);
 
 /* Blocking solve of n >= 1 problems of the user objective `obj`, as
  * zeus_minimize_batch: every problem has objective ZEUS_USER (else
- * ZEUS_EINVAL), precision ZEUS_FP64, and dim <= 208 with lbfgs_m 0 or
- * dim <= 256 with lbfgs_m 1..8 (else ZEUS_EUNSUPPORTED); required_converged
- * works as for zeus_minimize.  The other entry points refuse ZEUS_USER. */
+ * ZEUS_EINVAL), precision ZEUS_FP64 or ZEUS_MIXED, and dim <= 208 with
+ * lbfgs_m 0 or dim <= 256 with lbfgs_m 1..8 (else ZEUS_EUNSUPPORTED);
+ * required_converged works as for zeus_minimize.  The other entry points
+ * refuse ZEUS_USER. */
 zeus_err zeus_minimize_user(zeus_context *ctx, const zeus_user_objective *obj,
                             const zeus_problem *problems, int32_t n, const zeus_result *outs);
 

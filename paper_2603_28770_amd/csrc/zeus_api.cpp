@@ -46,7 +46,6 @@ zeus_err check_problem(const zeus_problem *p, bool user) {
   if (p->abi_version != ZEUS_ABI_VERSION) return fail(ZEUS_EINVAL, "abi_version mismatch");
   if (user) {
     if (p->objective != ZEUS_USER) return fail(ZEUS_EINVAL, "objective must be ZEUS_USER");
-    if (p->precision != ZEUS_FP64) return fail(ZEUS_EUNSUPPORTED, "user objectives run in FP64");
     if (p->lbfgs_m == 0 && p->dim > zeus::kHybridDim)
       return fail(ZEUS_EUNSUPPORTED, "user objectives need dim <= 208 with BFGS (L-BFGS: <= 256)");
   } else if (p->objective == ZEUS_USER) {

@@ -215,7 +215,7 @@ __device__ __forceinline__ int armijo_search(const GroupLanes<G> &L, const doubl
     for (int base = 0; base < q.iter_ls; base += G) {
       const int t = base + L.j;
       const double alpha = step_length(al, q.shrink, t);
-      const double ft = E::trial(xs, ps, alpha, q.d);
+      const double ft = E::template trial<U>(xs, ps, alpha, q.d);
       const bool ok = t < q.iter_ls && ft <= f + (q.armijo_c * alpha) * ddir;
       const uint64_t hit = L.ballot(ok);
       if (hit != 0ull) return base + (__ffsll((unsigned long long)hit) - 1);

@@ -81,9 +81,9 @@ __device__ __forceinline__ double block_eval(int d, const double *xs, double *gj
     // function on dual numbers seeded with e_j (pass j); the primal part is
     // the same on every lane
     const int j = threadIdx.x;
-    if (!kGrad) return E::value(xs, d);
+    if (!kGrad) return E::template value<T>(xs, d);
     double g;
-    const double f = E::value_grad(xs, d, j < d ? j : -1, &g);
+    const double f = E::template value_grad<T>(xs, d, j < d ? j : -1, &g);
     *gj = j < d ? g : 0.0;
     return f;
   } else {
@@ -167,7 +167,7 @@ __device__ __forceinline__ int block_armijo(Shm &sh, double f, double ddir, int 
       bool ok = false;
       if (t < q.iter_ls) {
         const double alpha = step_length(sh.al, q.shrink, t);
-        ok = E::trial(sh.xs, sh.ps, alpha, d) <= f + (q.armijo_c * alpha) * ddir;
+        ok = E::template trial<U>(sh.xs, sh.ps, alpha, d) <= f + (q.armijo_c * alpha) * ddir;
       }
       const uint64_t hit = __ballot(ok);
       if (lane == 0) sh.pass[lsphase][w] = hit ? __ffsll((unsigned long long)hit) : 0;

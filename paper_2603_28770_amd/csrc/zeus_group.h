@@ -469,7 +469,7 @@ __device__ __forceinline__ double group_value_slots(const GroupLanes<G> &L, int 
                                                     const double *xs) {
   using E = Elem<OBJ>;
   if constexpr (whole_form<E>::value) {
-    return E::value(xs, d);
+    return E::template value<T>(xs, d);
   } else {
   const int m = E::terms(d);
   T blk[E::K][CPL];
@@ -511,7 +511,7 @@ __device__ __forceinline__ double group_value_grad(const GroupLanes<G> &L, int d
   if constexpr (whole_form<E>::value) {
     // Alg. 5 as written: one evaluation on dual numbers seeded with e_j
     double g;
-    const double f = E::value_grad(xs, d, j < d ? j : -1, &g);
+    const double f = E::template value_grad<T>(xs, d, j < d ? j : -1, &g);
     *gj = j < d ? g : 0.0;
     return f;
   } else {

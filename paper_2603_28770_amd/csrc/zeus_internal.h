@@ -129,9 +129,10 @@ struct BatchDev {
 struct UserKernels {
   void *module;
   void *pso[9];
-  void *bfgs[7];
-  void *bfgs_tile, *bfgs_hybrid;
-  void *lbfgs[9];
+  // [0]: FP64, [1]: mixed precision (FP32 evaluations)
+  void *bfgs[2][7];
+  void *bfgs_tile[2], *bfgs_hybrid[2];
+  void *lbfgs[2][9];
 };
 
 // A launch group: device table of nreq requests plus its counters.

@@ -88,7 +88,7 @@ __device__ __forceinline__ double value_grad_slots(const GroupLanes<G> &L, int d
     for (int c = 0; c < CPL; ++c) {
       const int jj = L.j + G * c;
       double g;
-      fv = E::value_grad(xs, d, jj < d ? jj : -1, &g);
+      fv = E::template value_grad<T>(xs, d, jj < d ? jj : -1, &g);
       gj[c] = jj < d ? g : 0.0;
     }
     return fv;

@@ -6,7 +6,8 @@
 // size (swarm: 2..256 coordinate slots per particle, one per lane up to 64
 // lanes and 2 or 4 per lane beyond; BFGS: 4..64 lanes per start, and the two
 // on-chip block kernels for 64 < d <= 128 and <= 208; L-BFGS: 4..256
-// coordinate slots per start; FP64).  The
+// coordinate slots per start; the BFGS and L-BFGS kernels in FP64 and in
+// mixed precision).  The
 // headers are compiled into the library as text (zeus_rtc_headers.inc,
 // generated from the sources by the build), so the same template code runs
 // for built-in and user objectives.  The build's code-generation flags are
@@ -86,22 +87,19 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
     const int s = 1 << l, lanes = s < 64 ? s : 64;
     return std::to_string(lanes) + ", " + std::to_string(s / lanes);
   };
-  std::vector<std::string> pso_expr, bfgs_expr, lbfgs_expr;
-  for (int l = 1; l <= 8; ++l) {
-    pso_expr.push_back("&zeus::pso_kernel<7, " + split(l) + ">");
-    hiprtcAddNameExpression(p, pso_expr.back().c_str());
+  std::vector<std::string> pso_expr, bfgs_expr, lbfgs_expr, block_expr;
+  for (int l = 1; l <= 8; ++l) pso_expr.push_back("&zeus::pso_kernel<7, " + split(l) + ">");
+  // per precision (FP64, then mixed with FP32 evaluations): BFGS 4..64
+  // lanes, L-BFGS 4..256 slots, the two block kernels
+  for (const char *t : {"double", "float"}) {
+    for (int l = 2; l <= 6; ++l)
+      bfgs_expr.push_back("&zeus::bfgs_kernel<7, " + std::to_string(1 << l) + ", " + t + ">");
+    for (int l = 2; l <= 8; ++l) lbfgs_expr.push_back("&zeus::lbfgs_kernel<7, " + split(l) + ", " + t + ">");
+    block_expr.push_back(std::string("&zeus::bfgs_tile_kernel<7, ") + t + ">");
+    block_expr.push_back(std::string("&zeus::bfgs_hybrid_kernel<7, ") + t + ">");
   }
-  for (int l = 2; l <= 6; ++l) {
-    bfgs_expr.push_back("&zeus::bfgs_kernel<7, " + std::to_string(1 << l) + ", double>");
-    hiprtcAddNameExpression(p, bfgs_expr.back().c_str());
-  }
-  for (int l = 2; l <= 8; ++l) {
-    lbfgs_expr.push_back("&zeus::lbfgs_kernel<7, " + split(l) + ", double>");
-    hiprtcAddNameExpression(p, lbfgs_expr.back().c_str());
-  }
-  const std::vector<std::string> block_expr = {"&zeus::bfgs_tile_kernel<7, double>",
-                                               "&zeus::bfgs_hybrid_kernel<7, double>"};
-  for (const std::string &e : block_expr) hiprtcAddNameExpression(p, e.c_str());
+  for (const auto *v : {&pso_expr, &bfgs_expr, &lbfgs_expr, &block_expr})
+    for (const std::string &e : *v) hiprtcAddNameExpression(p, e.c_str());
   const std::string arch_opt = std::string("--offload-arch=") + arch;
   const char *opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
                         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
@@ -144,20 +142,22 @@ int user_compile(const char *arch, const char *source, UserKernels *out, std::st
     if ((he = hipModuleGetFunction(&f, mod, pso_names[l - 1].c_str())) != hipSuccess) break;
     out->pso[l] = f;
   }
-  for (int l = 2; he == hipSuccess && l <= 6; ++l) {
-    hipFunction_t f;
-    if ((he = hipModuleGetFunction(&f, mod, bfgs_names[l - 2].c_str())) != hipSuccess) break;
-    out->bfgs[l] = f;
-  }
-  for (int l = 2; he == hipSuccess && l <= 8; ++l) {
-    hipFunction_t f;
-    if ((he = hipModuleGetFunction(&f, mod, lbfgs_names[l - 2].c_str())) != hipSuccess) break;
-    out->lbfgs[l] = f;
-  }
-  for (int b = 0; he == hipSuccess && b < 2; ++b) {
-    hipFunction_t f;
-    if ((he = hipModuleGetFunction(&f, mod, block_names[b].c_str())) != hipSuccess) break;
-    (b == 0 ? out->bfgs_tile : out->bfgs_hybrid) = f;
+  for (int pr = 0; pr < 2; ++pr) {
+    for (int l = 2; he == hipSuccess && l <= 6; ++l) {
+      hipFunction_t f;
+      if ((he = hipModuleGetFunction(&f, mod, bfgs_names[5 * pr + l - 2].c_str())) != hipSuccess) break;
+      out->bfgs[pr][l] = f;
+    }
+    for (int l = 2; he == hipSuccess && l <= 8; ++l) {
+      hipFunction_t f;
+      if ((he = hipModuleGetFunction(&f, mod, lbfgs_names[7 * pr + l - 2].c_str())) != hipSuccess) break;
+      out->lbfgs[pr][l] = f;
+    }
+    for (int b = 0; he == hipSuccess && b < 2; ++b) {
+      hipFunction_t f;
+      if ((he = hipModuleGetFunction(&f, mod, block_names[2 * pr + b].c_str())) != hipSuccess) break;
+      (b == 0 ? out->bfgs_tile : out->bfgs_hybrid)[pr] = f;
+    }
   }
   if (he != hipSuccess) {
     *log = std::string("hipModuleGetFunction: ") + hipGetErrorString(he);
@@ -184,9 +184,10 @@ hipError_t launch_user_pso(const Group &g, int t) {
 }
 
 hipError_t launch_user_bfgs(const Group &g, int64_t want, int cus) {
+  const int pr = g.precision == ZEUS_MIXED ? 1 : 0;
   if (g.g_bfgs == kTileBlockDim || g.g_bfgs == kHybridDim) {
     // one block per start, as many as can be resident (static LDS only)
-    void *fn = g.user ? (g.g_bfgs == kTileBlockDim ? g.user->bfgs_tile : g.user->bfgs_hybrid) : nullptr;
+    void *fn = g.user ? (g.g_bfgs == kTileBlockDim ? g.user->bfgs_tile : g.user->bfgs_hybrid)[pr] : nullptr;
     if (!fn) return hipErrorInvalidValue;
     hipFunction_t f = static_cast<hipFunction_t>(fn);
     const int threads = g.g_bfgs == kTileBlockDim ? kWideLanes : 2 * kWideLanes;
@@ -208,8 +209,8 @@ hipError_t launch_user_bfgs(const Group &g, int64_t want, int cus) {
     return hipModuleLaunchKernel(f, blocks, 1, 1, (unsigned)threads, 1, 1, 0, g.stream, args, nullptr);
   }
   const int l = log2_of(g.g_bfgs);
-  if (!g.user || l < 2 || l > 6 || !g.user->bfgs[l]) return hipErrorInvalidValue;
-  hipFunction_t f = static_cast<hipFunction_t>(g.user->bfgs[l]);
+  if (!g.user || l < 2 || l > 6 || !g.user->bfgs[pr][l]) return hipErrorInvalidValue;
+  hipFunction_t f = static_cast<hipFunction_t>(g.user->bfgs[pr][l]);
   const size_t lds = bfgs_lds_bytes(g.g_bfgs);
   int per_cu = 0;
   hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBfgsBlock, lds);
@@ -233,9 +234,10 @@ hipError_t launch_user_bfgs(const Group &g, int64_t want, int cus) {
 // blocks as can be resident, at most one group per start.
 hipError_t launch_user_lbfgs(const Group &g, int cus) {
   const int l = log2_of(g.g_bfgs);
-  if (!g.user || l < 2 || l > 8 || (1 << l) != g.g_bfgs || !g.user->lbfgs[l])
+  const int pr = g.precision == ZEUS_MIXED ? 1 : 0;
+  if (!g.user || l < 2 || l > 8 || (1 << l) != g.g_bfgs || !g.user->lbfgs[pr][l])
     return hipErrorInvalidValue;
-  hipFunction_t f = static_cast<hipFunction_t>(g.user->lbfgs[l]);
+  hipFunction_t f = static_cast<hipFunction_t>(g.user->lbfgs[pr][l]);
   const int lanes = g.g_bfgs < 64 ? g.g_bfgs : 64;
   const size_t lds = lbfgs_lds_bytes(g.g_bfgs);
   int per_cu = 0;

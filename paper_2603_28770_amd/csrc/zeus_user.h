@@ -7,11 +7,15 @@
 //     template <class T, class X>
 //     ZEUS_FN T objective(const X &x, int d);
 //
-// where x[i] (i < d) yields a T, and T is double or zeus::Dual.  It may use
-// +, -, *, / between Ts and doubles (a double takes part as the dual number
-// (k, 0)), unary minus, and zsin, zcos, zexp, zlog, zsqrt; constants may sit
-// in namespace-scope constexpr arrays.  The same source, compiled for the CPU
-// against the oracle's own number type, gives the oracle's values.
+// where x[i] (i < d) yields a T, and T is double or zeus::Dual (FP64), or, for
+// the FP32 evaluations of mixed precision, zeus::F32 or zeus::DualF.  It may
+// use +, -, *, / between Ts and doubles (a double takes part as the dual
+// number (k, 0), rounded to FP32 in the FP32 types), unary minus, and zsin,
+// zcos, zexp, zlog, zsqrt; constants may sit in namespace-scope constexpr
+// arrays.  The same source, compiled for the CPU against the oracle's own
+// number type, gives the oracle's values.  All four instantiations are
+// compiled, so the source must be generic over T (as it must already be for
+// the dual numbers).
 //
 // The kernels see a user objective in "whole" form: no term structure is
 // known, so a value is one evaluation of the function; the gradient is Alg. 5
@@ -134,20 +138,145 @@ __device__ __forceinline__ Dual zsqrt(Dual a) {
   return {s, a.t / (2.0 * s)};
 }
 
-// Views of the point handed to the user's function.
+// FP32 numbers for the mixed-precision evaluations: every operation in FP32,
+// a double operand rounded to FP32 first.  No conversion back to double, so
+// a source cannot leave FP32 by accident.
+struct F32 {
+  float v;
+  F32() = default;
+  __device__ __forceinline__ F32(double c) : v((float)c) {}
+  __device__ __forceinline__ static F32 of(float c) {
+    F32 r;
+    r.v = c;
+    return r;
+  }
+};
+__device__ __forceinline__ F32 operator+(F32 a, F32 b) { return F32::of(a.v + b.v); }
+__device__ __forceinline__ F32 operator-(F32 a, F32 b) { return F32::of(a.v - b.v); }
+__device__ __forceinline__ F32 operator*(F32 a, F32 b) { return F32::of(a.v * b.v); }
+__device__ __forceinline__ F32 operator/(F32 a, F32 b) { return F32::of(a.v / b.v); }
+__device__ __forceinline__ F32 operator-(F32 a) { return F32::of(-a.v); }
+__device__ __forceinline__ F32 operator+(F32 a, double k) { return a + F32(k); }
+__device__ __forceinline__ F32 operator+(double k, F32 a) { return F32(k) + a; }
+__device__ __forceinline__ F32 operator-(F32 a, double k) { return a - F32(k); }
+__device__ __forceinline__ F32 operator-(double k, F32 a) { return F32(k) - a; }
+__device__ __forceinline__ F32 operator*(F32 a, double k) { return a * F32(k); }
+__device__ __forceinline__ F32 operator*(double k, F32 a) { return F32(k) * a; }
+__device__ __forceinline__ F32 operator/(F32 a, double k) { return a / F32(k); }
+__device__ __forceinline__ F32 operator/(double k, F32 a) { return F32(k) / a; }
+
+// The FP32 dual number, with the product and quotient rules of Dual.
+struct DualF {
+  float v, t;
+  DualF() = default;
+  __device__ __forceinline__ DualF(double c) : v((float)c), t(0.0f) {}
+  __device__ __forceinline__ static DualF of(float v_, float t_) {
+    DualF r;
+    r.v = v_;
+    r.t = t_;
+    return r;
+  }
+};
+__device__ __forceinline__ DualF operator+(DualF a, DualF b) { return DualF::of(a.v + b.v, a.t + b.t); }
+__device__ __forceinline__ DualF operator-(DualF a, DualF b) { return DualF::of(a.v - b.v, a.t - b.t); }
+__device__ __forceinline__ DualF operator*(DualF a, DualF b) {
+  return DualF::of(a.v * b.v, a.v * b.t + a.t * b.v);
+}
+__device__ __forceinline__ DualF operator/(DualF a, DualF b) {
+  return DualF::of(a.v / b.v, (a.t * b.v - a.v * b.t) / (b.v * b.v));
+}
+__device__ __forceinline__ DualF operator-(DualF a) { return DualF::of(-a.v, -a.t); }
+__device__ __forceinline__ DualF operator+(DualF a, double k) { return a + DualF(k); }
+__device__ __forceinline__ DualF operator+(double k, DualF a) { return DualF(k) + a; }
+__device__ __forceinline__ DualF operator-(DualF a, double k) { return a - DualF(k); }
+__device__ __forceinline__ DualF operator-(double k, DualF a) { return DualF(k) - a; }
+__device__ __forceinline__ DualF operator*(DualF a, double k) { return a * DualF(k); }
+__device__ __forceinline__ DualF operator*(double k, DualF a) { return DualF(k) * a; }
+__device__ __forceinline__ DualF operator/(DualF a, double k) { return a / DualF(k); }
+__device__ __forceinline__ DualF operator/(double k, DualF a) { return DualF(k) / a; }
+
+// FP32 functions: sine, cosine and exponential as the built-in objectives
+// take them in FP32 (hardware approximations, absolute error around 1e-6 for
+// moderate arguments), the library's FP32 logarithm and square root.  FP32
+// results only steer a start until it escalates to FP64 near its minimum.
+__device__ __forceinline__ F32 zsin(F32 a) {
+  float s, c;
+  sincos32(a.v, s, c);
+  return F32::of(s);
+}
+__device__ __forceinline__ F32 zcos(F32 a) {
+  float s, c;
+  sincos32(a.v, s, c);
+  return F32::of(c);
+}
+__device__ __forceinline__ F32 zexp(F32 a) { return F32::of(dexp(a.v)); }
+__device__ __forceinline__ F32 zlog(F32 a) { return F32::of(logf(a.v)); }
+__device__ __forceinline__ F32 zsqrt(F32 a) { return F32::of(sqrtf(a.v)); }
+__device__ __forceinline__ DualF zsin(DualF a) {
+  float s, c;
+  sincos32(a.v, s, c);
+  return DualF::of(s, a.t * c);
+}
+__device__ __forceinline__ DualF zcos(DualF a) {
+  float s, c;
+  sincos32(a.v, s, c);
+  return DualF::of(c, -(a.t * s));
+}
+__device__ __forceinline__ DualF zexp(DualF a) {
+  const float e = dexp(a.v);
+  return DualF::of(e, a.t * e);
+}
+__device__ __forceinline__ DualF zlog(DualF a) { return DualF::of(logf(a.v), a.t / a.v); }
+__device__ __forceinline__ DualF zsqrt(DualF a) {
+  const float s = sqrtf(a.v);
+  return DualF::of(s, a.t / (2.0f * s));
+}
+
+// The number types of an evaluation in precision P (double or float): the
+// plain number S and the dual number D.
+template <class P> struct UserNum;
+template <> struct UserNum<double> {
+  using S = double;
+  using D = Dual;
+  __device__ __forceinline__ static double val(double a) { return a; }
+  __device__ __forceinline__ static double val(Dual a) { return a.v; }
+  __device__ __forceinline__ static double tan(Dual a) { return a.t; }
+};
+template <> struct UserNum<float> {
+  using S = F32;
+  using D = DualF;
+  __device__ __forceinline__ static double val(F32 a) { return (double)a.v; }
+  __device__ __forceinline__ static double val(DualF a) { return (double)a.v; }
+  __device__ __forceinline__ static double tan(DualF a) { return (double)a.t; }
+};
+
+// Views of the point handed to the user's function, in precision P; the FP32
+// views round each coordinate (of x, or of the trial point formed in FP64)
+// to FP32, as the built-in objectives' FP32 evaluations do.
+template <class P>
 struct PlainView {  // the point in LDS
   const double *xs;
-  __device__ __forceinline__ double operator[](int i) const { return xs[i]; }
+  __device__ __forceinline__ typename UserNum<P>::S operator[](int i) const {
+    return typename UserNum<P>::S((double)(P)xs[i]);
+  }
 };
+template <class P>
 struct SeededView {  // the point as dual numbers with tangent e_j (none if j < 0)
   const double *xs;
   int j;
-  __device__ __forceinline__ Dual operator[](int i) const { return Dual(xs[i], i == j ? 1.0 : 0.0); }
+  __device__ __forceinline__ typename UserNum<P>::D operator[](int i) const {
+    typename UserNum<P>::D r((double)(P)xs[i]);
+    r.t = i == j ? 1 : 0;
+    return r;
+  }
 };
+template <class P>
 struct TrialView {  // the trial point x + alpha p, each coordinate rounded
   const double *xs, *ps;
   double alpha;
-  __device__ __forceinline__ double operator[](int i) const { return xs[i] + alpha * ps[i]; }
+  __device__ __forceinline__ typename UserNum<P>::S operator[](int i) const {
+    return typename UserNum<P>::S((double)(P)(xs[i] + alpha * ps[i]));
+  }
 };
 
 }  // namespace zeus
@@ -155,6 +284,8 @@ struct TrialView {  // the trial point x + alpha p, each coordinate rounded
 // The user's source is at namespace scope: make the number type and the
 // functions visible there (for double arguments no lookup reaches zeus::).
 using zeus::Dual;
+using zeus::DualF;
+using zeus::F32;
 using zeus::zcos;
 using zeus::zexp;
 using zeus::zlog;

@@ -13,20 +13,28 @@ struct Elem<kUser> {
   static constexpr int K = 1, W = 1;
   static constexpr bool kWhole = true;
   __host__ __device__ __forceinline__ static int terms(int) { return 1; }
+  // In number type T (double, or float for the FP32 evaluations of mixed
+  // precision), returned as a double.
   // f at the point xs[0..d)
+  template <class T>
   __device__ __forceinline__ static double value(const double *xs, int d) {
-    return ::objective<double>(PlainView{xs}, d);
+    using N = UserNum<T>;
+    return N::val(::objective<typename N::S>(PlainView<T>{xs}, d));
   }
   // f and df/dx_j (pass j of Alg. 5; j < 0: no seed, *g = 0)
+  template <class T>
   __device__ __forceinline__ static double value_grad(const double *xs, int d, int j, double *g) {
-    const Dual r = ::objective<Dual>(SeededView{xs, j}, d);
-    *g = r.t;
-    return r.v;
+    using N = UserNum<T>;
+    const typename N::D r = ::objective<typename N::D>(SeededView<T>{xs, j}, d);
+    *g = N::tan(r);
+    return N::val(r);
   }
   // f at the trial point xs + alpha ps
+  template <class T>
   __device__ __forceinline__ static double trial(const double *xs, const double *ps, double alpha,
                                                  int d) {
-    return ::objective<double>(TrialView{xs, ps, alpha}, d);
+    using N = UserNum<T>;
+    return N::val(::objective<typename N::S>(TrialView<T>{xs, ps, alpha}, d));
   }
 };
 

@@ -76,11 +76,14 @@ ROSENBROCK_D200 = problem(name="rosenbrock_d200_n8192", objective="rosenbrock", 
                           lower=-5.0, upper=5.0, iter_pso=2, iter_bfgs=2000, seed=5)
 
 # User-code objectives (compiled at run time): Rosenbrock restated as user
-# code on the d = 50 problem above (same box, seed and budgets), on the
+# code on the d = 50 problem above (same box, seed and budgets; also in mixed
+# precision with Theta 1e-4), on the
 # d = 200 problem with L-BFGS keeping 8 pairs, and the
 # synthetic binned Poisson-likelihood fit, 4 parameters in [0,10]^4,
 # N = 65,536, seed 6; PSO 10, BFGS <= 1000.
 USER_ROSENBROCK_D50 = dict(ROSENBROCK_D50, name="user_rosenbrock_d50_n131072", objective="user")
+USER_ROSENBROCK_D50_MIXED = dict(USER_ROSENBROCK_D50, name="user_rosenbrock_d50_n131072_mixed",
+                                 precision="mixed", grad_tol=1e-4)
 USER_ROSENBROCK_D200_LBFGS = dict(ROSENBROCK_D200, name="user_rosenbrock_d200_n8192_lbfgs8",
                                   objective="user", lbfgs_m=8)
 USER_POISSON_FIT = problem(name="user_poisson_fit_n65536", objective="user", dim=4, n=65536,

@@ -5,7 +5,9 @@ bit, for one to four requests per call (a Goldstein-Price batch), every lane
 count from 4 to 64, trigonometric, logarithmic and exponential user code
 (a binned Poisson likelihood fit), BFGS on the on-chip block kernels at
 d = 100 and 150, L-BFGS from d = 5 to d = 200 (one, two and four coordinates
-per lane), and early stop; plus the refusals."""
+per lane), and early stop; mixed precision (the user code run on the FP32
+number types) against the FP64 oracle, with the bars of the built-in
+objectives' mixed mode; plus the refusals."""
 import numpy as np
 import pytest
 
@@ -136,9 +138,63 @@ def test_poisson_fit_recovers_the_spectrum(Z, ctx, compiled, oracle_mod):
     assert np.all(np.abs(m_fit - m_true) <= 4.0 * np.sqrt(m_true) + 1.0)
 
 
+MIXED_CASES = [
+    ("rosenbrock_d9", UO.ROSENBROCK, _p(9, 300, -2.0, 2.0, 2, iter_bfgs=1000), 0.8),
+    ("rastrigin_d5", UO.RASTRIGIN, _p(5, 400, -5.12, 5.12, 3, iter_pso=10, iter_bfgs=500), 0.6),
+    ("goldstein_price_d2", UO.GOLDSTEIN_PRICE, _p(2, 512, -2.0, 2.0, 1, iter_bfgs=500), 0.8),
+    ("poisson_fit_d4", "poisson", _p(4, 512, 0.0, 10.0, 6, iter_pso=10, iter_bfgs=500), 0.5),
+    ("chain_log_d20_lbfgs", UO.CHAIN_LOG, _p(20, 256, -2.0, 2.0, 11, lbfgs_m=5, iter_bfgs=500), 0.8),
+    ("chain_log_d100_lbfgs", UO.CHAIN_LOG,
+     _p(100, 96, -2.0, 2.0, 13, lbfgs_m=6, iter_pso=2, iter_bfgs=400), 0.6),
+    # one block per start: H in registers, then in registers and LDS
+    ("chain_log_d100", UO.CHAIN_LOG, _p(100, 96, -2.0, 2.0, 15, iter_pso=2, iter_bfgs=400), 0.6),
+    ("rosenbrock_d150", UO.ROSENBROCK, _p(150, 32, -2.0, 2.0, 16, iter_pso=2, iter_bfgs=2000), 0.6),
+]
+
+
+@pytest.mark.parametrize("name,src,p,min_same", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_user_mixed_against_fp64_oracle(Z, ctx, compiled, oracle_mod, name, src, p, min_same):
+    """Mixed precision with user code: the swarm is FP64 and matches bit for
+    bit; the reported f is the FP64 value of the user code at the returned x;
+    a converged start's FP64 gradient norm is below Theta (the convergence
+    test is taken in FP64 after the escalation); most starts end at the
+    oracle's minimum to within FP32 noise (relative 1e-4 in f), and the
+    success rates (f within 1e-4 of the best FP64 value) agree: within 0.01,
+    or, with few starts, within three times the spread that the starts ending
+    elsewhere than the oracle's give by themselves."""
+    src = UO.poisson_fit_source() if src == "poisson" else src
+    pm = dict(p, precision="mixed", grad_tol=1e-4)
+    print(f"\n[user mixed] {name}: d = {p['dim']}, n = {p['n']}", flush=True)
+    g = Z.zeus_minimize_user(ctx, compiled(src), [pm], pso_state=True)[0]
+    OU.use(src, oracle_mod.lib())
+    sw = oracle_mod.pso(pm)
+    assert np.array_equal(g["seeds"], sw["x"]) and np.array_equal(g["pso_pf"], sw["pf"])
+    o = oracle_mod.bfgs(pm, sw["x"])
+    for i in range(0, p["n"], max(1, p["n"] // 25)):
+        if np.isfinite(g["f"][i]):
+            assert g["f"][i] == oracle_mod.f("user", g["x"][i])
+    conv = np.flatnonzero(g["status"] == 1)
+    for i in conv[:: max(1, conv.size // 25)]:
+        _, gr = oracle_mod.grad("user", g["x"][i])
+        assert np.linalg.norm(gr) < 1.01 * pm["grad_tol"], i
+    fs = np.maximum(1.0, np.abs(o["f"]))
+    same = np.abs(g["f"] - o["f"]) / fs <= 1e-4
+    best = min(np.nanmin(o["f"]), np.nanmin(g["f"]))
+    tol = 1e-4 * max(1.0, abs(best))
+    rg, ro = np.mean(g["f"] - best < tol), np.mean(o["f"] - best < tol)
+    print(f"[user mixed]   same minimum {same.mean():.3f}; converged gpu "
+          f"{np.mean(g['status'] == 1):.3f} oracle {np.mean(o['status'] == 1):.3f}; "
+          f"success gpu {rg:.4f} oracle {ro:.4f}", flush=True)
+    assert same.mean() >= min_same
+    # a start that ends elsewhere than the oracle's succeeds or fails on its
+    # own: from those starts alone the rates differ by about sqrt(q / n), q
+    # their share
+    assert abs(rg - ro) <= max(0.01, 3.0 * np.sqrt((1.0 - same.mean()) / p["n"]))
+
+
 def test_user_refusals(Z, ctx, compiled):
     obj = compiled(UO.ROSENBROCK)
-    for bad, code in ((dict(dim=209), Z.EUNSUPPORTED), (dict(precision="mixed"), Z.EUNSUPPORTED),
+    for bad, code in ((dict(dim=209), Z.EUNSUPPORTED), (dict(dim=209, precision="mixed"), Z.EUNSUPPORTED),
                       (dict(dim=257, lbfgs_m=4), Z.EUNSUPPORTED), (dict(lbfgs_m=9), Z.EUNSUPPORTED),
                       (dict(objective="rosenbrock"), Z.EINVAL)):
         with pytest.raises(Z.ZeusError) as e:
